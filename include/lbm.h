@@ -1,0 +1,207 @@
+/*
+ * lbm.h - C ABI of the windowed regularized LBM-LES solver and its discrete
+ * adjoint for AMD Instinct MI355X (gfx950).
+ *
+ * The library computes, on one GPU, the data-parallel hot path of the
+ * representative-time-window adjoint method ("Adaptive Time Windows for
+ * Discrete Adjoint Topology Optimization of Unsteady Flows"):
+ *   - the regularized D2Q9 (or D3Q19) BGK step with Smagorinsky eddy
+ *     viscosity (Sec. 2.1.1-2.1.2, Eqs. feq, Pi, tau_eff,
+ *     modified_collision), partial bounce-back driven by a per-node design
+ *     field gamma (Sec. 2.2, Eq. external_force), streaming with halfway
+ *     bounce-back walls and Zou-He inlet / outlet rows (Sec. 2.1.3,
+ *     Eqs. wall, inlet, outlet);
+ *   - window-averaged objective and monitor samples and the
+ *     consecutive-window convergence test (Sec. 3.1, Eqs. statistical_force,
+ *     statistical_criterion, weighted_temporal_sampling, Algorithm
+ *     "LES solver");
+ *   - the discrete adjoint over the last completed window, which returns
+ *     dJ/dgamma (Sec. 3.2, Eqs. adjoint_collision, adjoint_streaming,
+ *     adjoint_inlet_bc, adjoint_outlet_bc, sensitivity).
+ *
+ * Conventions
+ *   - gamma is the per-node design field, 1 = solid, 0 = fluid (the paper's
+ *     phi is 1 - gamma). The bounce-back fraction is s = gamma
+ *     (LBM_S_LINEAR) or s = g(1 - gamma) with the paper's convex
+ *     interpolation g(phi) = 0.5 (1 - phi (1+q)/(phi+q)) (LBM_S_PAPER).
+ *   - Node order is x fastest: node = (z * ny + y) * nx + x (nz = 1 in 2D).
+ *     Population arrays are structure-of-arrays: f[alpha * N + node],
+ *     N = nx * ny * nz. D2Q9 directions are ordered as printed in the
+ *     paper (rest, E, N, W, S, NE, NW, SW, SE); D3Q19 as rest, +x, -x, +y,
+ *     -y, +z, -z, then the 12 edge directions (+-x+-y, +-x+-z, +-y+-z with
+ *     the first sign slowest).
+ *   - Time: f^k is the post-streaming, post-boundary state after k steps
+ *     (f^0 = f^eq(rho_init, u_init)). Window i (1-based) is the |W|
+ *     transitions ending at step i*|W|; its samples are taken on f^k at
+ *     the end-aligned instants k = (i-1)|W| + m*dW, m = 1..|W|/dW, each
+ *     weighted dW/|W|.
+ *   - The adjoint differentiates the window-restricted subproblem: the
+ *     state entering the window is held fixed.
+ *
+ * Memory and streams
+ *   - The caller owns all device memory: the workspace (sized by
+ *     lbm_workspace_bytes), the gamma array and the dJ/dgamma array. The
+ *     library never allocates device memory. All work is enqueued on the
+ *     caller's HIP stream (passed as void*, a hipStream_t). The library
+ *     synchronises that stream only at window ends inside lbm_forward and
+ *     before lbm_forward, lbm_adjoint, lbm_window_replay, lbm_get_state
+ *     and lbm_set_state return.
+ *   - A context is bound to one stream and is not thread-safe.
+ *
+ * Errors
+ *   - Every call returns an lbm_status; lbm_last_error() gives a
+ *     thread-local message for the last failure. Arguments are validated
+ *     before any HIP call (LBM_E_INVALID). HIP failures return LBM_E_HIP.
+ *     A sampled state with a non-finite value or |u| >= 0.4 returns
+ *     LBM_E_UNSTABLE at the end of that window; the context then needs
+ *     lbm_reset, lbm_set_gamma or lbm_set_state. LBM_E_STATE reports a call
+ *     made in the wrong state (e.g. lbm_adjoint before any window ended).
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_E_INVALID = 1,
+    LBM_E_NOMEM = 2,      /* workspace smaller than lbm_workspace_bytes */
+    LBM_E_HIP = 3,
+    LBM_E_UNSTABLE = 4,
+    LBM_E_STATE = 5
+} lbm_status;
+
+enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };                 /* lattice */
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2 };      /* population storage */
+enum { LBM_WALL = 0, LBM_VELOCITY = 1, LBM_PRESSURE = 2 }; /* x-face row kinds */
+enum { LBM_S_LINEAR = 0, LBM_S_PAPER = 1 };           /* s(gamma) */
+enum { LBM_J_PRESSURE_DROP = 0, LBM_J_DISSIPATION_PLUS_DP = 1 }; /* objective / monitor */
+
+/*
+ * Problem description. Storage precisions: LBM_F64 stores and computes in
+ * FP64; LBM_F32 stores f - w_alpha in FP32 and computes in FP32; LBM_F16S
+ * stores f - w_alpha in IEEE binary16 (round to nearest even) and computes
+ * in FP32. The adjoint populations are FP64 in LBM_F64, FP32 otherwise.
+ * Objective, monitor, window means and dJ/dgamma are always accumulated in
+ * FP64.
+ */
+typedef struct {
+    int lattice;                 /* LBM_D2Q9 or LBM_D3Q19 */
+    int nx, ny, nz;              /* nodes per axis; nz = 1 for D2Q9 */
+    double tau;                  /* molecular relaxation time, > 0.5 */
+    double c_smag;               /* Smagorinsky constant C_s >= 0 (filter width = 1) */
+    int prec;                    /* LBM_F64 / LBM_F32 / LBM_F16S */
+    int s_map;                   /* LBM_S_LINEAR or LBM_S_PAPER */
+    double s_q;                  /* interpolation parameter q of LBM_S_PAPER, > 0 */
+    int periodic_x, periodic_y, periodic_z; /* 1 = periodic axis; else walls / open rows */
+    const int* west;             /* host, ny entries, x = 0 face row kinds (NULL = all wall) */
+    const int* east;             /* host, ny entries, x = nx-1 face (LBM_WALL or LBM_PRESSURE) */
+    const double* u_in;          /* host, ny entries: inlet x-velocity u0 of each velocity row */
+    double rho_out;              /* prescribed outlet density rho_0 of pressure rows */
+    double rho_init;             /* initial density */
+    int u_init_mode;             /* 0: u(x,0) = 0; 1: u(x,0) = (u_in(y), 0[, 0]) */
+    int window_len;              /* |W| in steps */
+    int sample_every;            /* dW, must divide window_len */
+    int max_windows;             /* W_max of the window loop (stop_on_converge runs) */
+    double eps;                  /* criterion tolerance; < 0 disables the test */
+    int objective;               /* LBM_J_* : sampled objective j(t) */
+    int monitor;                 /* LBM_J_* : monitored quantity of the criterion */
+    int sec_in_x, sec_in_lo, sec_in_hi;    /* inlet pressure section: x, rows [lo, hi), all z */
+    int sec_out_x, sec_out_lo, sec_out_hi; /* outlet pressure section */
+    int ckpt_every;              /* K: checkpoint interval, must divide window_len */
+} lbm_config;
+
+/* Result of lbm_forward. w_eff is the 1-based index of the last completed
+ * window (0 if none); converged tells whether that window passed the
+ * criterion; J_eff and monitor are its objective and monitor means. */
+typedef struct {
+    long steps_done;             /* total steps since t = 0 */
+    int windows_done;
+    int converged;
+    int w_eff;
+    double J_eff;
+    double monitor;
+    double rel_change;           /* |(M_i - M_{i-1}) / M_i| of the last window (NaN for window 1) */
+    int unstable;
+} lbm_fwd_report;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Bytes of device workspace that lbm_init needs for this configuration
+ * (state ping-pong, two checkpoint rings of |W|/K slots, K recompute slots,
+ * adjoint buffers, sample partials). Validates the configuration. */
+lbm_status lbm_workspace_bytes(const lbm_config* cfg, size_t* bytes);
+
+/* Creates a context. gamma_dev: device FP64 array of N design values in
+ * [0, 1] (copied; the caller may reuse it). workspace_dev: device memory of
+ * at least lbm_workspace_bytes bytes, 256-byte aligned, owned by the caller
+ * and used exclusively by this context until lbm_destroy. stream: the
+ * hipStream_t every launch goes to. Sets the state to f^0. */
+lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* workspace_dev,
+                    size_t bytes, void* stream, lbm_ctx** out);
+
+/* Copies a new design field (device FP64, N values) and resets to t = 0. */
+lbm_status lbm_set_gamma(lbm_ctx* ctx, const double* gamma_dev);
+
+/* Resets the state to f^0 and clears the window history. */
+lbm_status lbm_reset(lbm_ctx* ctx);
+
+/* Advances at most n_steps steps (Algorithm "LES solver"). Samples the
+ * objective and monitor, checkpoints the current window every K steps, and
+ * applies the criterion at each window end. With stop_on_converge it stops
+ * at the first window that passes the criterion or when max_windows windows
+ * have completed (not an error: rep->converged = 0). rep may be NULL. */
+lbm_status lbm_forward(lbm_ctx* ctx, long n_steps, int stop_on_converge, lbm_fwd_report* rep);
+
+/* Copies the per-window objective means, monitor means and relative changes
+ * (NaN for the first window) of the windows completed so far, oldest first,
+ * into host arrays of capacity cap (any may be NULL). *n = windows done. */
+lbm_status lbm_window_history(lbm_ctx* ctx, double* J, double* M, double* rel, int cap, int* n);
+
+/* Discrete adjoint over window `window` (1-based), which must be the last
+ * completed window (or pass 0 for it). Writes dJ/dgamma (device FP64, N
+ * values) and, if J_out is not NULL, the window objective. The forward
+ * state is not changed. Recomputes each K-step segment from its HBM
+ * checkpoint. */
+lbm_status lbm_adjoint(lbm_ctx* ctx, int window, double* dJdgamma_dev, double* J_out);
+
+/* Replays the last completed window from its (fixed) start state with the
+ * design field gamma_dev (device FP64, N values) and returns its objective:
+ * the function lbm_adjoint differentiates, for finite-difference checks.
+ * The forward state, checkpoints and the context's own gamma are unchanged. */
+lbm_status lbm_window_replay(lbm_ctx* ctx, const double* gamma_dev, double* J_out);
+
+/* Exports the current state f^k (unshifted populations, FP64, Q*N values in
+ * SoA order) to host memory, and its step k. */
+lbm_status lbm_get_state(lbm_ctx* ctx, double* host_f, long* step);
+
+/* Replaces the state by f^k given in host memory (layout of lbm_get_state).
+ * step must be a multiple of window_len; the window history is cleared and
+ * windows continue from step. */
+lbm_status lbm_set_state(lbm_ctx* ctx, const double* host_f, long step);
+
+/* Writes rho, u_x, u_y[, u_z] of the current state to device FP64 memory
+ * (planes of N values). */
+lbm_status lbm_get_fields(lbm_ctx* ctx, double* rho_u_dev);
+
+/* Per-launch HIP-event timing of the hot kernels. enable = 1 starts it (and
+ * clears the counters), 0 stops it. If out is not NULL it receives 6
+ * doubles: launches and total milliseconds of the forward step kernel,
+ * of the adjoint step kernel and of the recompute step launches. */
+lbm_status lbm_timing(lbm_ctx* ctx, int enable, double* out);
+
+/* Thread-local message of the last failing call on this thread. */
+const char* lbm_last_error(void);
+
+/* Frees the host-side context. The workspace stays with the caller. */
+void lbm_destroy(lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,722 @@
+// Host driver and C ABI (include/lbm.h): workspace layout, window loop
+// with the consecutive-window test, HBM checkpoint rings, the checkpointed
+// reverse sweep, replays for finite differences, state import / export.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "launch.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status fail(lbm_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) return fail(LBM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+    int Q, D;
+    long N;
+    size_t ss, cs, as;         // bytes per stored / compute / adjoint value
+    size_t SB;                 // bytes of one population state
+    int R;                     // checkpoint slots per window
+    int nseg;                  // recompute slots
+    long nblocks;
+    int nsamp;                 // samples per window
+    size_t off_G, off_ring, off_seg, off_s, off_srep, off_gamma, off_nu, off_sens, off_part, off_samples,
+        off_acc, off_roww, off_rowe, off_uin, total;
+};
+
+lbm_status validate(const lbm_config* c) {
+    if (!c) return fail(LBM_E_INVALID, "config is NULL");
+    if (c->lattice != LBM_D2Q9 && c->lattice != LBM_D3Q19) return fail(LBM_E_INVALID, "unknown lattice");
+    if (c->nx < 3 || c->ny < 3 || c->nz < 1) return fail(LBM_E_INVALID, "grid must be at least 3 x 3");
+    if (c->lattice == LBM_D2Q9 && c->nz != 1) return fail(LBM_E_INVALID, "D2Q9 needs nz = 1");
+    if (c->lattice == LBM_D3Q19 && c->nz < 3) return fail(LBM_E_INVALID, "D3Q19 needs nz >= 3");
+    const double nodes = (double)c->nx * c->ny * c->nz;
+    if (nodes * (c->lattice == LBM_D2Q9 ? 9 : 19) > 4.0e9) return fail(LBM_E_INVALID, "grid too large");
+    if (!(c->tau > 0.5) || !std::isfinite(c->tau)) return fail(LBM_E_INVALID, "tau must be > 0.5");
+    if (!(c->c_smag >= 0.0) || !std::isfinite(c->c_smag)) return fail(LBM_E_INVALID, "c_smag must be >= 0");
+    if (c->prec < LBM_F64 || c->prec > LBM_F16S) return fail(LBM_E_INVALID, "unknown precision");
+    if (c->s_map != LBM_S_LINEAR && c->s_map != LBM_S_PAPER) return fail(LBM_E_INVALID, "unknown s_map");
+    if (c->s_map == LBM_S_PAPER && !(c->s_q > 0.0)) return fail(LBM_E_INVALID, "s_q must be > 0");
+    if (c->window_len < 1 || c->sample_every < 1 || c->window_len % c->sample_every != 0)
+        return fail(LBM_E_INVALID, "sample_every must divide window_len");
+    if (c->ckpt_every < 1 || c->window_len % c->ckpt_every != 0)
+        return fail(LBM_E_INVALID, "ckpt_every must divide window_len");
+    if (c->max_windows < 1) return fail(LBM_E_INVALID, "max_windows must be >= 1");
+    if (std::isnan(c->eps)) return fail(LBM_E_INVALID, "eps is NaN");
+    if (c->objective < 0 || c->objective > 1 || c->monitor < 0 || c->monitor > 1)
+        return fail(LBM_E_INVALID, "unknown objective or monitor");
+    if (c->sec_in_x < 0 || c->sec_in_x >= c->nx || c->sec_out_x < 0 || c->sec_out_x >= c->nx ||
+        c->sec_in_lo < 0 || c->sec_in_hi > c->ny || c->sec_in_lo >= c->sec_in_hi || c->sec_out_lo < 0 ||
+        c->sec_out_hi > c->ny || c->sec_out_lo >= c->sec_out_hi)
+        return fail(LBM_E_INVALID, "bad pressure section");
+    if (!(c->rho_out > 0.0) || !(c->rho_init > 0.0)) return fail(LBM_E_INVALID, "densities must be > 0");
+    if (c->u_init_mode != 0 && c->u_init_mode != 1) return fail(LBM_E_INVALID, "u_init_mode must be 0 or 1");
+    bool need_u = c->u_init_mode == 1;
+    if (!c->periodic_x) {
+        for (int face = 0; face < 2; ++face) {
+            const int* k = face == 0 ? c->west : c->east;
+            if (!k) continue;
+            for (int y = 0; y < c->ny; ++y) {
+                if (k[y] < LBM_WALL || k[y] > LBM_PRESSURE) return fail(LBM_E_INVALID, "bad row kind");
+                if (face == 1 && k[y] == LBM_VELOCITY)
+                    return fail(LBM_E_INVALID, "velocity rows are supported on the west face only");
+                if (!c->periodic_y && (y == 0 || y == c->ny - 1) && k[y] != LBM_WALL)
+                    return fail(LBM_E_INVALID, "rows touching a y wall must be WALL");
+                if (k[y] == LBM_VELOCITY) need_u = true;
+            }
+        }
+    }
+    if (need_u) {
+        if (!c->u_in) return fail(LBM_E_INVALID, "u_in is required");
+        for (int y = 0; y < c->ny; ++y)
+            if (!std::isfinite(c->u_in[y]) || std::fabs(c->u_in[y]) >= 0.5)
+                return fail(LBM_E_INVALID, "u_in must be finite with |u0| < 0.5");
+    }
+    return LBM_OK;
+}
+
+void layout(const lbm_config* c, Layout& L) {
+    L.Q = c->lattice == LBM_D2Q9 ? 9 : 19;
+    L.D = c->lattice == LBM_D2Q9 ? 2 : 3;
+    L.N = (long)c->nx * c->ny * c->nz;
+    L.ss = c->prec == LBM_F64 ? 8 : (c->prec == LBM_F32 ? 4 : 2);
+    L.cs = c->prec == LBM_F64 ? 8 : 4;
+    L.as = L.cs;
+    L.SB = align_up((size_t)L.Q * L.N * L.ss);
+    L.R = c->window_len / c->ckpt_every;
+    L.nseg = c->ckpt_every < 2 ? 2 : c->ckpt_every;
+    L.nblocks = blocks_for(L.N);
+    L.nsamp = c->window_len / c->sample_every;
+    size_t o = 0;
+    L.off_G = o;       o += 2 * L.SB;
+    L.off_ring = o;    o += 2 * (size_t)L.R * L.SB;
+    L.off_seg = o;     o += (size_t)L.nseg * L.SB;
+    L.off_s = o;       o += align_up(L.N * L.cs);
+    L.off_srep = o;    o += align_up(L.N * L.cs);
+    L.off_gamma = o;   o += align_up(L.N * 8);
+    L.off_nu = o;      o += 2 * align_up((size_t)L.Q * L.N * L.as);   // >= Q N 8: FP64 staging
+    L.off_sens = o;    o += align_up(L.N * 8);
+    L.off_part = o;    o += 2 * align_up((size_t)L.nsamp * L.nblocks * 3 * 8);
+    L.off_samples = o; o += align_up((size_t)L.nsamp * 3 * 8);
+    L.off_acc = o;     o += align_up(8 * 8);
+    L.off_roww = o;    o += align_up(c->ny);
+    L.off_rowe = o;    o += align_up(c->ny);
+    L.off_uin = o;     o += align_up(c->ny * 8);
+    L.total = o;
+}
+
+struct Timer {
+    bool on = false;
+    std::vector<hipEvent_t> ev;      // pool of start/stop pairs
+    std::vector<int> cls;            // class of each pending pair
+    int used = 0;
+    double n[3] = {0, 0, 0}, ms[3] = {0, 0, 0};
+};
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_config cfg;
+    std::vector<int> west, east;
+    std::vector<double> u_in;
+    std::vector<signed char> roww, rowe;
+    hipStream_t stream;
+    Layout L;
+    char* ws;
+    void* G[2];
+    std::vector<void*> ring[2];
+    std::vector<void*> seg;
+    void *s, *s_rep, *nu[2];
+    double *gamma, *sens, *partials[2], *samples, *acc;
+    Geo geo;
+    Phys ph;
+    Obj ob;
+    long step, base;
+    int cur;
+    std::vector<double> J, M, rel;
+    std::vector<int> conv;
+    bool unstable;
+    Timer tm;
+};
+
+namespace {
+
+void* at(lbm_ctx* c, size_t off) { return c->ws + off; }
+
+lbm_status t_begin(lbm_ctx* c, int cls, int& slot) {
+    slot = -1;
+    if (!c->tm.on) return LBM_OK;
+    if (c->tm.used * 2 + 2 > (int)c->tm.ev.size()) {
+        // pool full: drain it
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (int i = 0; i < c->tm.used; ++i) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, c->tm.ev[2 * i], c->tm.ev[2 * i + 1]));
+            c->tm.n[c->tm.cls[i]] += 1;
+            c->tm.ms[c->tm.cls[i]] += ms;
+        }
+        c->tm.used = 0;
+    }
+    slot = c->tm.used++;
+    c->tm.cls[slot] = cls;
+    HIPCHK(hipEventRecord(c->tm.ev[2 * slot], c->stream));
+    return LBM_OK;
+}
+
+lbm_status t_end(lbm_ctx* c, int slot) {
+    if (slot < 0) return LBM_OK;
+    HIPCHK(hipEventRecord(c->tm.ev[2 * slot + 1], c->stream));
+    return LBM_OK;
+}
+
+lbm_status t_drain(lbm_ctx* c) {
+    if (!c->tm.on || c->tm.used == 0) return LBM_OK;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < c->tm.used; ++i) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c->tm.ev[2 * i], c->tm.ev[2 * i + 1]));
+        c->tm.n[c->tm.cls[i]] += 1;
+        c->tm.ms[c->tm.cls[i]] += ms;
+    }
+    c->tm.used = 0;
+    return LBM_OK;
+}
+
+StepLaunch step_args(lbm_ctx* c) {
+    StepLaunch a;
+    a.lattice = c->cfg.lattice;
+    a.prec = c->cfg.prec;
+    a.geo = c->geo;
+    a.ph = c->ph;
+    a.ob = c->ob;
+    a.stream = c->stream;
+    a.pre = nullptr;
+    a.sample = 0;
+    a.partials = nullptr;
+    return a;
+}
+
+AuxLaunch aux_args(lbm_ctx* c, int op) {
+    AuxLaunch a;
+    a.lattice = c->cfg.lattice;
+    a.prec = c->cfg.prec;
+    a.op = op;
+    a.src = nullptr;
+    a.dst = nullptr;
+    a.s = c->s;
+    a.rho0 = c->cfg.rho_init;
+    a.umode = c->cfg.u_init_mode;
+    a.map = c->cfg.s_map;
+    a.q = c->cfg.s_q;
+    a.geo = c->geo;
+    a.ph = c->ph;
+    a.stream = c->stream;
+    return a;
+}
+
+// Ring slot holding the checkpoint written by step m (m % K == 0).
+void* ring_slot_for_step(lbm_ctx* c, long m) {
+    const long W = c->cfg.window_len;
+    const int p = (int)(((m / W) + 1) % 2);
+    const int slot = (int)((m % W) / c->cfg.ckpt_every);
+    return c->ring[p][slot];
+}
+
+lbm_status apply_design(lbm_ctx* c, const double* gamma_src, void* s_dst) {
+    AuxLaunch a = aux_args(c, AUX_DESIGN);
+    a.src = gamma_src;
+    a.dst = s_dst;
+    HIPCHK(launch_aux(a));
+    return LBM_OK;
+}
+
+lbm_status check_gamma(lbm_ctx* c, const double* gamma_dev) {
+    std::vector<double> h(c->L.N);
+    HIPCHK(hipMemcpyAsync(h.data(), gamma_dev, c->L.N * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (long i = 0; i < c->L.N; ++i)
+        if (!std::isfinite(h[i])) return fail(LBM_E_INVALID, "gamma has a non-finite entry");
+    if (c->cfg.s_map == LBM_S_PAPER)
+        for (long i = 0; i < c->L.N; ++i)
+            if (!(1.0 - h[i] + c->cfg.s_q > 0.0)) return fail(LBM_E_INVALID, "gamma out of range of the paper map");
+    return LBM_OK;
+}
+
+// Loads a pre-collision state (already in the checkpoint slot of step k)
+// and makes G^k from it.
+lbm_status start_from_slot(lbm_ctx* c, long k) {
+    AuxLaunch a = aux_args(c, AUX_COLLIDE);
+    a.src = ring_slot_for_step(c, k);
+    a.dst = c->G[0];
+    HIPCHK(launch_aux(a));
+    c->cur = 0;
+    c->step = k;
+    c->base = k;
+    c->J.clear();
+    c->M.clear();
+    c->rel.clear();
+    c->conv.clear();
+    c->unstable = false;
+    return LBM_OK;
+}
+
+lbm_status do_reset(lbm_ctx* c) {
+    AuxLaunch a = aux_args(c, AUX_INIT_EQ);
+    a.dst = ring_slot_for_step(c, 0);
+    HIPCHK(launch_aux(a));
+    return start_from_slot(c, 0);
+}
+
+lbm_status window_end(lbm_ctx* c, double* accbuf, double* part, double out[3]) {
+    const Layout& L = c->L;
+    const double wgt = (double)c->cfg.sample_every / c->cfg.window_len;
+    HIPCHK(launch_reduce(part, L.nblocks, L.nsamp, c->samples, wgt, accbuf, c->stream));
+    HIPCHK(hipMemcpyAsync(out, accbuf, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+// Consecutive-window test (Eq. statistical_criterion), strict inequality;
+// a zero current mean passes only if the previous one is zero too.
+void criterion(double prev, double cur, double eps, double& rel, int& conv) {
+    if (cur == 0.0) {
+        rel = prev == 0.0 ? 0.0 : INFINITY;
+        conv = (prev == 0.0 && eps >= 0.0) ? 1 : 0;
+        return;
+    }
+    rel = std::fabs((cur - prev) / cur);
+    conv = (eps >= 0.0 && rel < eps) ? 1 : 0;
+}
+
+long last_window(lbm_ctx* c) {
+    const long W = c->cfg.window_len;
+    const long g = c->step / W;
+    return g > c->base / W ? g : 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_workspace_bytes(const lbm_config* cfg, size_t* bytes) {
+    lbm_status st = validate(cfg);
+    if (st != LBM_OK) return st;
+    if (!bytes) return fail(LBM_E_INVALID, "bytes is NULL");
+    Layout L;
+    layout(cfg, L);
+    *bytes = L.total;
+    return LBM_OK;
+}
+
+lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* workspace_dev, size_t bytes,
+                    void* stream, lbm_ctx** out) {
+    lbm_status st = validate(cfg);
+    if (st != LBM_OK) return st;
+    if (!out || !gamma_dev || !workspace_dev) return fail(LBM_E_INVALID, "NULL argument");
+    if ((uintptr_t)workspace_dev % ALIGN != 0) return fail(LBM_E_INVALID, "workspace must be 256-byte aligned");
+    Layout L;
+    layout(cfg, L);
+    if (bytes < L.total) return fail(LBM_E_NOMEM, "workspace smaller than lbm_workspace_bytes");
+    lbm_ctx* c = new lbm_ctx();
+    c->cfg = *cfg;
+    c->L = L;
+    c->stream = (hipStream_t)stream;
+    const int ny = cfg->ny;
+    c->west.assign(ny, LBM_WALL);
+    c->east.assign(ny, LBM_WALL);
+    c->u_in.assign(ny, 0.0);
+    if (!cfg->periodic_x) {
+        if (cfg->west) c->west.assign(cfg->west, cfg->west + ny);
+        if (cfg->east) c->east.assign(cfg->east, cfg->east + ny);
+    }
+    if (cfg->u_in) c->u_in.assign(cfg->u_in, cfg->u_in + ny);
+    c->cfg.west = c->cfg.east = nullptr;
+    c->cfg.u_in = nullptr;
+    c->roww.resize(ny);
+    c->rowe.resize(ny);
+    for (int y = 0; y < ny; ++y) {
+        c->roww[y] = (signed char)c->west[y];
+        c->rowe[y] = (signed char)c->east[y];
+    }
+    c->ws = (char*)workspace_dev;
+    c->G[0] = at(c, L.off_G);
+    c->G[1] = at(c, L.off_G + L.SB);
+    for (int p = 0; p < 2; ++p)
+        for (int r = 0; r < L.R; ++r) c->ring[p].push_back(at(c, L.off_ring + ((size_t)p * L.R + r) * L.SB));
+    for (int k = 0; k < L.nseg; ++k) c->seg.push_back(at(c, L.off_seg + (size_t)k * L.SB));
+    c->s = at(c, L.off_s);
+    c->s_rep = at(c, L.off_srep);
+    c->gamma = (double*)at(c, L.off_gamma);
+    const size_t nub = align_up((size_t)L.Q * L.N * L.as);
+    c->nu[0] = at(c, L.off_nu);
+    c->nu[1] = at(c, L.off_nu + nub);
+    c->sens = (double*)at(c, L.off_sens);
+    const size_t pb = align_up((size_t)L.nsamp * L.nblocks * 3 * 8);
+    c->partials[0] = (double*)at(c, L.off_part);
+    c->partials[1] = (double*)at(c, L.off_part + pb);
+    c->samples = (double*)at(c, L.off_samples);
+    c->acc = (double*)at(c, L.off_acc);
+    signed char* dw = (signed char*)at(c, L.off_roww);
+    signed char* de = (signed char*)at(c, L.off_rowe);
+    double* du = (double*)at(c, L.off_uin);
+
+    c->geo.nx = cfg->nx;
+    c->geo.ny = cfg->ny;
+    c->geo.nz = cfg->nz;
+    c->geo.N = L.N;
+    c->geo.per_x = cfg->periodic_x ? 1 : 0;
+    c->geo.per_y = cfg->periodic_y ? 1 : 0;
+    c->geo.per_z = cfg->periodic_z ? 1 : 0;
+    c->geo.west = dw;
+    c->geo.east = de;
+    c->geo.u_in = du;
+    c->geo.drho_out = cfg->rho_out - 1.0;
+    c->ph.tau = cfg->tau;
+    c->ph.c2 = cfg->c_smag * cfg->c_smag;
+    c->ob.obj = cfg->objective;
+    c->ob.mon = cfg->monitor;
+    c->ob.in_x = cfg->sec_in_x;
+    c->ob.in_lo = cfg->sec_in_lo;
+    c->ob.in_hi = cfg->sec_in_hi;
+    c->ob.out_x = cfg->sec_out_x;
+    c->ob.out_lo = cfg->sec_out_lo;
+    c->ob.out_hi = cfg->sec_out_hi;
+    c->ob.inv_nin = 1.0 / ((double)(cfg->sec_in_hi - cfg->sec_in_lo) * cfg->nz);
+    c->ob.inv_nout = 1.0 / ((double)(cfg->sec_out_hi - cfg->sec_out_lo) * cfg->nz);
+    c->step = c->base = 0;
+    c->cur = 0;
+    c->unstable = false;
+
+    auto bail = [&](lbm_status s2) {
+        std::string keep = g_err;
+        delete c;
+        g_err = keep;
+        return s2;
+    };
+#define INITCHK(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) {                                                                \
+            fail(LBM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));               \
+            return bail(LBM_E_HIP);                                                            \
+        }                                                                                      \
+    } while (0)
+    INITCHK(hipMemcpyAsync(dw, c->roww.data(), ny, hipMemcpyHostToDevice, c->stream));
+    INITCHK(hipMemcpyAsync(de, c->rowe.data(), ny, hipMemcpyHostToDevice, c->stream));
+    INITCHK(hipMemcpyAsync(du, c->u_in.data(), ny * 8, hipMemcpyHostToDevice, c->stream));
+    INITCHK(hipMemcpyAsync(c->gamma, gamma_dev, L.N * 8, hipMemcpyDeviceToDevice, c->stream));
+    INITCHK(hipStreamSynchronize(c->stream));
+#undef INITCHK
+    if ((st = check_gamma(c, c->gamma)) != LBM_OK) return bail(st);
+    if ((st = apply_design(c, c->gamma, c->s)) != LBM_OK) return bail(st);
+    if ((st = do_reset(c)) != LBM_OK) return bail(st);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        fail(LBM_E_HIP, std::string("init: ") + hipGetErrorString(e));
+        return bail(LBM_E_HIP);
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_gamma(lbm_ctx* c, const double* gamma_dev) {
+    if (!c || !gamma_dev) return fail(LBM_E_INVALID, "NULL argument");
+    lbm_status st = check_gamma(c, gamma_dev);
+    if (st != LBM_OK) return st;
+    HIPCHK(hipMemcpyAsync(c->gamma, gamma_dev, c->L.N * 8, hipMemcpyDeviceToDevice, c->stream));
+    if ((st = apply_design(c, c->gamma, c->s)) != LBM_OK) return st;
+    if ((st = do_reset(c)) != LBM_OK) return st;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_reset(lbm_ctx* c) {
+    if (!c) return fail(LBM_E_INVALID, "NULL context");
+    lbm_status st = do_reset(c);
+    if (st != LBM_OK) return st;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_forward(lbm_ctx* c, long n_steps, int stop_on_converge, lbm_fwd_report* rep) {
+    if (!c) return fail(LBM_E_INVALID, "NULL context");
+    if (n_steps < 0) return fail(LBM_E_INVALID, "n_steps < 0");
+    if (c->unstable) return fail(LBM_E_STATE, "state is unstable; reset, set_gamma or set_state first");
+    const long W = c->cfg.window_len, dW = c->cfg.sample_every, K = c->cfg.ckpt_every;
+    const Layout& L = c->L;
+    lbm_status st;
+    StepLaunch a = step_args(c);
+    a.s = c->s;
+    for (long it = 0; it < n_steps; ++it) {
+        const long m = c->step + 1;
+        const long mw = m % W;
+        a.gin = c->G[c->cur];
+        a.gout = c->G[c->cur ^ 1];
+        a.pre = (m % K == 0) ? ring_slot_for_step(c, m) : nullptr;
+        a.sample = (m % dW == 0) ? 1 : 0;
+        if (a.sample) {
+            const long js = (mw == 0 ? W : mw) / dW - 1;
+            a.partials = c->partials[0] + js * L.nblocks * 3;
+        }
+        int slot;
+        if ((st = t_begin(c, 0, slot)) != LBM_OK) return st;
+        HIPCHK(launch_step(a));
+        if ((st = t_end(c, slot)) != LBM_OK) return st;
+        c->cur ^= 1;
+        c->step = m;
+        if (mw == 0) {
+            double r[3];
+            if ((st = window_end(c, c->acc, c->partials[0], r)) != LBM_OK) return st;
+            double rel = NAN;
+            int conv = 0;
+            if (!c->M.empty()) criterion(c->M.back(), r[1], c->cfg.eps, rel, conv);
+            c->J.push_back(r[0]);
+            c->M.push_back(r[1]);
+            c->rel.push_back(rel);
+            c->conv.push_back(conv);
+            if (r[2] > 0.0) {
+                c->unstable = true;
+                t_drain(c);
+                if (rep) {
+                    rep->unstable = 1;
+                    rep->steps_done = c->step;
+                }
+                return fail(LBM_E_UNSTABLE, "non-finite or |u| >= 0.4 in window " + std::to_string(m / W));
+            }
+            if (stop_on_converge && (conv || (int)c->M.size() >= c->cfg.max_windows)) break;
+        }
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if ((st = t_drain(c)) != LBM_OK) return st;
+    if (rep) {
+        rep->steps_done = c->step;
+        rep->windows_done = (int)c->M.size();
+        rep->w_eff = (int)last_window(c);
+        rep->converged = c->conv.empty() ? 0 : c->conv.back();
+        rep->J_eff = c->J.empty() ? NAN : c->J.back();
+        rep->monitor = c->M.empty() ? NAN : c->M.back();
+        rep->rel_change = c->rel.empty() ? NAN : c->rel.back();
+        rep->unstable = 0;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_window_history(lbm_ctx* c, double* J, double* M, double* rel, int cap, int* n) {
+    if (!c) return fail(LBM_E_INVALID, "NULL context");
+    const int k = (int)c->M.size();
+    for (int i = 0; i < k && i < cap; ++i) {
+        if (J) J[i] = c->J[i];
+        if (M) M[i] = c->M[i];
+        if (rel) rel[i] = c->rel[i];
+    }
+    if (n) *n = k;
+    return LBM_OK;
+}
+
+lbm_status lbm_adjoint(lbm_ctx* c, int window, double* dJdgamma_dev, double* J_out) {
+    if (!c || !dJdgamma_dev) return fail(LBM_E_INVALID, "NULL argument");
+    const long g = last_window(c);
+    if (g == 0) return fail(LBM_E_STATE, "no completed window");
+    if (window != 0 && window != g) return fail(LBM_E_STATE, "only the last completed window can be differentiated");
+    if (c->unstable) return fail(LBM_E_STATE, "state is unstable");
+    const long W = c->cfg.window_len, dW = c->cfg.sample_every, K = c->cfg.ckpt_every;
+    const Layout& L = c->L;
+    const long ns = (g - 1) * W + 1;
+    const double wgt = (double)dW / W;
+    const int p = (int)(g % 2);
+    lbm_status st;
+    HIPCHK(launch_fill(c->sens, L.N, 0.0, c->stream));
+
+    StepLaunch sa = step_args(c);
+    sa.s = c->s;
+    AdjLaunch aa;
+    aa.lattice = c->cfg.lattice;
+    aa.prec = c->cfg.prec;
+    aa.s = c->s;
+    aa.sens = c->sens;
+    aa.geo = c->geo;
+    aa.ph = c->ph;
+    aa.ob = c->ob;
+    aa.stream = c->stream;
+    int cur = 0;
+    for (int seg = L.R - 1; seg >= 0; --seg) {
+        const long c0 = ns - 1 + (long)seg * K;       // checkpoint step
+        const bool last = seg == L.R - 1;
+        const long nrec = last ? K - 1 : K - 2;       // step launches after the restart
+        if (last || K >= 2) {
+            AuxLaunch ca = aux_args(c, AUX_COLLIDE);
+            ca.src = c->ring[p][seg];
+            ca.dst = c->seg[0];
+            HIPCHK(launch_aux(ca));
+            for (long j = 1; j <= nrec; ++j) {
+                sa.gin = c->seg[j - 1];
+                sa.gout = c->seg[j];
+                int slot;
+                if ((st = t_begin(c, 2, slot)) != LBM_OK) return st;
+                HIPCHK(launch_step(sa));
+                if ((st = t_end(c, slot)) != LBM_OK) return st;
+            }
+        }
+        if (last) {
+            // terminal condition: nu_hat^{n_e} = BC^T (dJ/df^{n_e}), f^{n_e} = BC(S(G^{n_e - 1}))
+            aa.nu_in = nullptr;
+            aa.nu_out = c->nu[cur];
+            aa.state = c->seg[K - 1];
+            aa.direct = 0;
+            aa.seed = 1;
+            aa.src_w = wgt;
+            HIPCHK(launch_adjoint(aa));
+        }
+        for (long k = c0 + K; k >= c0 + 1; --k) {
+            aa.nu_in = c->nu[cur];
+            aa.nu_out = c->nu[cur ^ 1];
+            aa.seed = 0;
+            if (k - 1 == c0) {
+                aa.direct = 1;
+                aa.state = c->ring[p][seg];
+            } else {
+                aa.direct = 0;
+                aa.state = c->seg[k - 2 - c0];
+            }
+            aa.src_w = (k > ns && (k - ns) % dW == 0) ? wgt : 0.0;
+            int slot;
+            if ((st = t_begin(c, 1, slot)) != LBM_OK) return st;
+            HIPCHK(launch_adjoint(aa));
+            if ((st = t_end(c, slot)) != LBM_OK) return st;
+            cur ^= 1;
+        }
+    }
+    HIPCHK(launch_finalize(c->gamma, c->sens, dJdgamma_dev, L.N, c->cfg.s_map, c->cfg.s_q, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if ((st = t_drain(c)) != LBM_OK) return st;
+    if (J_out) *J_out = c->J.back();
+    return LBM_OK;
+}
+
+lbm_status lbm_window_replay(lbm_ctx* c, const double* gamma_dev, double* J_out) {
+    if (!c || !gamma_dev) return fail(LBM_E_INVALID, "NULL argument");
+    const long g = last_window(c);
+    if (g == 0) return fail(LBM_E_STATE, "no completed window");
+    lbm_status st = check_gamma(c, gamma_dev);
+    if (st != LBM_OK) return st;
+    const long W = c->cfg.window_len, dW = c->cfg.sample_every;
+    const Layout& L = c->L;
+    if ((st = apply_design(c, gamma_dev, c->s_rep)) != LBM_OK) return st;
+    AuxLaunch ca = aux_args(c, AUX_COLLIDE);
+    ca.src = c->ring[g % 2][0];
+    ca.dst = c->seg[0];
+    ca.s = c->s_rep;
+    HIPCHK(launch_aux(ca));
+    StepLaunch a = step_args(c);
+    a.s = c->s_rep;
+    int cur = 0;
+    for (long m = 1; m <= W; ++m) {
+        a.gin = c->seg[cur];
+        a.gout = c->seg[cur ^ 1];
+        a.sample = (m % dW == 0) ? 1 : 0;
+        if (a.sample) a.partials = c->partials[1] + (m / dW - 1) * L.nblocks * 3;
+        HIPCHK(launch_step(a));
+        cur ^= 1;
+    }
+    double r[3];
+    if ((st = window_end(c, c->acc + 4, c->partials[1], r)) != LBM_OK) return st;
+    if (r[2] > 0.0) return fail(LBM_E_UNSTABLE, "replay became unstable");
+    if (J_out) *J_out = r[0];
+    return LBM_OK;
+}
+
+lbm_status lbm_get_state(lbm_ctx* c, double* host_f, long* step) {
+    if (!c || !host_f) return fail(LBM_E_INVALID, "NULL argument");
+    const Layout& L = c->L;
+    AuxLaunch a = aux_args(c, c->step == c->base ? AUX_EXPORT_DIRECT : AUX_EXPORT_PULL);
+    a.src = c->step == c->base ? ring_slot_for_step(c, c->base) : c->G[c->cur ^ 1];
+    a.dst = c->nu[0];
+    HIPCHK(launch_aux(a));
+    HIPCHK(hipMemcpyAsync(host_f, c->nu[0], (size_t)L.Q * L.N * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (step) *step = c->step;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_state(lbm_ctx* c, const double* host_f, long step) {
+    if (!c || !host_f) return fail(LBM_E_INVALID, "NULL argument");
+    if (step < 0 || step % c->cfg.window_len != 0) return fail(LBM_E_INVALID, "step must be a multiple of window_len");
+    const Layout& L = c->L;
+    for (long i = 0; i < (long)L.Q * L.N; ++i)
+        if (!std::isfinite(host_f[i])) return fail(LBM_E_INVALID, "state has a non-finite entry");
+    HIPCHK(hipMemcpyAsync(c->nu[0], host_f, (size_t)L.Q * L.N * 8, hipMemcpyHostToDevice, c->stream));
+    AuxLaunch a = aux_args(c, AUX_IMPORT);
+    a.src = c->nu[0];
+    a.dst = ring_slot_for_step(c, step);
+    HIPCHK(launch_aux(a));
+    lbm_status st = start_from_slot(c, step);
+    if (st != LBM_OK) return st;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_get_fields(lbm_ctx* c, double* rho_u_dev) {
+    if (!c || !rho_u_dev) return fail(LBM_E_INVALID, "NULL argument");
+    AuxLaunch a = aux_args(c, c->step == c->base ? AUX_FIELDS_DIRECT : AUX_FIELDS_PULL);
+    a.src = c->step == c->base ? ring_slot_for_step(c, c->base) : c->G[c->cur ^ 1];
+    a.dst = rho_u_dev;
+    HIPCHK(launch_aux(a));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_timing(lbm_ctx* c, int enable, double* out) {
+    if (!c) return fail(LBM_E_INVALID, "NULL context");
+    lbm_status st = t_drain(c);
+    if (st != LBM_OK) return st;
+    if (out) {
+        for (int i = 0; i < 3; ++i) {
+            out[2 * i] = c->tm.n[i];
+            out[2 * i + 1] = c->tm.ms[i];
+        }
+    }
+    if (enable) {
+        if (c->tm.ev.empty()) {
+            c->tm.ev.resize(2048);
+            c->tm.cls.resize(1024);
+            for (auto& e : c->tm.ev) HIPCHK(hipEventCreate(&e));
+        }
+        for (int i = 0; i < 3; ++i) c->tm.n[i] = c->tm.ms[i] = 0.0;
+        c->tm.used = 0;
+    }
+    c->tm.on = enable != 0;
+    return LBM_OK;
+}
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+void lbm_destroy(lbm_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& e : c->tm.ev) (void)hipEventDestroy(e);
+    delete c;
+}
+
+}  // extern "C"

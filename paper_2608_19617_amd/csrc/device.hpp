@@ -1,0 +1,485 @@
+// Device-side building blocks of the lattice kernels: node geometry, the
+// pull with halfway bounce-back, the Zou-He rules and their transposes, the
+// regularized Smagorinsky collision with partial bounce-back, and its
+// reverse-mode derivative in moment space.
+//
+// Populations are held shifted, h_a = f_a - w_a, so that the small
+// deviations from rest keep their precision in FP32 / FP16 storage; every
+// formula below is the paper's, rewritten in h (the shift cancels exactly in
+// the moments because sum w = 1, sum w c = 0, sum w c c = c_s^2 I).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lattice.hpp"
+
+namespace lbm {
+
+enum RowKind : int { ROW_WALL = 0, ROW_VELOCITY = 1, ROW_PRESSURE = 2 };
+
+// Geometry and boundary description shared by every kernel.
+struct Geo {
+    int nx, ny, nz;
+    long N;                    // nodes
+    int per_x, per_y, per_z;   // periodic axes
+    const signed char* west;   // per row kind of the x = 0 face
+    const signed char* east;   // per row kind of the x = nx-1 face
+    const double* u_in;        // per row inlet velocity
+    double drho_out;           // rho_0 - 1 of pressure rows
+};
+
+// Collision constants.
+struct Phys {
+    double tau;
+    double c2;                 // C_s^2 (filter width 1)
+};
+
+// Objective / monitor description (per-node contributions).
+struct Obj {
+    int obj, mon;              // 0: pressure drop, 1: dissipation + pressure drop
+    int in_x, in_lo, in_hi;
+    int out_x, out_lo, out_hi;
+    double inv_nin, inv_nout;  // 1 / section node counts
+};
+
+__device__ __forceinline__ void node_coords(const Geo& g, long n, int& x, int& y, int& z) {
+    long r = n / g.nx;
+    x = (int)(n - r * g.nx);
+    if (g.nz == 1) {
+        y = (int)r;
+        z = 0;
+    } else {
+        z = (int)(r / g.ny);
+        y = (int)(r - (long)z * g.ny);
+    }
+}
+
+// Open-face code of a node: 0 = not open; 1 + face * 3 + kind otherwise
+// (face 0 = west, 1 = east). Rows touching a non-periodic y (or z) wall
+// are wall nodes, which the host validation guarantees for the row tables.
+template <class L>
+__device__ __forceinline__ int open_code(const Geo& g, int x, int y, int z) {
+    if (g.per_x) return 0;
+    if (L::D == 3 && !g.per_z && (z == 0 || z == g.nz - 1)) return 0;
+    if (x == 0) {
+        int k = g.west[y];
+        return k ? 1 + k : 0;
+    }
+    if (x == g.nx - 1) {
+        int k = g.east[y];
+        return k ? 4 + k : 0;
+    }
+    return 0;
+}
+
+template <class S>
+__device__ __forceinline__ float to_f(S v) { return (float)v; }
+
+// Pull of the post-collision populations into node (x, y, z) (Eq.
+// streaming_step): h_a(x) = G_a(x - c_a). A source outside a non-periodic
+// axis is the halfway bounce-back of Eq. wall, h_a(x) = G_opp(a)(x), unless
+// the node is open, where the value is left for the Zou-He rule.
+template <class L, class S, class T>
+__device__ __forceinline__ void pull(const S* __restrict__ G, const Geo& g, long n, int x, int y,
+                                     int z, int oc, T h[L::Q]) {
+    const long N = g.N;
+    const bool interior = x > 0 && x < g.nx - 1 && y > 0 && y < g.ny - 1 &&
+                          (L::D == 2 || (z > 0 && z < g.nz - 1));
+    if (interior) {
+#pragma unroll
+        for (int a = 0; a < L::Q; ++a) {
+            const long off = (long)L::cx[a] + (long)L::cy[a] * g.nx + (long)L::cz[a] * g.nx * g.ny;
+            h[a] = (T)G[a * N + n - off];
+        }
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) {
+        int xs = x - L::cx[a], ys = y - L::cy[a], zs = z - L::cz[a];
+        bool out = false;
+        if (xs < 0 || xs >= g.nx) {
+            if (g.per_x) xs = xs < 0 ? xs + g.nx : xs - g.nx;
+            else out = true;
+        }
+        if (ys < 0 || ys >= g.ny) {
+            if (g.per_y) ys = ys < 0 ? ys + g.ny : ys - g.ny;
+            else out = true;
+        }
+        if (L::D == 3 && (zs < 0 || zs >= g.nz)) {
+            if (g.per_z) zs = zs < 0 ? zs + g.nz : zs - g.nz;
+            else out = true;
+        }
+        if (!out) {
+            h[a] = (T)G[a * N + ((long)zs * g.ny + ys) * g.nx + xs];
+        } else if (oc == 0) {
+            h[a] = (T)G[L::opp[a] * N + n];
+        } else {
+            h[a] = (T)0;
+        }
+    }
+}
+
+// Zou-He rule on an open x-face node (Eqs. inlet, outlet; the west
+// pressure outlet is their x-mirror; in 3D the same rule with the
+// tangential momentum correction of every transverse axis). In shifted
+// form: with b = sum_{c_x=0} h + 2 sum_{leaving} h, the mass balance gives
+// rho = (1 + b)/(1 - u0) on a velocity row and rho u_x = rho_0 - (1 + b)
+// (west) or (1 + b) - rho_0 (east) on a pressure row; each entering
+// population is h_a = h_opp(a) + 6 w_a c_ax rho u_x - 1/2 sum_p c_ap N_p with
+// N_p = sum_{c_x=0} c_p h.
+template <class L, class T>
+__device__ __forceinline__ void zou_he(const Geo& g, int oc, int y, T h[L::Q]) {
+    const int face = (oc - 1) / 3;
+    const int kind = (oc - 1) % 3;
+    const int sgn = face == 0 ? 1 : -1;
+    T b = 0, Ny = 0, Nz = 0;
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) {
+        if (L::cx[a] == 0) {
+            b += h[a];
+            Ny += (T)L::cy[a] * h[a];
+            if (L::D == 3) Nz += (T)L::cz[a] * h[a];
+        } else if (L::cx[a] == -sgn) {
+            b += (T)2 * h[a];
+        }
+    }
+    T rux;
+    if (kind == ROW_VELOCITY) {
+        const T u0 = (T)g.u_in[y];
+        rux = ((T)1 + b) * u0 / ((T)1 - u0);
+    } else {
+        const T d0 = (T)g.drho_out;
+        rux = face == 0 ? d0 - b : b - d0;
+    }
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) {
+        if (L::cx[a] == sgn) {
+            T v = h[L::opp[a]] + (T)(6.0 * L::w[a] * L::cx[a]) * rux;
+            if (L::cy[a] != 0) v -= (T)(0.5 * L::cy[a]) * Ny;
+            if (L::D == 3 && L::cz[a] != 0) v -= (T)(0.5 * L::cz[a]) * Nz;
+            h[a] = v;
+        }
+    }
+}
+
+// Transpose of zou_he on the adjoint populations mu of the post-boundary
+// state: entering directions get 0, the others collect their Jacobian
+// column. With chi = u0/(1 - u0) (velocity), -1 (west pressure) or +1 (east
+// pressure): mu_b += A m_b (m = 1 tangential, 2 leaving), mu_opp(a) += mu_a,
+// and tangential directions lose sum_p c_bp B_p, where
+// A = 6 chi sum_{entering} w_a c_ax mu_a and B_p = 1/2 sum_{entering} c_ap mu_a.
+// For D2Q9 this is Eqs. adjoint_inlet_bc and adjoint_outlet_bc.
+template <class L, class T>
+__device__ __forceinline__ void zou_he_adjoint(const Geo& g, int oc, int y, T mu[L::Q]) {
+    const int face = (oc - 1) / 3;
+    const int kind = (oc - 1) % 3;
+    const int sgn = face == 0 ? 1 : -1;
+    T chi;
+    if (kind == ROW_VELOCITY) {
+        const T u0 = (T)g.u_in[y];
+        chi = u0 / ((T)1 - u0);
+    } else {
+        chi = face == 0 ? (T)-1 : (T)1;
+    }
+    T A = 0, By = 0, Bz = 0;
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) {
+        if (L::cx[a] == sgn) {
+            A += (T)(6.0 * L::w[a] * L::cx[a]) * mu[a];
+            By += (T)(0.5 * L::cy[a]) * mu[a];
+            if (L::D == 3) Bz += (T)(0.5 * L::cz[a]) * mu[a];
+        }
+    }
+    A *= chi;
+    T out[L::Q];
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) {
+        if (L::cx[a] == sgn) {
+            out[a] = 0;
+        } else if (L::cx[a] == 0) {
+            T v = mu[a] + A;
+            if (L::cy[a] != 0) v -= (T)L::cy[a] * By;
+            if (L::D == 3 && L::cz[a] != 0) v -= (T)L::cz[a] * Bz;
+            out[a] = v;
+        } else {
+            out[a] = mu[a] + (T)2 * A + mu[L::opp[a]];
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) mu[a] = out[a];
+}
+
+// Symmetric-tensor helpers over D x D, stored as the upper triangle in the
+// order xx, xy, (xz,) yy, (yz,) zz.
+template <int D>
+struct Sym;
+template <>
+struct Sym<2> {
+    static constexpr int K = 3;
+    static constexpr int idx[2][2] = {{0, 1}, {1, 2}};
+};
+template <>
+struct Sym<3> {
+    static constexpr int K = 6;
+    static constexpr int idx[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+};
+
+// Moments of a shifted node state: drho = sum h, j = sum c h, and the
+// non-equilibrium second moment Pi = sum (c c - c_s^2 I) h - j j / rho
+// (Eq. Pi, with sum c c f^eq = rho c_s^2 I + rho u u).
+template <class L, class T>
+struct Moments {
+    T drho, rho;
+    T j[L::D];
+    T Pi[Sym<L::D>::K];
+    T PP;       // Pi : Pi (full contraction)
+    T norm;     // ||Pi|| = sqrt(2 Pi:Pi)
+    T R;        // sqrt(tau^2 + 2 C^2 ||Pi|| / (rho c_s^4))
+    T te;       // tau_eff (Eq. tau_eff)
+};
+
+template <class L, class T>
+__device__ __forceinline__ void moments(const T h[L::Q], const Phys& ph, Moments<L, T>& m) {
+    constexpr int D = L::D;
+    using SY = Sym<D>;
+    T drho = 0;
+    T j[D];
+    T M[SY::K];
+#pragma unroll
+    for (int p = 0; p < D; ++p) j[p] = 0;
+#pragma unroll
+    for (int k = 0; k < SY::K; ++k) M[k] = 0;
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) {
+        drho += h[a];
+#pragma unroll
+        for (int p = 0; p < D; ++p) {
+            const int cp = comp<L>(a, p);
+            if (cp != 0) j[p] += (T)cp * h[a];
+#pragma unroll
+            for (int q = p; q < D; ++q) {
+                const int cc = cp * comp<L>(a, q);
+                if (cc != 0) M[SY::idx[p][q]] += (T)cc * h[a];
+            }
+        }
+    }
+    const T rho = (T)1 + drho;
+    const T irho = (T)1 / rho;
+    T PP = 0;
+#pragma unroll
+    for (int p = 0; p < D; ++p) {
+#pragma unroll
+        for (int q = p; q < D; ++q) {
+            const int k = SY::idx[p][q];
+            T v = M[k] - j[p] * j[q] * irho;
+            if (p == q) v -= (T)(1.0 / 3.0) * drho;
+            m.Pi[k] = v;
+            PP += (p == q ? (T)1 : (T)2) * v * v;
+        }
+    }
+    m.drho = drho;
+    m.rho = rho;
+#pragma unroll
+    for (int p = 0; p < D; ++p) m.j[p] = j[p];
+    m.PP = PP;
+    m.norm = sqrt((T)2 * PP);
+    const T tau = (T)ph.tau;
+    m.R = sqrt(tau * tau + (T)(18.0 * ph.c2) * m.norm * irho);
+    m.te = (T)0.5 * (tau + m.R);
+}
+
+// Regularized collision (Eq. modified_collision) followed by the partial
+// bounce-back (Eq. external_force), in closed form: with a = 1 - 1/tau_eff,
+//   f**_a - w_a = w_a [drho + 3(1 - 2s) c.j + 4.5 (c.j)^2/rho - 1.5 j.j/rho]
+//               + 4.5 a w_a (c c - c_s^2 I) : Pi,
+// since f*_opp - f*_a = -6 w_a c_a.j for the regularized post-collision state.
+template <class L, class T>
+__device__ __forceinline__ void collide(const Moments<L, T>& m, T s, T out[L::Q]) {
+    constexpr int D = L::D;
+    using SY = Sym<D>;
+    const T irho = (T)1 / m.rho;
+    const T a = (T)1 - (T)1 / m.te;
+    T jj = 0, tr = 0;
+#pragma unroll
+    for (int p = 0; p < D; ++p) {
+        jj += m.j[p] * m.j[p];
+        tr += m.Pi[SY::idx[p][p]];
+    }
+    const T base = m.drho - (T)1.5 * jj * irho;
+    const T odd = (T)3 * ((T)1 - (T)2 * s);
+    const T ev = (T)4.5 * a;
+#pragma unroll
+    for (int al = 0; al < L::Q; ++al) {
+        T cj = 0, cPc = 0;
+#pragma unroll
+        for (int p = 0; p < D; ++p) {
+            const int cp = comp<L>(al, p);
+            if (cp != 0) cj += (T)cp * m.j[p];
+#pragma unroll
+            for (int q = 0; q < D; ++q) {
+                const int cc = cp * comp<L>(al, q);
+                if (cc != 0) cPc += (T)cc * m.Pi[SY::idx[p][q]];
+            }
+        }
+        const T wa = (T)L::w[al];
+        out[al] = wa * (base + odd * cj + (T)4.5 * cj * cj * irho + ev * (cPc - (T)(1.0 / 3.0) * tr));
+    }
+}
+
+// Node dissipation 2 rho nu_eff S:S with S from Eq. Lallemand_equation:
+// (tau_eff - 1/2) Pi:Pi / (2 rho c_s^2 tau_eff^2).
+template <class L, class T>
+__device__ __forceinline__ T dissipation(const Moments<L, T>& m) {
+    return (T)1.5 * (m.te - (T)0.5) * m.PP / (m.rho * m.te * m.te);
+}
+
+// Gradient of a scalar with respect to the node moments (rho, j, Pi), with
+// Pi held as its own variable; chain() maps it to (rho, j, M = sum c c f),
+// after which d/df_a = g_rho + g_j . c_a + c_a . G_M . c_a.
+template <class L, class T>
+struct MomentGrad {
+    T gr;
+    T gj[L::D];
+    T GP[Sym<L::D>::K];   // symmetric tensor, full-contraction convention
+};
+
+// Adds d/d(rho, Pi) of a function of tau_eff only: dT * d tau_eff.
+template <class L, class T>
+__device__ __forceinline__ void add_tau_grad(const Moments<L, T>& m, const Phys& ph, T dT,
+                                             MomentGrad<L, T>& g) {
+    // tau_eff = (tau + R)/2, R^2 = tau^2 + 18 C^2 ||Pi|| / rho
+    // d tau_eff / d||Pi|| = 4.5 C^2 / (rho R);  d tau_eff / d rho = -4.5 C^2 ||Pi|| / (rho^2 R)
+    if (ph.c2 == 0.0) return;
+    const T k = (T)(4.5 * ph.c2) / (m.rho * m.R);
+    g.gr += -dT * k * m.norm / m.rho;
+    if (m.norm > (T)0) {
+        // d||Pi|| / dPi = 2 Pi / ||Pi||
+        const T f = dT * k * (T)2 / m.norm;
+#pragma unroll
+        for (int k2 = 0; k2 < Sym<L::D>::K; ++k2) g.GP[k2] += f * m.Pi[k2];
+    }
+}
+
+// Reverse mode of collide(): given kappa (adjoint of f**), accumulate the
+// moment gradient of sum_a kappa_a f**_a and return d/ds of it
+// (= sum_a kappa_a (f*_opp - f*_a) = -6 sum_a w_a kappa_a c_a . j).
+template <class L, class T>
+__device__ __forceinline__ T collide_adjoint(const Moments<L, T>& m, const Phys& ph, T s,
+                                             const T kappa[L::Q], MomentGrad<L, T>& g) {
+    constexpr int D = L::D;
+    using SY = Sym<D>;
+    T K0 = 0;
+    T K1[D];
+    T K2[SY::K];
+#pragma unroll
+    for (int p = 0; p < D; ++p) K1[p] = 0;
+#pragma unroll
+    for (int k = 0; k < SY::K; ++k) K2[k] = 0;
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) {
+        const T wk = (T)L::w[a] * kappa[a];
+        K0 += wk;
+#pragma unroll
+        for (int p = 0; p < D; ++p) {
+            const int cp = comp<L>(a, p);
+            if (cp != 0) K1[p] += (T)cp * wk;
+#pragma unroll
+            for (int q = p; q < D; ++q) {
+                const int cc = cp * comp<L>(a, q);
+                if (cc != 0) K2[SY::idx[p][q]] += (T)cc * wk;
+            }
+        }
+    }
+    const T irho = (T)1 / m.rho;
+    const T a = (T)1 - (T)1 / m.te;
+    // T = K2 - K0/3 I ; P = T : Pi
+    T Tt[SY::K];
+#pragma unroll
+    for (int k = 0; k < SY::K; ++k) Tt[k] = K2[k];
+#pragma unroll
+    for (int p = 0; p < D; ++p) Tt[SY::idx[p][p]] -= K0 * (T)(1.0 / 3.0);
+    T P = 0;
+#pragma unroll
+    for (int p = 0; p < D; ++p)
+#pragma unroll
+        for (int q = 0; q < D; ++q) P += Tt[SY::idx[p][q]] * m.Pi[SY::idx[p][q]];
+    // explicit dependence on (rho, j) of the equilibrium-like part
+    T jK2j = 0, jj = 0, K1j = 0;
+    T K2j[D];
+#pragma unroll
+    for (int p = 0; p < D; ++p) {
+        T v = 0;
+#pragma unroll
+        for (int q = 0; q < D; ++q) v += K2[SY::idx[p][q]] * m.j[q];
+        K2j[p] = v;
+        jK2j += m.j[p] * v;
+        jj += m.j[p] * m.j[p];
+        K1j += K1[p] * m.j[p];
+    }
+    g.gr += K0 - ((T)4.5 * jK2j - (T)1.5 * K0 * jj) * irho * irho;
+    const T odd = (T)3 * ((T)1 - (T)2 * s);
+#pragma unroll
+    for (int p = 0; p < D; ++p)
+        g.gj[p] += odd * K1[p] + ((T)9 * K2j[p] - (T)3 * K0 * m.j[p]) * irho;
+    // direct Pi dependence: 4.5 a T ; through a(tau_eff): 4.5 P / tau_eff^2
+#pragma unroll
+    for (int k = 0; k < SY::K; ++k) g.GP[k] += (T)4.5 * a * Tt[k];
+    add_tau_grad<L, T>(m, ph, (T)4.5 * P / (m.te * m.te), g);
+    return (T)-6 * K1j;
+}
+
+// Moment gradient of the node dissipation (for sampled objectives).
+template <class L, class T>
+__device__ __forceinline__ void dissipation_adjoint(const Moments<L, T>& m, const Phys& ph, T wgt,
+                                                    MomentGrad<L, T>& g) {
+    // D = 1.5 (te - 1/2) Z / (rho te^2), Z = Pi:Pi
+    const T te = m.te;
+    const T dZ = wgt * (T)1.5 * (te - (T)0.5) / (m.rho * te * te);
+#pragma unroll
+    for (int k = 0; k < Sym<L::D>::K; ++k) g.GP[k] += dZ * (T)2 * m.Pi[k];
+    const T D = (T)1.5 * (te - (T)0.5) * m.PP / (m.rho * te * te);
+    g.gr += -wgt * D / m.rho;
+    const T dte = wgt * (T)1.5 * m.PP * ((T)1 - te) / (m.rho * te * te * te);
+    add_tau_grad<L, T>(m, ph, dte, g);
+}
+
+// Maps a gradient in (rho, j, Pi) to (rho, j, M) through
+// Pi = M - c_s^2 rho I - j j / rho, then to the populations.
+template <class L, class T>
+__device__ __forceinline__ void expand(const Moments<L, T>& m, MomentGrad<L, T>& g, T mu[L::Q]) {
+    constexpr int D = L::D;
+    using SY = Sym<D>;
+    const T irho = (T)1 / m.rho;
+    T tr = 0, jGj = 0;
+    T Gj[D];
+#pragma unroll
+    for (int p = 0; p < D; ++p) {
+        tr += g.GP[SY::idx[p][p]];
+        T v = 0;
+#pragma unroll
+        for (int q = 0; q < D; ++q) v += g.GP[SY::idx[p][q]] * m.j[q];
+        Gj[p] = v;
+        jGj += m.j[p] * v;
+    }
+    const T gr = g.gr - tr * (T)(1.0 / 3.0) + jGj * irho * irho;
+    T gj[D];
+#pragma unroll
+    for (int p = 0; p < D; ++p) gj[p] = g.gj[p] - (T)2 * Gj[p] * irho;
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) {
+        T v = gr;
+#pragma unroll
+        for (int p = 0; p < D; ++p) {
+            const int cp = comp<L>(a, p);
+            if (cp != 0) v += (T)cp * gj[p];
+#pragma unroll
+            for (int q = 0; q < D; ++q) {
+                const int cc = cp * comp<L>(a, q);
+                if (cc != 0) v += (T)cc * g.GP[SY::idx[p][q]];
+            }
+        }
+        mu[a] = v;
+    }
+}
+
+}  // namespace lbm

@@ -1,0 +1,465 @@
+// gfx950 kernels of the windowed LBM-LES solver and its discrete adjoint.
+//
+// One thread per lattice node, 256 threads (four wave64) per workgroup,
+// structure-of-arrays populations so that every load and store of a wave
+// covers a contiguous run of one population plane. The step is a fused
+// pull (stream) -> boundary rules -> sample -> collide -> partial
+// bounce-back -> store: each population is read and written once per step,
+// the state in HBM is the post-collision one (G^k = C(f^k)), and the
+// post-boundary state f^k of the paper only lives in registers. The adjoint
+// step is the mirror pull of the adjoint populations fused with the
+// transposed collision in moment space. This path is bandwidth-bound
+// (about 3 flop per byte), so there is no MFMA and no LDS staging: there is
+// no data reuse across threads to stage.
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+#include "launch.hpp"
+
+namespace lbm {
+
+constexpr int BLOCK = 256;
+
+// Block-wide FP64 sum of NC channels; thread 0 writes them to out[0..NC).
+template <int NC>
+__device__ __forceinline__ void block_sum(double v[NC], double* out) {
+    __shared__ double red[NC][BLOCK / 64];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double x = v[c];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        v[c] = x;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) red[c][wid] = v[c];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double acc = 0;
+#pragma unroll
+            for (int w = 0; w < BLOCK / 64; ++w) acc += red[c][w];
+            out[c] = acc;
+        }
+    }
+}
+
+// Per-node objective and monitor contributions on the post-boundary state
+// f^k: the pressure drop c_s^2 (mean_in rho - mean_out rho) written with
+// drho (the constant cancels), plus the node dissipation when asked for.
+template <class L, class T>
+__device__ __forceinline__ void node_samples(const Obj& ob, int x, int y, const Moments<L, T>& m,
+                                             double v[3]) {
+    double dp = 0.0;
+    if (x == ob.in_x && y >= ob.in_lo && y < ob.in_hi) dp += (1.0 / 3.0) * (double)m.drho * ob.inv_nin;
+    if (x == ob.out_x && y >= ob.out_lo && y < ob.out_hi) dp -= (1.0 / 3.0) * (double)m.drho * ob.inv_nout;
+    double diss = 0.0;
+    if (ob.obj == 1 || ob.mon == 1) diss = (double)dissipation<L, T>(m);
+    v[0] = dp + (ob.obj == 1 ? diss : 0.0);
+    v[1] = dp + (ob.mon == 1 ? diss : 0.0);
+    T uu = 0;
+#pragma unroll
+    for (int p = 0; p < L::D; ++p) uu += m.j[p] * m.j[p];
+    uu /= m.rho * m.rho;
+    v[2] = (uu < (T)0.16) ? 0.0 : 1.0;   // also catches NaN
+}
+
+// Forward step k: G_out = C(BC(S(G_in))). SAMPLE: write the block partials
+// of the sampled quantities of f^k. WPRE: also store f^k (pre-collision,
+// shifted) as a checkpoint.
+template <class L, class S, class T, bool SAMPLE, bool WPRE>
+__global__ __launch_bounds__(BLOCK) void k_step(const S* __restrict__ gin, S* __restrict__ gout,
+                                                S* __restrict__ pre, const T* __restrict__ sfield,
+                                                Geo g, Phys ph, Obj ob, double* __restrict__ partials) {
+    const long n = (long)blockIdx.x * BLOCK + threadIdx.x;
+    const bool active = n < g.N;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (active) {
+        int x, y, z;
+        node_coords(g, n, x, y, z);
+        const int oc = open_code<L>(g, x, y, z);
+        T h[L::Q];
+        pull<L, S, T>(gin, g, n, x, y, z, oc, h);
+        if (oc) zou_he<L, T>(g, oc, y, h);
+        if (WPRE) {
+#pragma unroll
+            for (int a = 0; a < L::Q; ++a) pre[a * g.N + n] = (S)h[a];
+        }
+        Moments<L, T> m;
+        moments<L, T>(h, ph, m);
+        if (SAMPLE) node_samples<L, T>(ob, x, y, m, v);
+        T out[L::Q];
+        collide<L, T>(m, sfield[n], out);
+#pragma unroll
+        for (int a = 0; a < L::Q; ++a) gout[a * g.N + n] = (S)out[a];
+    }
+    if (SAMPLE) block_sum<3>(v, partials + 3 * (long)blockIdx.x);
+}
+
+// G = C(f) for a stored pre-collision state f (checkpoint restart).
+template <class L, class S, class T>
+__global__ __launch_bounds__(BLOCK) void k_collide(const S* __restrict__ pre, S* __restrict__ gout,
+                                                   const T* __restrict__ sfield, Geo g, Phys ph) {
+    const long n = (long)blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= g.N) return;
+    T h[L::Q];
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) h[a] = (T)pre[a * g.N + n];
+    Moments<L, T> m;
+    moments<L, T>(h, ph, m);
+    T out[L::Q];
+    collide<L, T>(m, sfield[n], out);
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) gout[a * g.N + n] = (S)out[a];
+}
+
+// f^0 = f^eq(rho_init, u_init) (Sec. 2.1.3), shifted.
+template <class L, class S>
+__global__ __launch_bounds__(BLOCK) void k_init_eq(S* __restrict__ pre, Geo g, double rho0, int umode) {
+    const long n = (long)blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= g.N) return;
+    int x, y, z;
+    node_coords(g, n, x, y, z);
+    const double ux = umode ? g.u_in[y] : 0.0;
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) {
+        const double cu = L::cx[a] * ux;
+        const double feq = L::w[a] * rho0 * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * ux * ux);
+        pre[a * g.N + n] = (S)(feq - L::w[a]);
+    }
+}
+
+// Pre-collision state f^k at every node, unshifted FP64, from either a
+// stored pre-collision state (DIRECT) or the previous post-collision state
+// (pull + boundary rules). FIELDS: write rho and u instead.
+template <class L, class S, bool DIRECT, bool FIELDS>
+__global__ __launch_bounds__(BLOCK) void k_export(const S* __restrict__ src, double* __restrict__ out, Geo g) {
+    const long n = (long)blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= g.N) return;
+    double h[L::Q];
+    if (DIRECT) {
+#pragma unroll
+        for (int a = 0; a < L::Q; ++a) h[a] = (double)src[a * g.N + n];
+    } else {
+        int x, y, z;
+        node_coords(g, n, x, y, z);
+        const int oc = open_code<L>(g, x, y, z);
+        pull<L, S, double>(src, g, n, x, y, z, oc, h);
+        if (oc) zou_he<L, double>(g, oc, y, h);
+    }
+    if (!FIELDS) {
+#pragma unroll
+        for (int a = 0; a < L::Q; ++a) out[a * g.N + n] = h[a] + L::w[a];
+    } else {
+        double rho = 1.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int a = 0; a < L::Q; ++a) {
+            rho += h[a];
+            j[0] += L::cx[a] * h[a];
+            j[1] += L::cy[a] * h[a];
+            j[2] += L::cz[a] * h[a];
+        }
+        out[n] = rho;
+#pragma unroll
+        for (int p = 0; p < L::D; ++p) out[(p + 1) * g.N + n] = j[p] / rho;
+    }
+}
+
+// Unshifted FP64 populations -> shifted storage.
+template <class L, class S>
+__global__ __launch_bounds__(BLOCK) void k_import(const double* __restrict__ f, S* __restrict__ pre, Geo g) {
+    const long n = (long)blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= g.N) return;
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) pre[a * g.N + n] = (S)(f[a * g.N + n] - L::w[a]);
+}
+
+// Adjoint step for transition k (f^{k-1} -> f^k), reverse order.
+//   kappa_a(y) = nu_hat_a(y + c_a)  (adjoint streaming), with the adjoint
+//   wall rule kappa_a(y) = nu_hat_opp(a)(y) where y + c_a leaves through a
+//   wall and 0 where it leaves through an open face;
+//   sens(y) += d/ds <kappa, f**>  (FP64);
+//   mu = (d f** / d f^{k-1})^T kappa  (+ sampled objective source);
+//   nu_hat^{k-1} = BC^T mu on open nodes.
+// The pre-state f^{k-1}(y) comes from a stored checkpoint (DIRECT) or by
+// pulling the post-collision state G^{k-2} (recomputed segment). SEED only
+// evaluates the source (terminal condition at the window end).
+template <class L, class S, class T, class A, bool DIRECT, bool SEED>
+__global__ __launch_bounds__(BLOCK) void k_adjoint(const A* __restrict__ nu_in, A* __restrict__ nu_out,
+                                                   const S* __restrict__ state, const T* __restrict__ sfield,
+                                                   double* __restrict__ sens, Geo g, Phys ph, Obj ob,
+                                                   double src_w) {
+    const long n = (long)blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= g.N) return;
+    int x, y, z;
+    node_coords(g, n, x, y, z);
+    const int oc = open_code<L>(g, x, y, z);
+    // pre-state of the transition
+    T h[L::Q];
+    if (DIRECT) {
+#pragma unroll
+        for (int a = 0; a < L::Q; ++a) h[a] = (T)state[a * g.N + n];
+    } else {
+        pull<L, S, T>(state, g, n, x, y, z, oc, h);
+        if (oc) zou_he<L, T>(g, oc, y, h);
+    }
+    Moments<L, T> m;
+    moments<L, T>(h, ph, m);
+    MomentGrad<L, T> gr;
+    gr.gr = 0;
+#pragma unroll
+    for (int p = 0; p < L::D; ++p) gr.gj[p] = 0;
+#pragma unroll
+    for (int k = 0; k < Sym<L::D>::K; ++k) gr.GP[k] = 0;
+    if (!SEED) {
+        T kap[L::Q];
+        const long N = g.N;
+        const bool interior = x > 0 && x < g.nx - 1 && y > 0 && y < g.ny - 1 &&
+                              (L::D == 2 || (z > 0 && z < g.nz - 1));
+        if (interior) {
+#pragma unroll
+            for (int a = 0; a < L::Q; ++a) {
+                const long off = (long)L::cx[a] + (long)L::cy[a] * g.nx + (long)L::cz[a] * g.nx * g.ny;
+                kap[a] = (T)nu_in[a * N + n + off];
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < L::Q; ++a) {
+                int xt = x + L::cx[a], yt = y + L::cy[a], zt = z + L::cz[a];
+                bool out = false;
+                if (xt < 0 || xt >= g.nx) {
+                    if (g.per_x) xt = xt < 0 ? xt + g.nx : xt - g.nx;
+                    else out = true;
+                }
+                if (yt < 0 || yt >= g.ny) {
+                    if (g.per_y) yt = yt < 0 ? yt + g.ny : yt - g.ny;
+                    else out = true;
+                }
+                if (L::D == 3 && (zt < 0 || zt >= g.nz)) {
+                    if (g.per_z) zt = zt < 0 ? zt + g.nz : zt - g.nz;
+                    else out = true;
+                }
+                if (!out) kap[a] = (T)nu_in[a * N + ((long)zt * g.ny + yt) * g.nx + xt];
+                else if (oc == 0) kap[a] = (T)nu_in[L::opp[a] * N + n];
+                else kap[a] = (T)0;
+            }
+        }
+        const T s = sfield[n];
+        const T ds = collide_adjoint<L, T>(m, ph, s, kap, gr);
+        sens[n] += (double)ds;
+    }
+    if (src_w != 0.0) {
+        T dp = 0;
+        if (x == ob.in_x && y >= ob.in_lo && y < ob.in_hi) dp += (T)((1.0 / 3.0) * ob.inv_nin * src_w);
+        if (x == ob.out_x && y >= ob.out_lo && y < ob.out_hi) dp -= (T)((1.0 / 3.0) * ob.inv_nout * src_w);
+        gr.gr += dp;
+        if (ob.obj == 1) dissipation_adjoint<L, T>(m, ph, (T)src_w, gr);
+    }
+    T mu[L::Q];
+    expand<L, T>(m, gr, mu);
+    if (oc) zou_he_adjoint<L, T>(g, oc, y, mu);
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) nu_out[a * g.N + n] = (A)mu[a];
+}
+
+// Per-sample sums of the block partials in a fixed order (deterministic).
+__global__ __launch_bounds__(BLOCK) void k_reduce_samples(const double* __restrict__ partials, long nblocks,
+                                                          double* __restrict__ samples) {
+    const double* p = partials + (long)blockIdx.x * nblocks * 3;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (long b = threadIdx.x; b < nblocks; b += BLOCK) {
+        v[0] += p[3 * b + 0];
+        v[1] += p[3 * b + 1];
+        v[2] += p[3 * b + 2];
+    }
+    block_sum<3>(v, samples + 3 * (long)blockIdx.x);
+}
+
+// Window sums: acc[c] = weight * sum over samples, in sample order.
+__global__ void k_window_sum(const double* __restrict__ samples, int nsamples, double weight,
+                             double* __restrict__ acc) {
+    const int c = threadIdx.x;
+    if (c >= 3) return;
+    double a = 0.0;
+    for (int i = 0; i < nsamples; ++i) a += samples[3 * i + c];
+    acc[c] = c < 2 ? weight * a : a;
+}
+
+// s(gamma): linear, or the paper's convex interpolation with phi = 1 - gamma.
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_design(const double* __restrict__ gamma, T* __restrict__ s, long N,
+                                                  int map, double q) {
+    const long n = (long)blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= N) return;
+    const double gm = gamma[n];
+    double v;
+    if (map == 0) {
+        v = gm;
+    } else {
+        const double phi = 1.0 - gm;
+        v = 0.5 * (1.0 - phi * (1.0 + q) / (phi + q));
+    }
+    s[n] = (T)v;
+}
+
+// dJ/dgamma = s'(gamma) * dJ/ds (Eq. sensitivity, chain rule through s).
+__global__ __launch_bounds__(BLOCK) void k_finalize(const double* __restrict__ gamma,
+                                                    const double* __restrict__ sens, double* __restrict__ out,
+                                                    long N, int map, double q) {
+    const long n = (long)blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= N) return;
+    double d = 1.0;
+    if (map != 0) {
+        const double phi = 1.0 - gamma[n];
+        d = 0.5 * q * (1.0 + q) / ((phi + q) * (phi + q));
+    }
+    out[n] = d * sens[n];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_fill(double* __restrict__ p, long n, double v) {
+    const long i = (long)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_copy_bytes(const unsigned int* __restrict__ a,
+                                                      unsigned int* __restrict__ b, long nwords) {
+    const long i = (long)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < nwords) b[i] = a[i];
+}
+
+// ------------------------------------------------------------ launchers
+
+static inline dim3 grid_for(long n) { return dim3((unsigned)((n + BLOCK - 1) / BLOCK)); }
+
+template <class L, class S, class T>
+static hipError_t step_t(const StepLaunch& a) {
+    const Geo& g = a.geo;
+    const S* gin = (const S*)a.gin;
+    S* gout = (S*)a.gout;
+    S* pre = (S*)a.pre;
+    const T* sf = (const T*)a.s;
+    dim3 gr = grid_for(g.N);
+    if (a.sample) {
+        if (pre) hipLaunchKernelGGL((k_step<L, S, T, true, true>), gr, dim3(BLOCK), 0, a.stream, gin, gout, pre, sf, g, a.ph, a.ob, a.partials);
+        else hipLaunchKernelGGL((k_step<L, S, T, true, false>), gr, dim3(BLOCK), 0, a.stream, gin, gout, pre, sf, g, a.ph, a.ob, a.partials);
+    } else {
+        if (pre) hipLaunchKernelGGL((k_step<L, S, T, false, true>), gr, dim3(BLOCK), 0, a.stream, gin, gout, pre, sf, g, a.ph, a.ob, a.partials);
+        else hipLaunchKernelGGL((k_step<L, S, T, false, false>), gr, dim3(BLOCK), 0, a.stream, gin, gout, pre, sf, g, a.ph, a.ob, a.partials);
+    }
+    return hipGetLastError();
+}
+
+template <class L, class S, class T, class A>
+static hipError_t adj_t(const AdjLaunch& a) {
+    const Geo& g = a.geo;
+    dim3 gr = grid_for(g.N);
+    const A* nin = (const A*)a.nu_in;
+    A* nout = (A*)a.nu_out;
+    const S* st = (const S*)a.state;
+    const T* sf = (const T*)a.s;
+    if (a.seed) {
+        hipLaunchKernelGGL((k_adjoint<L, S, T, A, false, true>), gr, dim3(BLOCK), 0, a.stream, nin, nout, st, sf, a.sens, g, a.ph, a.ob, a.src_w);
+    } else if (a.direct) {
+        hipLaunchKernelGGL((k_adjoint<L, S, T, A, true, false>), gr, dim3(BLOCK), 0, a.stream, nin, nout, st, sf, a.sens, g, a.ph, a.ob, a.src_w);
+    } else {
+        hipLaunchKernelGGL((k_adjoint<L, S, T, A, false, false>), gr, dim3(BLOCK), 0, a.stream, nin, nout, st, sf, a.sens, g, a.ph, a.ob, a.src_w);
+    }
+    return hipGetLastError();
+}
+
+template <class L, class S, class T>
+static hipError_t aux_t(const AuxLaunch& a) {
+    const Geo& g = a.geo;
+    dim3 gr = grid_for(g.N);
+    switch (a.op) {
+        case AUX_COLLIDE:
+            hipLaunchKernelGGL((k_collide<L, S, T>), gr, dim3(BLOCK), 0, a.stream, (const S*)a.src, (S*)a.dst, (const T*)a.s, g, a.ph);
+            break;
+        case AUX_INIT_EQ:
+            hipLaunchKernelGGL((k_init_eq<L, S>), gr, dim3(BLOCK), 0, a.stream, (S*)a.dst, g, a.rho0, a.umode);
+            break;
+        case AUX_EXPORT_DIRECT:
+            hipLaunchKernelGGL((k_export<L, S, true, false>), gr, dim3(BLOCK), 0, a.stream, (const S*)a.src, (double*)a.dst, g);
+            break;
+        case AUX_EXPORT_PULL:
+            hipLaunchKernelGGL((k_export<L, S, false, false>), gr, dim3(BLOCK), 0, a.stream, (const S*)a.src, (double*)a.dst, g);
+            break;
+        case AUX_FIELDS_DIRECT:
+            hipLaunchKernelGGL((k_export<L, S, true, true>), gr, dim3(BLOCK), 0, a.stream, (const S*)a.src, (double*)a.dst, g);
+            break;
+        case AUX_FIELDS_PULL:
+            hipLaunchKernelGGL((k_export<L, S, false, true>), gr, dim3(BLOCK), 0, a.stream, (const S*)a.src, (double*)a.dst, g);
+            break;
+        case AUX_IMPORT:
+            hipLaunchKernelGGL((k_import<L, S>), gr, dim3(BLOCK), 0, a.stream, (const double*)a.src, (S*)a.dst, g);
+            break;
+        case AUX_DESIGN:
+            hipLaunchKernelGGL((k_design<T>), gr, dim3(BLOCK), 0, a.stream, (const double*)a.src, (T*)a.dst, g.N, a.map, a.q);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Dispatch on (lattice, precision): F64 stores and computes in double;
+// F32 stores float; F16S stores _Float16; both compute in float.
+#define LBM_DISPATCH(FN, ARG)                                                                        \
+    switch (ARG.lattice * 3 + ARG.prec) {                                                           \
+        case 0: return FN<D2Q9, double, double>(ARG);                                               \
+        case 1: return FN<D2Q9, float, float>(ARG);                                                 \
+        case 2: return FN<D2Q9, _Float16, float>(ARG);                                              \
+        case 3: return FN<D3Q19, double, double>(ARG);                                              \
+        case 4: return FN<D3Q19, float, float>(ARG);                                                \
+        case 5: return FN<D3Q19, _Float16, float>(ARG);                                             \
+        default: return hipErrorInvalidValue;                                                        \
+    }
+
+hipError_t launch_step(const StepLaunch& a) { LBM_DISPATCH(step_t, a) }
+
+hipError_t launch_aux(const AuxLaunch& a) { LBM_DISPATCH(aux_t, a) }
+
+hipError_t launch_adjoint(const AdjLaunch& a) {
+    switch (a.lattice * 3 + a.prec) {
+        case 0: return adj_t<D2Q9, double, double, double>(a);
+        case 1: return adj_t<D2Q9, float, float, float>(a);
+        case 2: return adj_t<D2Q9, _Float16, float, float>(a);
+        case 3: return adj_t<D3Q19, double, double, double>(a);
+        case 4: return adj_t<D3Q19, float, float, float>(a);
+        case 5: return adj_t<D3Q19, _Float16, float, float>(a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_reduce(const double* partials, long nblocks, int nsamples, double* samples,
+                         double weight, double* acc, hipStream_t stream) {
+    hipLaunchKernelGGL(k_reduce_samples, dim3(nsamples), dim3(BLOCK), 0, stream, partials, nblocks, samples);
+    hipLaunchKernelGGL(k_window_sum, dim3(1), dim3(64), 0, stream, samples, nsamples, weight, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* gamma, const double* sens, double* out, long N, int map, double q,
+                           hipStream_t stream) {
+    hipLaunchKernelGGL(k_finalize, grid_for(N), dim3(BLOCK), 0, stream, gamma, sens, out, N, map, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, long n, double v, hipStream_t stream) {
+    hipLaunchKernelGGL(k_fill, grid_for(n), dim3(BLOCK), 0, stream, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t stream) {
+    const long nwords = (long)(bytes / 4);
+    hipLaunchKernelGGL(k_copy_bytes, grid_for(nwords), dim3(BLOCK), 0, stream, (const unsigned int*)src,
+                       (unsigned int*)dst, nwords);
+    return hipGetLastError();
+}
+
+long blocks_for(long n) { return (n + BLOCK - 1) / BLOCK; }
+
+}  // namespace lbm

@@ -1,0 +1,76 @@
+// Launch descriptors between the host driver and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+
+namespace lbm {
+
+struct StepLaunch {
+    int lattice, prec;
+    const void* gin;       // post-collision state G^{k-1}
+    void* gout;            // post-collision state G^k
+    void* pre;             // if not null: also store f^k here (checkpoint)
+    const void* s;         // bounce-back fraction plane
+    int sample;            // write block partials of the samples of f^k
+    double* partials;      // [blocks][3]
+    Geo geo;
+    Phys ph;
+    Obj ob;
+    hipStream_t stream;
+};
+
+struct AdjLaunch {
+    int lattice, prec;
+    const void* nu_in;     // nu_hat^k
+    void* nu_out;          // nu_hat^{k-1}
+    const void* state;     // f^{k-1} (direct) or G^{k-2} (pull)
+    const void* s;
+    double* sens;
+    int direct, seed;
+    double src_w;          // weight of the objective source on f^{k-1} (0: none)
+    Geo geo;
+    Phys ph;
+    Obj ob;
+    hipStream_t stream;
+};
+
+enum AuxOp {
+    AUX_COLLIDE = 0,       // dst = C(src) with s
+    AUX_INIT_EQ,           // dst = f^eq(rho0, u_init) - w
+    AUX_EXPORT_DIRECT,     // dst (FP64) = src + w
+    AUX_EXPORT_PULL,       // dst (FP64) = BC(S(src)) + w
+    AUX_FIELDS_DIRECT,     // dst (FP64) = rho, u of src + w
+    AUX_FIELDS_PULL,       // dst (FP64) = rho, u of BC(S(src)) + w
+    AUX_IMPORT,            // dst = src (FP64) - w
+    AUX_DESIGN             // dst = s(src = gamma)
+};
+
+struct AuxLaunch {
+    int lattice, prec;
+    int op;
+    const void* src;
+    void* dst;
+    const void* s;
+    double rho0;
+    int umode;
+    int map;
+    double q;
+    Geo geo;
+    Phys ph;
+    hipStream_t stream;
+};
+
+hipError_t launch_step(const StepLaunch& a);
+hipError_t launch_adjoint(const AdjLaunch& a);
+hipError_t launch_aux(const AuxLaunch& a);
+hipError_t launch_reduce(const double* partials, long nblocks, int nsamples, double* samples, double weight,
+                         double* acc, hipStream_t stream);
+hipError_t launch_finalize(const double* gamma, const double* sens, double* out, long N, int map, double q,
+                           hipStream_t stream);
+hipError_t launch_fill(double* p, long n, double v, hipStream_t stream);
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
+long blocks_for(long n);
+
+}  // namespace lbm

@@ -1,0 +1,208 @@
+"""Python front end of the HIP library: a Solver owning its device workspace
+(torch memory on the current HIP stream) and forwarding every call to the C
+ABI. No solver arithmetic happens here."""
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+_PREC = {"f64": B.LBM_F64, "f32": B.LBM_F32, "f16s": B.LBM_F16S}
+_OBJ = {"dp": B.LBM_J_PRESSURE_DROP, "diss_dp": B.LBM_J_DISSIPATION_PLUS_DP}
+_SMAP = {"linear": B.LBM_S_LINEAR, "paper": B.LBM_S_PAPER}
+
+
+def to_device_order(a):
+    """[x, y(, z)] array -> flat x-fastest node order used by the library."""
+    a = np.asarray(a)
+    return np.ascontiguousarray(a.transpose(tuple(range(a.ndim - 1, -1, -1)))).reshape(-1)
+
+
+def from_device_order(flat, shape):
+    """Inverse of to_device_order for one field."""
+    rev = tuple(reversed(shape))
+    a = np.asarray(flat).reshape(rev)
+    return a.transpose(tuple(range(a.ndim - 1, -1, -1)))
+
+
+def make_config(w, prec="f32"):
+    """lbm_config for a Workload; returns (config, keep-alive buffers)."""
+    shape = tuple(w.shape)
+    nz = shape[2] if len(shape) == 3 else 1
+    ny = shape[1]
+    west = np.ascontiguousarray(np.asarray(w.west, dtype=np.int32))
+    east = np.ascontiguousarray(np.asarray(w.east, dtype=np.int32))
+    u_in = np.ascontiguousarray(np.asarray(w.u_in, dtype=np.float64))
+    assert west.shape == (ny,) and east.shape == (ny,) and u_in.shape == (ny,)
+    per = tuple(w.periodic) + (False,) * (3 - len(w.periodic))
+    c = B.lbm_config()
+    c.lattice = B.LBM_D2Q9 if len(shape) == 2 else B.LBM_D3Q19
+    c.nx, c.ny, c.nz = shape[0], ny, nz
+    c.tau = float(w.tau)
+    c.c_smag = float(w.c_smag)
+    c.prec = _PREC[prec]
+    c.s_map = _SMAP[w.s_map]
+    c.s_q = float(w.s_q)
+    c.periodic_x, c.periodic_y, c.periodic_z = (int(bool(p)) for p in per)
+    c.west = west.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    c.east = east.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    c.u_in = u_in.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    c.rho_out = float(w.rho_out)
+    c.rho_init = float(w.rho_init)
+    c.u_init_mode = int(w.u_init_mode)
+    c.window_len = int(w.window_len)
+    c.sample_every = int(w.sample_every)
+    c.max_windows = int(w.max_windows)
+    c.eps = float(w.eps)
+    c.objective = _OBJ[w.objective]
+    c.monitor = _OBJ[w.monitor]
+    c.sec_in_x, c.sec_in_lo, c.sec_in_hi = (int(v) for v in w.sec_in)
+    c.sec_out_x, c.sec_out_lo, c.sec_out_hi = (int(v) for v in w.sec_out)
+    c.ckpt_every = int(w.ckpt_every)
+    return c, (west, east, u_in)
+
+
+def workspace_bytes(w, prec="f32"):
+    cfg, keep = make_config(w, prec)
+    n = ctypes.c_size_t(0)
+    B.check(B.lib.lbm_workspace_bytes(ctypes.byref(cfg), ctypes.byref(n)))
+    return n.value
+
+
+class Solver:
+    """One context of the library on the current HIP device and stream.
+
+    gamma: design field indexed [x, y(, z)] (numpy or torch), 1 = solid.
+    """
+
+    def __init__(self, w, prec="f32", gamma=None, device="cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the solver needs a GPU (no CPU fallback)")
+        self.w = w
+        self.prec = prec
+        self.shape = tuple(w.shape)
+        self.N = int(np.prod(self.shape))
+        self.Q = 9 if len(self.shape) == 2 else 19
+        self.D = len(self.shape)
+        self.device = torch.device(device)
+        cfg, self._keep = make_config(w, prec)
+        self._cfg = cfg
+        n = ctypes.c_size_t(0)
+        B.check(B.lib.lbm_workspace_bytes(ctypes.byref(cfg), ctypes.byref(n)))
+        self.workspace_bytes = n.value
+        self._ws = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.device)
+        g = self._gamma_tensor(w.gamma if gamma is None else gamma)
+        self._ctx = ctypes.c_void_p()
+        B.check(B.lib.lbm_init(ctypes.byref(cfg), ctypes.c_void_p(g.data_ptr()),
+                               ctypes.c_void_p(self._ws_ptr), ctypes.c_size_t(n.value),
+                               ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._ctx)))
+
+    # ------------------------------------------------------------ helpers
+    def _gamma_tensor(self, gamma):
+        if isinstance(gamma, torch.Tensor):
+            if tuple(gamma.shape) == self.shape:
+                g = gamma.detach().to(self.device, torch.float64)
+                g = g.permute(*range(g.ndim - 1, -1, -1)).contiguous().reshape(-1)
+            else:
+                g = gamma.detach().to(self.device, torch.float64).contiguous().reshape(-1)
+        else:
+            g = torch.from_numpy(to_device_order(np.asarray(gamma, np.float64))).to(self.device)
+        assert g.numel() == self.N
+        return g
+
+    def _state_to_host_layout(self, flat):
+        """(Q*N,) library order -> [alpha, x, y(, z)]."""
+        rev = (self.Q,) + tuple(reversed(self.shape))
+        a = flat.reshape(rev)
+        return a.transpose((0,) + tuple(range(a.ndim - 1, 0, -1)))
+
+    # -------------------------------------------------------------- calls
+    def set_gamma(self, gamma):
+        g = self._gamma_tensor(gamma)
+        B.check(B.lib.lbm_set_gamma(self._ctx, ctypes.c_void_p(g.data_ptr())))
+
+    def reset(self):
+        B.check(B.lib.lbm_reset(self._ctx))
+
+    def forward(self, n_steps, stop_on_converge=False):
+        rep = B.lbm_fwd_report()
+        B.check(B.lib.lbm_forward(self._ctx, int(n_steps), int(bool(stop_on_converge)), ctypes.byref(rep)))
+        return {k: getattr(rep, k) for k, _ in B.lbm_fwd_report._fields_}
+
+    def history(self):
+        n = ctypes.c_int(0)
+        B.check(B.lib.lbm_window_history(self._ctx, None, None, None, 0, ctypes.byref(n)))
+        k = n.value
+        J = np.zeros(max(k, 1))
+        M = np.zeros(max(k, 1))
+        R = np.zeros(max(k, 1))
+        P = ctypes.POINTER(ctypes.c_double)
+        B.check(B.lib.lbm_window_history(self._ctx, J.ctypes.data_as(P), M.ctypes.data_as(P),
+                                         R.ctypes.data_as(P), k, ctypes.byref(n)))
+        return J[:k], M[:k], R[:k]
+
+    def adjoint(self, window=0):
+        """dJ/dgamma of the last completed window: (torch FP64 [x, y(, z)], J)."""
+        out = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        J = ctypes.c_double(0.0)
+        B.check(B.lib.lbm_adjoint(self._ctx, int(window), ctypes.c_void_p(out.data_ptr()), ctypes.byref(J)))
+        rev = tuple(reversed(self.shape))
+        g = out.reshape(rev).permute(*range(len(rev) - 1, -1, -1))
+        return g, J.value
+
+    def replay(self, gamma):
+        """Objective of the last completed window replayed with gamma."""
+        g = self._gamma_tensor(gamma)
+        J = ctypes.c_double(0.0)
+        B.check(B.lib.lbm_window_replay(self._ctx, ctypes.c_void_p(g.data_ptr()), ctypes.byref(J)))
+        return J.value
+
+    def get_state(self):
+        """(f [alpha, x, y(, z)] FP64 numpy, step)."""
+        buf = np.empty(self.Q * self.N, np.float64)
+        step = ctypes.c_long(0)
+        B.check(B.lib.lbm_get_state(self._ctx, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    ctypes.byref(step)))
+        return np.ascontiguousarray(self._state_to_host_layout(buf)), step.value
+
+    def set_state(self, f, step):
+        f = np.asarray(f, np.float64)
+        flat = np.ascontiguousarray(f.transpose((0,) + tuple(range(f.ndim - 1, 0, -1)))).reshape(-1)
+        B.check(B.lib.lbm_set_state(self._ctx, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(step)))
+
+    def fields(self):
+        """rho and u as a torch FP64 tensor [1 + D, x, y(, z)]."""
+        out = torch.empty((1 + self.D) * self.N, dtype=torch.float64, device=self.device)
+        B.check(B.lib.lbm_get_fields(self._ctx, ctypes.c_void_p(out.data_ptr())))
+        rev = (1 + self.D,) + tuple(reversed(self.shape))
+        return out.reshape(rev).permute(0, *range(len(rev) - 1, 0, -1))
+
+    def timing(self, enable):
+        out = np.zeros(6)
+        B.check(B.lib.lbm_timing(self._ctx, int(bool(enable)), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return {"fwd_launches": out[0], "fwd_ms": out[1], "adj_launches": out[2], "adj_ms": out[3],
+                "rec_launches": out[4], "rec_ms": out[5]}
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            B.lib.lbm_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def state_rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+__all__ = ["Solver", "make_config", "workspace_bytes", "to_device_order", "from_device_order",
+           "state_rel_l2"]

@@ -1,0 +1,203 @@
+"""Seeded synthetic inputs: geometries, design fields, inlet profiles and
+window parameters of the benchmark and test configurations.
+
+This module holds no solver arithmetic. It only describes problems (numbers
+and numpy arrays) so that the HIP path and the CPU oracle can be fed the
+same inputs. Arrays are indexed [x, y] (2D) or [x, y, z] (3D); the binding
+converts them to the library's x-fastest node order.
+
+Readings used for the inputs (the paper does not fix them):
+  * Re = U L / nu with U the peak inlet speed and L the obstacle diameter,
+    step height or channel width; nu = (tau - 1/2) / 3 (Eq.
+    viscosity_relation), so tau = 1/2 + 3 U L / Re.
+  * parabolic inlet rows: u0(y) = 4 U (y - a)(b - y) / (b - a)^2 with the
+    halfway walls at y = a and y = b (half a node outside the open rows);
+  * an obstacle given as gamma = 1 inside, 0 outside, with a linear ramp two
+    nodes wide: gamma = clip((R + 1 - r) / 2, 0, 1);
+  * the initial state is rho = 1 and u = (u0(y), 0) along x unless stated.
+"""
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+WALL, VELOCITY, PRESSURE = 0, 1, 2
+
+
+@dataclass
+class Workload:
+    name: str
+    shape: tuple                     # (nx, ny) or (nx, ny, nz)
+    tau: float
+    c_smag: float
+    gamma: np.ndarray                # design field, 1 = solid
+    west: np.ndarray                 # row kinds of the x = 0 face
+    east: np.ndarray                 # row kinds of the x = nx-1 face
+    u_in: np.ndarray                 # inlet speed per row
+    periodic: tuple = (False, False, False)
+    rho_out: float = 1.0
+    rho_init: float = 1.0
+    u_init_mode: int = 1             # 1: u = (u_in(y), 0) everywhere at t = 0
+    objective: str = "dp"            # "dp" or "diss_dp"
+    monitor: str = "dp"
+    sec_in: tuple = (0, 0, 1)        # (x, ylo, yhi)
+    sec_out: tuple = (0, 0, 1)
+    window_len: int = 100
+    sample_every: int = 1
+    ckpt_every: int = 10
+    eps: float = -1.0
+    max_windows: int = 1
+    n_steps: int = 100               # forward steps of the workload
+    s_map: str = "linear"
+    s_q: float = 0.1
+    notes: dict = field(default_factory=dict)
+
+    @property
+    def nodes(self):
+        return int(np.prod(self.shape))
+
+    @property
+    def lattice(self):
+        return "D2Q9" if len(self.shape) == 2 else "D3Q19"
+
+
+def tau_from_re(u, length, re):
+    return 0.5 + 3.0 * u * length / re
+
+
+def parabola(ny, lo, hi, u_max):
+    """u0 on rows [lo, hi) with walls half a node outside them; 0 elsewhere."""
+    y = np.arange(ny, dtype=np.float64)
+    a, b = lo - 0.5, hi - 0.5
+    u = 4 * u_max * (y - a) * (b - y) / (b - a) ** 2
+    u[(y < lo) | (y >= hi)] = 0.0
+    return u
+
+
+def disk(shape, cx, cy, radius):
+    """gamma of a disk (a cylinder along z in 3D) with a 2-node linear ramp."""
+    X, Y = np.meshgrid(np.arange(shape[0]), np.arange(shape[1]), indexing="ij")
+    r = np.hypot(X - cx, Y - cy)
+    g = np.clip((radius + 1 - r) / 2, 0.0, 1.0)
+    if len(shape) == 3:
+        g = np.repeat(g[:, :, None], shape[2], axis=2)
+    return g
+
+
+def _rows(ny, lo, hi, kind):
+    k = np.zeros(ny, np.int64)
+    k[lo:hi] = kind
+    return k
+
+
+def cylinder_channel(nx=160, ny=64, radius=8, center=(40, 32), u_max=0.05, re=100.0,
+                     window_len=500, sample_every=1, ckpt_every=50, n_windows=4, c_smag=0.1):
+    """Cylinder in a channel: parabolic Zou-He inlet, pressure outlet, walls
+    top and bottom, J = mean inlet-outlet pressure drop over each window."""
+    return Workload(
+        name=f"cylinder_channel_{nx}x{ny}",
+        shape=(nx, ny), tau=tau_from_re(u_max, 2 * radius, re), c_smag=c_smag,
+        gamma=disk((nx, ny), center[0], center[1], radius),
+        west=_rows(ny, 1, ny - 1, VELOCITY), east=_rows(ny, 1, ny - 1, PRESSURE),
+        u_in=_channel_parabola(ny, u_max),
+        sec_in=(0, 1, ny - 1), sec_out=(nx - 1, 1, ny - 1),
+        window_len=window_len, sample_every=sample_every, ckpt_every=ckpt_every,
+        eps=-1.0, max_windows=n_windows, n_steps=n_windows * window_len)
+
+
+def _channel_parabola(ny, u_max):
+    """Parabola between the halfway walls y = -1/2 and y = ny - 1/2."""
+    y = np.arange(ny, dtype=np.float64)
+    u = 4 * u_max * (y + 0.5) * (ny - 0.5 - y) / ny ** 2
+    u[0] = u[-1] = 0.0      # corner rows are wall nodes
+    return u
+
+
+def backward_facing_step(nx=800, ny=200, step_len=100, step_h=100, u_max=0.05, re=800.0,
+                         window_len=2000, sample_every=100, eps=1e-3, max_windows=20,
+                         ckpt_every=100, c_smag=0.1):
+    """Backward-facing step: the step (gamma = 1) fills x < step_len,
+    y < step_h; the inlet rows above it carry a parabola between the step top
+    and the upper wall; pressure outlet; consecutive windows with the
+    criterion on the window-mean pressure drop."""
+    g = np.zeros((nx, ny))
+    g[:step_len, :step_h] = 1.0
+    u = parabola(ny, step_h, ny, u_max)
+    u[ny - 1] = 0.0
+    return Workload(
+        name=f"backward_facing_step_{nx}x{ny}",
+        shape=(nx, ny), tau=tau_from_re(u_max, step_h, re), c_smag=c_smag, gamma=g,
+        west=_rows(ny, step_h, ny - 1, VELOCITY), east=_rows(ny, 1, ny - 1, PRESSURE), u_in=u,
+        sec_in=(0, step_h, ny - 1), sec_out=(nx - 1, 1, ny - 1),
+        window_len=window_len, sample_every=sample_every, ckpt_every=ckpt_every,
+        eps=eps, max_windows=max_windows, n_steps=max_windows * window_len)
+
+
+def cylinder_wake(nx=2048, ny=512, radius=32, u_max=0.04, re=1000.0, window_len=20000,
+                  sample_every=20, ckpt_every=500, max_windows=5, eps=1e-3, c_smag=0.1):
+    """Cylinder wake at high Reynolds number (LES regime)."""
+    w = cylinder_channel(nx, ny, radius, (nx // 4, ny // 2), u_max, re, window_len, sample_every,
+                         ckpt_every, max_windows, c_smag)
+    w.name = f"cylinder_wake_{nx}x{ny}"
+    w.eps = eps
+    return w
+
+
+def u_bend(n=1024, width=128, u0=0.03, re=2000.0, window_len=10000, sample_every=20,
+           ckpt_every=500, seed=0, sigma=4.0, c_smag=0.1, max_windows=2):
+    """U-bend: inlet and outlet legs on the west face joined by a half
+    annulus; the channel is fluid (gamma = 0) and every other node is a
+    design node with gamma drawn uniform in [0, 1] from the seed,
+    Gaussian-smoothed (sigma nodes) and rescaled to [0, 1]. Uniform inlet
+    speed u0; J = dissipation plus the pressure drop between sections at
+    x = width across each leg."""
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.default_rng(seed)
+    raw = rng.random((n, n))
+    sm = gaussian_filter(raw, sigma, mode="nearest")
+    g = (sm - sm.min()) / (sm.max() - sm.min())
+    c = n // 2
+    in_lo, in_hi = c + width // 2, c + width // 2 + width           # upper (inlet) leg
+    out_lo, out_hi = c - width // 2 - width, c - width // 2         # lower (outlet) leg
+    x_bend = 3 * width
+    X, Y = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    chan = np.zeros((n, n), bool)
+    chan[:x_bend, in_lo:in_hi] = True
+    chan[:x_bend, out_lo:out_hi] = True
+    r = np.hypot(X - x_bend, Y - (c - 0.5))
+    r_in, r_out = c - 0.5 - (out_hi - 0.5), c - 0.5 - (out_lo - 0.5)
+    chan |= (X >= x_bend) & (r >= r_in) & (r <= r_out)
+    g[chan] = 0.0
+    west = np.zeros(n, np.int64)
+    west[in_lo:in_hi] = VELOCITY
+    west[out_lo:out_hi] = PRESSURE
+    u = np.zeros(n)
+    u[in_lo:in_hi] = u0
+    return Workload(
+        name=f"u_bend_{n}x{n}", shape=(n, n), tau=tau_from_re(u0, width, re), c_smag=c_smag,
+        gamma=g, west=west, east=np.zeros(n, np.int64), u_in=u, u_init_mode=0,
+        objective="diss_dp", monitor="diss_dp",
+        sec_in=(width, in_lo, in_hi), sec_out=(width, out_lo, out_hi),
+        window_len=window_len, sample_every=sample_every, ckpt_every=ckpt_every,
+        eps=0.05, max_windows=max_windows, n_steps=max_windows * window_len)
+
+
+def cylinder_3d(nx=384, ny=128, nz=128, radius=16, center=(96, 64), u_max=0.05, re=1000.0,
+                window_len=5000, sample_every=20, ckpt_every=250, n_windows=4, c_smag=0.1):
+    """D3Q19 channel with a cylinder along z: parabolic inlet in y, uniform
+    in z; pressure outlet; walls in y; periodic in z."""
+    w = Workload(
+        name=f"cylinder_3d_{nx}x{ny}x{nz}", shape=(nx, ny, nz),
+        tau=tau_from_re(u_max, 2 * radius, re), c_smag=c_smag,
+        gamma=disk((nx, ny, nz), center[0], center[1], radius),
+        west=_rows(ny, 1, ny - 1, VELOCITY), east=_rows(ny, 1, ny - 1, PRESSURE),
+        u_in=_channel_parabola(ny, u_max), periodic=(False, False, True),
+        sec_in=(0, 1, ny - 1), sec_out=(nx - 1, 1, ny - 1),
+        window_len=window_len, sample_every=sample_every, ckpt_every=ckpt_every,
+        eps=-1.0, max_windows=n_windows, n_steps=n_windows * window_len)
+    return w
+
+
+def random_design(shape, seed, lo=0.0, hi=1.0):
+    """Uniform random design field (test input)."""
+    return np.random.default_rng(seed).uniform(lo, hi, size=shape)

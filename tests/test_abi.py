@@ -1,0 +1,131 @@
+"""C-ABI contract on the CPU: the library loads, exports every symbol that
+include/lbm.h declares, validates configurations before any HIP call, and
+its workspace sizing matches the documented layout. No kernel runs here."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2608_19617_amd import binding
+    return binding
+
+
+def test_exports_every_declared_symbol(B):
+    declared = _declared_functions()
+    assert len(declared) >= 14
+    assert sorted(B.EXPORTED) == declared
+    for name in declared:
+        assert hasattr(B.lib, name), name
+
+
+def test_header_is_plain_c():
+    """The header compiles as C (no HIP, torch or C++ types)."""
+    import subprocess
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "t.c")
+        with open(src, "w") as fh:
+            fh.write('#include "lbm.h"\nint main(void){lbm_config c; (void)c; return 0;}\n')
+        r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                            "-c", src, "-o", os.path.join(d, "t.o")], capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
+
+
+def _cfg(B, **over):
+    from paper_2608_19617_amd import workloads as W
+    from paper_2608_19617_amd.solver import make_config
+    w = W.cylinder_channel(nx=40, ny=16, radius=3, center=(10, 8), window_len=20, ckpt_every=5)
+    for k, v in over.items():
+        setattr(w, k, v)
+    return make_config(w)
+
+
+def _bytes(B, cfg):
+    n = ctypes.c_size_t(0)
+    st = B.lib.lbm_workspace_bytes(ctypes.byref(cfg), ctypes.byref(n))
+    return st, n.value
+
+
+def test_workspace_layout(B):
+    cfg, keep = _cfg(B)
+    st, n = _bytes(B, cfg)
+    assert st == B.LBM_OK
+    N, Q = 40 * 16, 9
+    state = -(-Q * N * 4 // 256) * 256
+    # two ping-pong states, two rings of |W|/K = 4 slots, K = 5 recompute slots
+    assert n >= (2 + 2 * 4 + 5) * state
+    assert n < (2 + 2 * 4 + 5) * state + 2 * 2 * Q * N * 4 + 64 * 1024 + 20 * 3 * 8 * 8
+
+
+@pytest.mark.parametrize("field,value", [
+    ("tau", 0.5), ("tau", float("nan")), ("c_smag", -0.1), ("window_len", 0),
+    ("sample_every", 3), ("ckpt_every", 3), ("max_windows", 0), ("eps", float("nan")),
+    ("rho_out", 0.0), ("sec_in", (0, 5, 5)), ("sec_out", (40, 1, 15)), ("u_init_mode", 2),
+])
+def test_invalid_configs_rejected(B, field, value):
+    cfg, keep = _cfg(B, **{field: value})
+    st, _ = _bytes(B, cfg)
+    assert st == B.LBM_E_INVALID
+    assert len(B.lib.lbm_last_error()) > 0
+
+
+def test_invalid_rows_rejected(B):
+    from paper_2608_19617_amd import workloads as W
+    from paper_2608_19617_amd.solver import make_config
+    w = W.cylinder_channel(nx=40, ny=16, radius=3, center=(10, 8), window_len=20, ckpt_every=5)
+    w.west = w.west.copy()
+    w.west[0] = 1                       # velocity row touching the y wall
+    cfg, keep = make_config(w)
+    assert _bytes(B, cfg)[0] == B.LBM_E_INVALID
+    w = W.cylinder_channel(nx=40, ny=16, radius=3, center=(10, 8), window_len=20, ckpt_every=5)
+    w.east = w.east.copy()
+    w.east[4] = 1                       # east velocity rows are not modelled
+    cfg, keep = make_config(w)
+    assert _bytes(B, cfg)[0] == B.LBM_E_INVALID
+    w = W.cylinder_channel(nx=40, ny=16, radius=3, center=(10, 8), window_len=20, ckpt_every=5)
+    w.u_in = np.full(16, 0.7)           # |u0| must stay below 0.5
+    cfg, keep = make_config(w)
+    assert _bytes(B, cfg)[0] == B.LBM_E_INVALID
+
+
+def test_null_arguments(B):
+    assert B.lib.lbm_workspace_bytes(None, None) == B.LBM_E_INVALID
+    cfg, keep = _cfg(B)
+    assert B.lib.lbm_forward(None, 1, 0, None) == B.LBM_E_INVALID
+    assert B.lib.lbm_adjoint(None, 0, None, None) == B.LBM_E_INVALID
+    out = ctypes.c_void_p()
+    # NULL gamma and workspace are rejected before any HIP call
+    assert B.lib.lbm_init(ctypes.byref(cfg), None, None, 0, None, ctypes.byref(out)) == B.LBM_E_INVALID
+    # misaligned workspace
+    assert B.lib.lbm_init(ctypes.byref(cfg), ctypes.c_void_p(256), ctypes.c_void_p(258), 1 << 30,
+                          None, ctypes.byref(out)) == B.LBM_E_INVALID
+    # too-small workspace
+    assert B.lib.lbm_init(ctypes.byref(cfg), ctypes.c_void_p(256), ctypes.c_void_p(512), 16,
+                          None, ctypes.byref(out)) == B.LBM_E_NOMEM
+
+
+def test_product_path_has_no_cpu_fallback():
+    """The binding refuses to run without the HIP library and the package never
+    imports the oracle."""
+    pkg = os.path.join(ROOT, "paper_2608_19617_amd")
+    for fn in os.listdir(pkg):
+        if fn.endswith(".py"):
+            text = open(os.path.join(pkg, fn)).read()
+            assert "oracle" not in re.sub(r'""".*?"""', "", text, flags=re.S), fn
+    src = open(os.path.join(pkg, "binding.py")).read()
+    assert "raise ImportError" in src
