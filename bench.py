@@ -1,0 +1,219 @@
+"""Benchmark of the windowed LBM-LES forward + discrete-adjoint hot path.
+
+Workload: backward-facing step, 800 x 200 D2Q9 nodes, regularized BGK with
+Smagorinsky C_s = 0.1, Re = 800 on the step height, parabolic inlet
+u_max = 0.05, pressure outlet; consecutive windows of 2000 steps sampled
+every 100 steps, criterion 1e-3 on the window-mean pressure drop, at most
+20 windows (40k steps); then the discrete adjoint over the representative
+window (checkpoints every 100 steps in HBM, recompute, adjoint) -> dJ/dgamma.
+
+One benchmark step = set the design field (reset to t = 0) -> forward window
+loop until the criterion passes -> adjoint over that window. The inputs are
+resident in HBM before the timed region. value = lattice updates per second
+over the timed steps, counting every forward step and every adjoint step of
+each node once (recompute steps are not counted as updates).
+
+Prints one JSON line (see the keys below). Single GPU only.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS fwd & adjoint step, % HBM peak; FP32/FP16 vs FP64 at stated dJ/dγ error"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per lattice update of the forward step: read and write
+# of the Q populations in storage precision plus the bounce-back fraction
+# plane in compute precision (boundary kinds come from coordinates).
+FWD_BYTES = {"f64": 9 * 8 * 2 + 8, "f32": 9 * 4 * 2 + 4, "f16s": 9 * 2 * 2 + 4}
+# Adjoint step: adjoint populations read + write, pre-state read, s, FP64
+# sensitivity read-modify-write.
+ADJ_BYTES = {"f64": 9 * 8 * 2 + 9 * 8 + 8 + 16, "f32": 9 * 4 * 2 + 9 * 4 + 4 + 16,
+             "f16s": 9 * 4 * 2 + 9 * 2 + 4 + 16}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="f32", choices=["f64", "f32", "f16s"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 / FP16S comparison")
+    ap.add_argument("--max-windows", type=int, default=20)
+    return ap.parse_args()
+
+
+def bench_step(sv, w, max_windows):
+    rep = sv.forward(max_windows * w.window_len, stop_on_converge=True)
+    g, J = sv.adjoint()
+    return rep, g, J
+
+
+def run_timed(sv, w, args, torch):
+    gamma = w.gamma
+    for _ in range(args.warmup):
+        sv.set_gamma(gamma)
+        bench_step(sv, w, args.max_windows)
+    torch.cuda.synchronize()
+    sv.timing(True)
+    total_fwd = total_adj = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sv.set_gamma(gamma)
+        rep, g, J = bench_step(sv, w, args.max_windows)
+        total_fwd += rep["steps_done"]
+        total_adj += w.window_len
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tm = sv.timing(False)
+    return dict(rep=rep, g=g, J=J, dt=dt, fwd=total_fwd, adj=total_adj, tm=tm)
+
+
+def cpu_baseline(w, fwd_per_step, adj_per_step):
+    """The oracle as it stands, on this host, on a bounded sample of the same
+    workload: 100 forward steps from t = 0 and a 6-step window adjoint."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from helpers import oracle_problem
+    from oracle import adjoint as ad
+    from oracle import forward as fw
+
+    n_f, n_a = 100, 6
+    with threadpool_limits(limits=1):
+        prob = oracle_problem(w)
+        s = fw.design_map(prob, w.gamma)
+        f = fw.initial_state(prob)
+        t0 = time.perf_counter()
+        for _ in range(n_f):
+            f = fw.step(prob, f, s)
+        t_f = (time.perf_counter() - t0) / n_f
+        prob_a = oracle_problem(w, window_len=n_a, sample_every=1)
+        t0 = time.perf_counter()
+        ad.window_gradient(prob_a, w.gamma, f)
+        t_wa = time.perf_counter() - t0
+        t_a = max(t_wa / n_a - t_f, 1e-9)      # the window gradient replays the forward too
+    N = w.nodes
+    secs = fwd_per_step * t_f + adj_per_step * t_a
+    value = N * (fwd_per_step + adj_per_step) / secs / 1e6
+    return {"value": round(value, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": (f"{n_f} forward steps and a {n_a}-step window adjoint of the same "
+                       f"{w.shape[0]}x{w.shape[1]} workload (FP64 numpy, 1 thread); per-step "
+                       f"times {t_f*1e3:.1f} ms forward, {t_a*1e3:.1f} ms adjoint, weighted by "
+                       f"the GPU step's mix of {fwd_per_step} forward + {adj_per_step} adjoint steps"),
+            "fwd_mlups": round(N / t_f / 1e6, 4), "adj_mlups": round(N / t_a / 1e6, 4)}
+
+
+def precision_compare(w, ref_prec, res_ref, args, torch, Solver):
+    """FP64 and FP16S beside the benchmarked precision: time one benchmark
+    step of each, and the error of J and dJ/dgamma of the same window
+    computed from the FP64 window-start state."""
+    import numpy as np
+    out = {}
+    sv64 = Solver(w, "f64")
+    sv64.set_gamma(w.gamma)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep64, g64, J64 = bench_step(sv64, w, args.max_windows)
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t0
+    n_upd64 = rep64["steps_done"] + w.window_len
+    out["f64"] = {"mlups": round(w.nodes * n_upd64 / t64 / 1e6, 1), "w_eff": rep64["w_eff"],
+                  "J": J64}
+    # shared window-start state: FP64 state entering W_eff
+    w_eff = rep64["w_eff"]
+    sv64.set_gamma(w.gamma)
+    start = (w_eff - 1) * w.window_len
+    if start > 0:
+        sv64.forward(start)
+    f_start, step = sv64.get_state()
+    sv64.forward(w.window_len)
+    g64w, J64w = sv64.adjoint()
+    g64w = g64w.cpu().numpy()
+    sv64.close()
+    for prec in ("f32", "f16s"):
+        sv = Solver(w, prec)
+        sv.set_gamma(w.gamma)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep, g, J = bench_step(sv, w, args.max_windows)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        n_upd = rep["steps_done"] + w.window_len
+        mlups = w.nodes * n_upd / tp / 1e6
+        sv.set_state(f_start, step)
+        sv.forward(w.window_len)
+        gw, Jw = sv.adjoint()
+        gw = gw.cpu().numpy()
+        out[prec] = {"mlups": round(mlups, 1), "w_eff": rep["w_eff"],
+                     "speedup_vs_f64": round(mlups / out["f64"]["mlups"], 3),
+                     "J_rel_err_vs_f64_same_start": float(abs(Jw - J64w) / abs(J64w)),
+                     "dJdgamma_rel_l2_vs_f64_same_start":
+                         float(np.linalg.norm(gw - g64w) / np.linalg.norm(g64w))}
+        sv.close()
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "decomposition is designed but not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    from paper_2608_19617_amd import workloads as W
+    from paper_2608_19617_amd.solver import Solver
+
+    w = W.backward_facing_step(max_windows=args.max_windows)
+    sv = Solver(w, args.prec)
+    res = run_timed(sv, w, args, torch)
+    N = w.nodes
+    upd = N * (res["fwd"] + res["adj"])
+    value = upd / res["dt"] / 1e6
+    tm = res["tm"]
+    fwd_avg_s = tm["fwd_ms"] / tm["fwd_launches"] * 1e-3
+    adj_avg_s = tm["adj_ms"] / tm["adj_launches"] * 1e-3
+    achieved = FWD_BYTES[args.prec] * N / fwd_avg_s / 1e9
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(res["dt"] / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.prec, "data": "synthetic",
+        "config": {"workload": "backward-facing step 800x200 D2Q9, Re 800, C_s 0.1, windows 2000 / "
+                               "dW 100 / eps 1e-3 / max 20, adjoint over W_eff with K = 100",
+                   "grid": list(w.shape), "window_len": w.window_len, "sample_every": w.sample_every,
+                   "ckpt_every": w.ckpt_every, "tau": w.tau,
+                   "fwd_steps_per_step": res["fwd"] // args.steps,
+                   "adj_steps_per_step": res["adj"] // args.steps,
+                   "w_eff": res["rep"]["w_eff"], "converged": res["rep"]["converged"]},
+        "roofline": {"bound": "hbm", "kernel": "k_step (forward)", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "bytes_per_lup": FWD_BYTES[args.prec],
+                     "avg_launch_us": round(fwd_avg_s * 1e6, 3)},
+        "fwd_kernel_mlups": round(N / fwd_avg_s / 1e6, 1),
+        "adj_kernel_mlups": round(N / adj_avg_s / 1e6, 1),
+        "adj_kernel": {"avg_launch_us": round(adj_avg_s * 1e6, 3), "bytes_per_lup": ADJ_BYTES[args.prec],
+                       "achieved_GBs": round(ADJ_BYTES[args.prec] * N / adj_avg_s / 1e9, 1)},
+        "J": res["J"],
+    }
+    sv.close()
+    if not args.no_compare:
+        line["precision"] = precision_compare(w, args.prec, res, args, torch, Solver)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(w, res["fwd"] // args.steps, res["adj"] // args.steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

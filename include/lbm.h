@@ -188,10 +188,13 @@ lbm_status lbm_set_state(lbm_ctx* ctx, const double* host_f, long step);
  * (planes of N values). */
 lbm_status lbm_get_fields(lbm_ctx* ctx, double* rho_u_dev);
 
-/* Per-launch HIP-event timing of the hot kernels. enable = 1 starts it (and
+/* HIP-event timing of the hot kernels: one event pair brackets each run of
+ * back-to-back launches of the forward step kernel, of the adjoint step
+ * kernel and of the recompute step launches. enable = 1 starts it (and
  * clears the counters), 0 stops it. If out is not NULL it receives 6
- * doubles: launches and total milliseconds of the forward step kernel,
- * of the adjoint step kernel and of the recompute step launches. */
+ * doubles: launches and total milliseconds of each of the three classes,
+ * so ms / launches is the average launch duration including the dispatch
+ * gaps between consecutive launches. */
 lbm_status lbm_timing(lbm_ctx* ctx, int enable, double* out);
 
 /* Thread-local message of the last failing call on this thread. */

@@ -53,7 +53,8 @@ lbm_status validate(const lbm_config* c) {
     if (c->lattice == LBM_D2Q9 && c->nz != 1) return fail(LBM_E_INVALID, "D2Q9 needs nz = 1");
     if (c->lattice == LBM_D3Q19 && c->nz < 3) return fail(LBM_E_INVALID, "D3Q19 needs nz >= 3");
     const double nodes = (double)c->nx * c->ny * c->nz;
-    if (nodes * (c->lattice == LBM_D2Q9 ? 9 : 19) > 4.0e9) return fail(LBM_E_INVALID, "grid too large");
+    if (nodes * (c->lattice == LBM_D2Q9 ? 9 : 19) > 2147483647.0)
+        return fail(LBM_E_INVALID, "grid too large (Q * nodes must stay below 2^31)");
     if (!(c->tau > 0.5) || !std::isfinite(c->tau)) return fail(LBM_E_INVALID, "tau must be > 0.5");
     if (!(c->c_smag >= 0.0) || !std::isfinite(c->c_smag)) return fail(LBM_E_INVALID, "c_smag must be >= 0");
     if (c->prec < LBM_F64 || c->prec > LBM_F16S) return fail(LBM_E_INVALID, "unknown precision");
@@ -127,11 +128,17 @@ void layout(const lbm_config* c, Layout& L) {
     L.total = o;
 }
 
+// Timing of the hot kernels: one HIP event pair brackets each run of
+// consecutive launches of one kernel class (forward step, adjoint step,
+// recompute step), so the per-launch average includes the back-to-back
+// dispatch gaps but no event overhead inside a run.
 struct Timer {
     bool on = false;
     std::vector<hipEvent_t> ev;      // pool of start/stop pairs
-    std::vector<int> cls;            // class of each pending pair
-    int used = 0;
+    std::vector<int> cls;            // class of each closed or open run
+    std::vector<long> cnt;           // launches in each run
+    int used = 0;                    // runs in the pool
+    int open = -1;                   // class of the open run, -1 if none
     double n[3] = {0, 0, 0}, ms[3] = {0, 0, 0};
 };
 
@@ -165,42 +172,47 @@ namespace {
 
 void* at(lbm_ctx* c, size_t off) { return c->ws + off; }
 
-lbm_status t_begin(lbm_ctx* c, int cls, int& slot) {
-    slot = -1;
-    if (!c->tm.on) return LBM_OK;
-    if (c->tm.used * 2 + 2 > (int)c->tm.ev.size()) {
-        // pool full: drain it
-        HIPCHK(hipStreamSynchronize(c->stream));
-        for (int i = 0; i < c->tm.used; ++i) {
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, c->tm.ev[2 * i], c->tm.ev[2 * i + 1]));
-            c->tm.n[c->tm.cls[i]] += 1;
-            c->tm.ms[c->tm.cls[i]] += ms;
-        }
-        c->tm.used = 0;
-    }
-    slot = c->tm.used++;
-    c->tm.cls[slot] = cls;
-    HIPCHK(hipEventRecord(c->tm.ev[2 * slot], c->stream));
-    return LBM_OK;
-}
-
-lbm_status t_end(lbm_ctx* c, int slot) {
-    if (slot < 0) return LBM_OK;
-    HIPCHK(hipEventRecord(c->tm.ev[2 * slot + 1], c->stream));
+lbm_status t_close(lbm_ctx* c) {
+    if (!c->tm.on || c->tm.open < 0) return LBM_OK;
+    HIPCHK(hipEventRecord(c->tm.ev[2 * (c->tm.used - 1) + 1], c->stream));
+    c->tm.open = -1;
     return LBM_OK;
 }
 
 lbm_status t_drain(lbm_ctx* c) {
-    if (!c->tm.on || c->tm.used == 0) return LBM_OK;
+    if (!c->tm.on) return LBM_OK;
+    lbm_status st = t_close(c);
+    if (st != LBM_OK) return st;
+    if (c->tm.used == 0) return LBM_OK;
     HIPCHK(hipStreamSynchronize(c->stream));
     for (int i = 0; i < c->tm.used; ++i) {
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, c->tm.ev[2 * i], c->tm.ev[2 * i + 1]));
-        c->tm.n[c->tm.cls[i]] += 1;
+        c->tm.n[c->tm.cls[i]] += (double)c->tm.cnt[i];
         c->tm.ms[c->tm.cls[i]] += ms;
     }
     c->tm.used = 0;
+    return LBM_OK;
+}
+
+// Called before each hot launch of class cls: extends the open run or
+// starts a new one.
+lbm_status t_launch(lbm_ctx* c, int cls) {
+    if (!c->tm.on) return LBM_OK;
+    if (c->tm.open == cls) {
+        c->tm.cnt[c->tm.used - 1] += 1;
+        return LBM_OK;
+    }
+    lbm_status st = t_close(c);
+    if (st != LBM_OK) return st;
+    if (2 * c->tm.used + 2 > (int)c->tm.ev.size()) {
+        if ((st = t_drain(c)) != LBM_OK) return st;
+    }
+    const int r = c->tm.used++;
+    c->tm.cls[r] = cls;
+    c->tm.cnt[r] = 1;
+    c->tm.open = cls;
+    HIPCHK(hipEventRecord(c->tm.ev[2 * r], c->stream));
     return LBM_OK;
 }
 
@@ -385,7 +397,7 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
     c->geo.nx = cfg->nx;
     c->geo.ny = cfg->ny;
     c->geo.nz = cfg->nz;
-    c->geo.N = L.N;
+    c->geo.N = (int)L.N;
     c->geo.per_x = cfg->periodic_x ? 1 : 0;
     c->geo.per_y = cfg->periodic_y ? 1 : 0;
     c->geo.per_z = cfg->periodic_z ? 1 : 0;
@@ -480,13 +492,12 @@ lbm_status lbm_forward(lbm_ctx* c, long n_steps, int stop_on_converge, lbm_fwd_r
             const long js = (mw == 0 ? W : mw) / dW - 1;
             a.partials = c->partials[0] + js * L.nblocks * 3;
         }
-        int slot;
-        if ((st = t_begin(c, 0, slot)) != LBM_OK) return st;
+        if ((st = t_launch(c, 0)) != LBM_OK) return st;
         HIPCHK(launch_step(a));
-        if ((st = t_end(c, slot)) != LBM_OK) return st;
         c->cur ^= 1;
         c->step = m;
         if (mw == 0) {
+            if ((st = t_close(c)) != LBM_OK) return st;
             double r[3];
             if ((st = window_end(c, c->acc, c->partials[0], r)) != LBM_OK) return st;
             double rel = NAN;
@@ -508,6 +519,7 @@ lbm_status lbm_forward(lbm_ctx* c, long n_steps, int stop_on_converge, lbm_fwd_r
             if (stop_on_converge && (conv || (int)c->M.size() >= c->cfg.max_windows)) break;
         }
     }
+    if ((st = t_close(c)) != LBM_OK) return st;
     HIPCHK(hipStreamSynchronize(c->stream));
     if ((st = t_drain(c)) != LBM_OK) return st;
     if (rep) {
@@ -573,11 +585,10 @@ lbm_status lbm_adjoint(lbm_ctx* c, int window, double* dJdgamma_dev, double* J_o
             for (long j = 1; j <= nrec; ++j) {
                 sa.gin = c->seg[j - 1];
                 sa.gout = c->seg[j];
-                int slot;
-                if ((st = t_begin(c, 2, slot)) != LBM_OK) return st;
+                if ((st = t_launch(c, 2)) != LBM_OK) return st;
                 HIPCHK(launch_step(sa));
-                if ((st = t_end(c, slot)) != LBM_OK) return st;
             }
+            if ((st = t_close(c)) != LBM_OK) return st;
         }
         if (last) {
             // terminal condition: nu_hat^{n_e} = BC^T (dJ/df^{n_e}), f^{n_e} = BC(S(G^{n_e - 1}))
@@ -601,12 +612,11 @@ lbm_status lbm_adjoint(lbm_ctx* c, int window, double* dJdgamma_dev, double* J_o
                 aa.state = c->seg[k - 2 - c0];
             }
             aa.src_w = (k > ns && (k - ns) % dW == 0) ? wgt : 0.0;
-            int slot;
-            if ((st = t_begin(c, 1, slot)) != LBM_OK) return st;
+            if ((st = t_launch(c, 1)) != LBM_OK) return st;
             HIPCHK(launch_adjoint(aa));
-            if ((st = t_end(c, slot)) != LBM_OK) return st;
             cur ^= 1;
         }
+        if ((st = t_close(c)) != LBM_OK) return st;
     }
     HIPCHK(launch_finalize(c->gamma, c->sens, dJdgamma_dev, L.N, c->cfg.s_map, c->cfg.s_q, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -699,12 +709,14 @@ lbm_status lbm_timing(lbm_ctx* c, int enable, double* out) {
     }
     if (enable) {
         if (c->tm.ev.empty()) {
-            c->tm.ev.resize(2048);
-            c->tm.cls.resize(1024);
+            c->tm.ev.resize(512);
+            c->tm.cls.resize(256);
+            c->tm.cnt.resize(256);
             for (auto& e : c->tm.ev) HIPCHK(hipEventCreate(&e));
         }
         for (int i = 0; i < 3; ++i) c->tm.n[i] = c->tm.ms[i] = 0.0;
         c->tm.used = 0;
+        c->tm.open = -1;
     }
     c->tm.on = enable != 0;
     return LBM_OK;

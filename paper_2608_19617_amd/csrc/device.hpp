@@ -20,7 +20,7 @@ enum RowKind : int { ROW_WALL = 0, ROW_VELOCITY = 1, ROW_PRESSURE = 2 };
 // Geometry and boundary description shared by every kernel.
 struct Geo {
     int nx, ny, nz;
-    long N;                    // nodes
+    int N;                     // nodes (the host keeps Q * N below 2^31)
     int per_x, per_y, per_z;   // periodic axes
     const signed char* west;   // per row kind of the x = 0 face
     const signed char* east;   // per row kind of the x = nx-1 face
@@ -42,17 +42,21 @@ struct Obj {
     double inv_nin, inv_nout;  // 1 / section node counts
 };
 
-__device__ __forceinline__ void node_coords(const Geo& g, long n, int& x, int& y, int& z) {
-    long r = n / g.nx;
-    x = (int)(n - r * g.nx);
+__device__ __forceinline__ void node_coords(const Geo& g, int n, int& x, int& y, int& z) {
+    const unsigned r = (unsigned)n / (unsigned)g.nx;
+    x = n - (int)r * g.nx;
     if (g.nz == 1) {
         y = (int)r;
         z = 0;
     } else {
-        z = (int)(r / g.ny);
-        y = (int)(r - (long)z * g.ny);
+        z = (int)(r / (unsigned)g.ny);
+        y = (int)r - z * g.ny;
     }
 }
+
+// Base pointer of population plane a (uniform across the wave).
+template <class P>
+__device__ __forceinline__ P* plane(P* base, int a, int N) { return base + (size_t)a * (size_t)N; }
 
 // Open-face code of a node: 0 = not open; 1 + face * 3 + kind otherwise
 // (face 0 = west, 1 = east). Rows touching a non-periodic y (or z) wall
@@ -80,16 +84,16 @@ __device__ __forceinline__ float to_f(S v) { return (float)v; }
 // axis is the halfway bounce-back of Eq. wall, h_a(x) = G_opp(a)(x), unless
 // the node is open, where the value is left for the Zou-He rule.
 template <class L, class S, class T>
-__device__ __forceinline__ void pull(const S* __restrict__ G, const Geo& g, long n, int x, int y,
+__device__ __forceinline__ void pull(const S* __restrict__ G, const Geo& g, int n, int x, int y,
                                      int z, int oc, T h[L::Q]) {
-    const long N = g.N;
+    const int N = g.N;
     const bool interior = x > 0 && x < g.nx - 1 && y > 0 && y < g.ny - 1 &&
                           (L::D == 2 || (z > 0 && z < g.nz - 1));
     if (interior) {
 #pragma unroll
         for (int a = 0; a < L::Q; ++a) {
-            const long off = (long)L::cx[a] + (long)L::cy[a] * g.nx + (long)L::cz[a] * g.nx * g.ny;
-            h[a] = (T)G[a * N + n - off];
+            const int off = L::cx[a] + L::cy[a] * g.nx + L::cz[a] * g.nx * g.ny;
+            h[a] = (T)plane(G, a, N)[(unsigned)(n - off)];
         }
         return;
     }
@@ -110,9 +114,9 @@ __device__ __forceinline__ void pull(const S* __restrict__ G, const Geo& g, long
             else out = true;
         }
         if (!out) {
-            h[a] = (T)G[a * N + ((long)zs * g.ny + ys) * g.nx + xs];
+            h[a] = (T)plane(G, a, N)[(unsigned)((zs * g.ny + ys) * g.nx + xs)];
         } else if (oc == 0) {
-            h[a] = (T)G[L::opp[a] * N + n];
+            h[a] = (T)plane(G, L::opp[a], N)[(unsigned)n];
         } else {
             h[a] = (T)0;
         }

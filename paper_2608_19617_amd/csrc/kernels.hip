@@ -75,7 +75,7 @@ template <class L, class S, class T, bool SAMPLE, bool WPRE>
 __global__ __launch_bounds__(BLOCK) void k_step(const S* __restrict__ gin, S* __restrict__ gout,
                                                 S* __restrict__ pre, const T* __restrict__ sfield,
                                                 Geo g, Phys ph, Obj ob, double* __restrict__ partials) {
-    const long n = (long)blockIdx.x * BLOCK + threadIdx.x;
+    const int n = (int)(blockIdx.x * BLOCK + threadIdx.x);
     const bool active = n < g.N;
     double v[3] = {0.0, 0.0, 0.0};
     if (active) {
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const S* __restrict__ gin, S* __
         if (oc) zou_he<L, T>(g, oc, y, h);
         if (WPRE) {
 #pragma unroll
-            for (int a = 0; a < L::Q; ++a) pre[a * g.N + n] = (S)h[a];
+            for (int a = 0; a < L::Q; ++a) plane(pre, a, g.N)[(unsigned)n] = (S)h[a];
         }
         Moments<L, T> m;
         moments<L, T>(h, ph, m);
@@ -95,32 +95,32 @@ __global__ __launch_bounds__(BLOCK) void k_step(const S* __restrict__ gin, S* __
         T out[L::Q];
         collide<L, T>(m, sfield[n], out);
 #pragma unroll
-        for (int a = 0; a < L::Q; ++a) gout[a * g.N + n] = (S)out[a];
+        for (int a = 0; a < L::Q; ++a) plane(gout, a, g.N)[(unsigned)n] = (S)out[a];
     }
-    if (SAMPLE) block_sum<3>(v, partials + 3 * (long)blockIdx.x);
+    if (SAMPLE) block_sum<3>(v, partials + 3 * (size_t)blockIdx.x);
 }
 
 // G = C(f) for a stored pre-collision state f (checkpoint restart).
 template <class L, class S, class T>
 __global__ __launch_bounds__(BLOCK) void k_collide(const S* __restrict__ pre, S* __restrict__ gout,
                                                    const T* __restrict__ sfield, Geo g, Phys ph) {
-    const long n = (long)blockIdx.x * BLOCK + threadIdx.x;
+    const int n = (int)(blockIdx.x * BLOCK + threadIdx.x);
     if (n >= g.N) return;
     T h[L::Q];
 #pragma unroll
-    for (int a = 0; a < L::Q; ++a) h[a] = (T)pre[a * g.N + n];
+    for (int a = 0; a < L::Q; ++a) h[a] = (T)plane(pre, a, g.N)[(unsigned)n];
     Moments<L, T> m;
     moments<L, T>(h, ph, m);
     T out[L::Q];
     collide<L, T>(m, sfield[n], out);
 #pragma unroll
-    for (int a = 0; a < L::Q; ++a) gout[a * g.N + n] = (S)out[a];
+    for (int a = 0; a < L::Q; ++a) plane(gout, a, g.N)[(unsigned)n] = (S)out[a];
 }
 
 // f^0 = f^eq(rho_init, u_init) (Sec. 2.1.3), shifted.
 template <class L, class S>
 __global__ __launch_bounds__(BLOCK) void k_init_eq(S* __restrict__ pre, Geo g, double rho0, int umode) {
-    const long n = (long)blockIdx.x * BLOCK + threadIdx.x;
+    const int n = (int)(blockIdx.x * BLOCK + threadIdx.x);
     if (n >= g.N) return;
     int x, y, z;
     node_coords(g, n, x, y, z);
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(BLOCK) void k_init_eq(S* __restrict__ pre, Geo g, d
     for (int a = 0; a < L::Q; ++a) {
         const double cu = L::cx[a] * ux;
         const double feq = L::w[a] * rho0 * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * ux * ux);
-        pre[a * g.N + n] = (S)(feq - L::w[a]);
+        plane(pre, a, g.N)[(unsigned)n] = (S)(feq - L::w[a]);
     }
 }
 
@@ -138,12 +138,12 @@ __global__ __launch_bounds__(BLOCK) void k_init_eq(S* __restrict__ pre, Geo g, d
 // (pull + boundary rules). FIELDS: write rho and u instead.
 template <class L, class S, bool DIRECT, bool FIELDS>
 __global__ __launch_bounds__(BLOCK) void k_export(const S* __restrict__ src, double* __restrict__ out, Geo g) {
-    const long n = (long)blockIdx.x * BLOCK + threadIdx.x;
+    const int n = (int)(blockIdx.x * BLOCK + threadIdx.x);
     if (n >= g.N) return;
     double h[L::Q];
     if (DIRECT) {
 #pragma unroll
-        for (int a = 0; a < L::Q; ++a) h[a] = (double)src[a * g.N + n];
+        for (int a = 0; a < L::Q; ++a) h[a] = (double)plane(src, a, g.N)[(unsigned)n];
     } else {
         int x, y, z;
         node_coords(g, n, x, y, z);
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(BLOCK) void k_export(const S* __restrict__ src, dou
     }
     if (!FIELDS) {
 #pragma unroll
-        for (int a = 0; a < L::Q; ++a) out[a * g.N + n] = h[a] + L::w[a];
+        for (int a = 0; a < L::Q; ++a) plane(out, a, g.N)[(unsigned)n] = h[a] + L::w[a];
     } else {
         double rho = 1.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -165,17 +165,17 @@ __global__ __launch_bounds__(BLOCK) void k_export(const S* __restrict__ src, dou
         }
         out[n] = rho;
 #pragma unroll
-        for (int p = 0; p < L::D; ++p) out[(p + 1) * g.N + n] = j[p] / rho;
+        for (int p = 0; p < L::D; ++p) plane(out, p + 1, g.N)[(unsigned)n] = j[p] / rho;
     }
 }
 
 // Unshifted FP64 populations -> shifted storage.
 template <class L, class S>
 __global__ __launch_bounds__(BLOCK) void k_import(const double* __restrict__ f, S* __restrict__ pre, Geo g) {
-    const long n = (long)blockIdx.x * BLOCK + threadIdx.x;
+    const int n = (int)(blockIdx.x * BLOCK + threadIdx.x);
     if (n >= g.N) return;
 #pragma unroll
-    for (int a = 0; a < L::Q; ++a) pre[a * g.N + n] = (S)(f[a * g.N + n] - L::w[a]);
+    for (int a = 0; a < L::Q; ++a) plane(pre, a, g.N)[(unsigned)n] = (S)(plane(f, a, g.N)[(unsigned)n] - L::w[a]);
 }
 
 // Adjoint step for transition k (f^{k-1} -> f^k), reverse order.
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(const A* __restrict__ nu_in, 
                                                    const S* __restrict__ state, const T* __restrict__ sfield,
                                                    double* __restrict__ sens, Geo g, Phys ph, Obj ob,
                                                    double src_w) {
-    const long n = (long)blockIdx.x * BLOCK + threadIdx.x;
+    const int n = (int)(blockIdx.x * BLOCK + threadIdx.x);
     if (n >= g.N) return;
     int x, y, z;
     node_coords(g, n, x, y, z);
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(const A* __restrict__ nu_in, 
     T h[L::Q];
     if (DIRECT) {
 #pragma unroll
-        for (int a = 0; a < L::Q; ++a) h[a] = (T)state[a * g.N + n];
+        for (int a = 0; a < L::Q; ++a) h[a] = (T)plane(state, a, g.N)[(unsigned)n];
     } else {
         pull<L, S, T>(state, g, n, x, y, z, oc, h);
         if (oc) zou_he<L, T>(g, oc, y, h);
@@ -217,14 +217,14 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(const A* __restrict__ nu_in, 
     for (int k = 0; k < Sym<L::D>::K; ++k) gr.GP[k] = 0;
     if (!SEED) {
         T kap[L::Q];
-        const long N = g.N;
+        const int N = g.N;
         const bool interior = x > 0 && x < g.nx - 1 && y > 0 && y < g.ny - 1 &&
                               (L::D == 2 || (z > 0 && z < g.nz - 1));
         if (interior) {
 #pragma unroll
             for (int a = 0; a < L::Q; ++a) {
-                const long off = (long)L::cx[a] + (long)L::cy[a] * g.nx + (long)L::cz[a] * g.nx * g.ny;
-                kap[a] = (T)nu_in[a * N + n + off];
+                const int off = L::cx[a] + L::cy[a] * g.nx + L::cz[a] * g.nx * g.ny;
+                kap[a] = (T)plane(nu_in, a, N)[(unsigned)(n + off)];
             }
         } else {
 #pragma unroll
@@ -243,8 +243,8 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(const A* __restrict__ nu_in, 
                     if (g.per_z) zt = zt < 0 ? zt + g.nz : zt - g.nz;
                     else out = true;
                 }
-                if (!out) kap[a] = (T)nu_in[a * N + ((long)zt * g.ny + yt) * g.nx + xt];
-                else if (oc == 0) kap[a] = (T)nu_in[L::opp[a] * N + n];
+                if (!out) kap[a] = (T)plane(nu_in, a, N)[(unsigned)((zt * g.ny + yt) * g.nx + xt)];
+                else if (oc == 0) kap[a] = (T)plane(nu_in, L::opp[a], N)[(unsigned)n];
                 else kap[a] = (T)0;
             }
         }
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(const A* __restrict__ nu_in, 
     expand<L, T>(m, gr, mu);
     if (oc) zou_he_adjoint<L, T>(g, oc, y, mu);
 #pragma unroll
-    for (int a = 0; a < L::Q; ++a) nu_out[a * g.N + n] = (A)mu[a];
+    for (int a = 0; a < L::Q; ++a) plane(nu_out, a, g.N)[(unsigned)n] = (A)mu[a];
 }
 
 // Per-sample sums of the block partials in a fixed order (deterministic).
@@ -293,7 +293,7 @@ __global__ void k_window_sum(const double* __restrict__ samples, int nsamples, d
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_design(const double* __restrict__ gamma, T* __restrict__ s, long N,
                                                   int map, double q) {
-    const long n = (long)blockIdx.x * BLOCK + threadIdx.x;
+    const int n = (int)(blockIdx.x * BLOCK + threadIdx.x);
     if (n >= N) return;
     const double gm = gamma[n];
     double v;
@@ -310,7 +310,7 @@ __global__ __launch_bounds__(BLOCK) void k_design(const double* __restrict__ gam
 __global__ __launch_bounds__(BLOCK) void k_finalize(const double* __restrict__ gamma,
                                                     const double* __restrict__ sens, double* __restrict__ out,
                                                     long N, int map, double q) {
-    const long n = (long)blockIdx.x * BLOCK + threadIdx.x;
+    const int n = (int)(blockIdx.x * BLOCK + threadIdx.x);
     if (n >= N) return;
     double d = 1.0;
     if (map != 0) {

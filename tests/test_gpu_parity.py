@@ -113,57 +113,247 @@ def test_small_window_reduced(Solver, prec, tol_f, tol_g):
 
 
 # --------------------------------------------------------- cylinder channel
+#
+# The cylinder channel (160 x 64, Re 100, tau = 0.524) amplifies round-off
+# at the pressure outlet: a 1e-10 perturbation grows to 1.5e-8 of the field
+# norm by step 2000 in the oracle itself, and the FP64 oracle differs from
+# the same algorithm in extended precision by ~1e-11 after 1000 steps. So
+# the fields are compared from t = 0 where two FP64 programs can agree
+# (step 300), and at step 1000 against the extended-precision solution;
+# window statistics and dJ/dgamma are compared from a shared window-start
+# state (the GPU's FP64 state entering each window, handed to the oracle).
 
 @pytest.fixture(scope="module")
-def c1_oracle():
-    """Cylinder channel 160 x 64, Re 100, C_s = 0.1: oracle states after 1000
-    and 1500 steps, window means of windows 1-4 (|W| = 500, dW = 1) and the
-    adjoint over window 4."""
+def c1():
     w = W.cylinder_channel()
     prob = oracle_problem(w)
-    res = fw.run(prob, w.gamma, 2000, keep=(1000, 1500))
-    J4, g4, _ = ad.window_gradient(prob, w.gamma, res["states"][1500])
-    return dict(w=w, f1000=res["states"][1000], J=res["J"], M=res["M"], J4=J4, g4=g4)
+    res = fw.run(prob, w.gamma, 1000, keep=(300, 1000))
+    s_ld = fw.design_map(prob, w.gamma).astype(np.longdouble)
+    f_ld = fw.initial_state(prob).astype(np.longdouble)
+    for _ in range(1000):
+        f_ld = fw.step(prob, f_ld, s_ld)
+    drift = rel_l2(res["states"][1000], f_ld.astype(np.float64))
+    return dict(w=w, prob=prob, f300=res["states"][300], f1000=res["states"][1000],
+                f1000_ld=f_ld.astype(np.float64), drift1000=drift)
 
 
-def test_c1_fp64(Solver, c1_oracle):
-    w = c1_oracle["w"]
+@pytest.fixture(scope="module")
+def c1_gpu64(Solver, c1):
+    """GPU FP64 run over 4 windows: states entering each window, window
+    means, and the adjoint of window 4."""
+    w = c1["w"]
     sv = Solver(w, "f64")
-    sv.forward(1000)
-    f, step = sv.get_state()
-    assert step == 1000
-    assert rel_l2(f, c1_oracle["f1000"]) <= 1e-12
-    rep = sv.forward(1000)
-    assert rep["windows_done"] == 4
-    J, M, _ = sv.history()
-    assert rel_l2(J, c1_oracle["J"]) <= 1e-12
-    assert rel_l2(M, c1_oracle["M"]) <= 1e-12
-    g, Jw = sv.adjoint()
-    assert abs(Jw - c1_oracle["J4"]) <= 1e-12 * abs(c1_oracle["J4"])
-    assert rel_l2(g.cpu().numpy(), c1_oracle["g4"]) <= 1e-10
+    out = {"starts": {}}
+    sv.forward(300)
+    out["f300"], _ = sv.get_state()
+    sv.forward(200)
+    for k in range(3):
+        f, step = sv.get_state()
+        out["starts"][step] = f
+        if step == 1000:
+            out["f1000"] = f
+        sv.forward(500)
+    assert sv.get_state()[1] == 2000
+    out["J"], out["M"], _ = sv.history()
+    out["g4"], out["J4"] = sv.adjoint()
+    out["g4"] = out["g4"].cpu().numpy()
+    sv.close()
+    return out
+
+
+def test_c1_fp64_fields(c1, c1_gpu64):
+    e300 = rel_l2(c1_gpu64["f300"], c1["f300"])
+    e1000 = rel_l2(c1_gpu64["f1000"], c1["f1000"])
+    e1000_ld = rel_l2(c1_gpu64["f1000"], c1["f1000_ld"])
+    print(f"C1 FP64 fields: step 300 {e300:.2e}; step 1000 vs oracle {e1000:.2e}, vs extended "
+          f"precision {e1000_ld:.2e} (FP64 oracle vs extended {c1['drift1000']:.2e})")
+    assert e300 <= 1e-12
+    assert e1000_ld <= max(1e-12, 3 * c1["drift1000"])
+
+
+@pytest.fixture(scope="module")
+def c1_window4(c1, c1_gpu64):
+    """Oracle window objectives of windows 2-4 from the GPU's FP64
+    window-start states and the oracle adjoint of window 4 from the state at
+    step 1500."""
+    prob = c1["prob"]
+    w = c1["w"]
+    J, M = [], []
+    s = fw.design_map(prob, w.gamma)
+    for step in sorted(c1_gpu64["starts"]):
+        f = c1_gpu64["starts"][step]
+        jacc = 0.0
+        for m in range(1, 501):
+            f = fw.step(prob, f, s)
+            jacc += fw.sample(prob, f, "dp") / 500
+        J.append(jacc)
+    J4, g4, _ = ad.window_gradient(prob, w.gamma, c1_gpu64["starts"][1500])
+    return dict(J=np.array(J), J4=J4, g4=g4)
+
+
+def test_c1_fp64_windows_and_adjoint(c1_gpu64, c1_window4):
+    assert len(c1_gpu64["J"]) == 4
+    eJ = np.abs(c1_gpu64["J"][1:] - c1_window4["J"]) / np.abs(c1_window4["J"])
+    eJ4 = abs(c1_gpu64["J4"] - c1_window4["J4"]) / abs(c1_window4["J4"])
+    eg = rel_l2(c1_gpu64["g4"], c1_window4["g4"])
+    print(f"C1 FP64 from shared window starts: window means {eJ.max():.2e}; J4 {eJ4:.2e}; dJ/dgamma {eg:.2e}")
+    assert eJ.max() <= 1e-11
+    assert eJ4 <= 1e-11
+    assert eg <= 1e-10
+
+
+@pytest.mark.parametrize("prec,tol_J,tol_g", [("f32", 1e-3, 1e-4), ("f16s", 1e-1, 1e-2)])
+def test_c1_reduced_precision(Solver, c1, c1_gpu64, c1_window4, prec, tol_J, tol_g):
+    """FP32 / FP16-shifted storage: laminar fields from t = 0 (step 300), and
+    J and dJ/dgamma of window 4 from the shared FP64 window-start state."""
+    w = c1["w"]
+    sv = Solver(w, prec)
+    sv.forward(300)
+    f300, _ = sv.get_state()
+    sv.set_state(c1_gpu64["starts"][1500], 1500)
+    sv.forward(500)
+    g, J = sv.adjoint()
+    e300 = rel_l2(f300, c1["f300"])
+    eJ = abs(J - c1_window4["J4"]) / abs(c1_window4["J4"])
+    eg = rel_l2(g.cpu().numpy(), c1_window4["g4"])
+    print(f"C1 {prec}: fields@300 {e300:.2e}; J4 {eJ:.2e}; dJ/dgamma {eg:.2e}")
+    assert e300 <= (1e-5 if prec == "f32" else 1e-2)
+    assert eJ <= tol_J
+    assert eg <= tol_g
     sv.close()
 
 
-def test_c1_fp32(Solver, c1_oracle):
-    w = c1_oracle["w"]
+# ------------------------------------------------------------------ D3Q19
+
+def _small_3d():
+    w = W.cylinder_3d(nx=21, ny=11, nz=6, radius=3, center=(6, 5), window_len=8, sample_every=2,
+                      ckpt_every=4, n_windows=1)
+    w.gamma = np.clip(w.gamma + 0.2 * W.random_design(w.shape, 9), 0, 1)
+    return w
+
+
+@pytest.mark.parametrize("objective", ["dp", "diss_dp"])
+def test_small_window_d3q19_fp64(Solver, objective):
+    """D3Q19 channel (walls in y, periodic z, Zou-He on x faces): J and
+    dJ/dgamma against the oracle from a shared random start state."""
+    w = _small_3d()
+    w.objective = w.monitor = objective
+    prob = oracle_problem(w)
+    f0 = random_start_state(prob, seed=21)
+    J_o, g_o, _ = ad.window_gradient(prob, w.gamma, f0)
+    sv = Solver(w, "f64")
+    sv.set_state(f0, 0)
+    sv.forward(w.window_len)
+    res = f0
+    s = fw.design_map(prob, w.gamma)
+    for _ in range(w.window_len):
+        res = fw.step(prob, res, s)
+    f_gpu, _ = sv.get_state()
+    assert rel_l2(f_gpu, res) <= 1e-12
+    g, J = sv.adjoint()
+    assert abs(J - J_o) <= 1e-12 * abs(J_o)
+    assert rel_l2(g.cpu().numpy(), g_o) <= 1e-11
+    sv.close()
+
+
+def test_small_window_d3q19_fp32(Solver):
+    w = _small_3d()
+    prob = oracle_problem(w)
+    f0 = random_start_state(prob, seed=22)
+    J_o, g_o, _ = ad.window_gradient(prob, w.gamma, f0)
     sv = Solver(w, "f32")
-    sv.forward(1000)
-    f, _ = sv.get_state()
-    assert rel_l2(f, c1_oracle["f1000"]) <= 1e-5
-    sv.forward(1000)
-    g, Jw = sv.adjoint()
-    assert abs(Jw - c1_oracle["J4"]) <= 1e-3 * abs(c1_oracle["J4"])
-    assert rel_l2(g.cpu().numpy(), c1_oracle["g4"]) <= 1e-4
+    sv.set_state(f0, 0)
+    sv.forward(w.window_len)
+    g, J = sv.adjoint()
+    assert abs(J - J_o) <= 1e-5 * abs(J_o)
+    assert rel_l2(g.cpu().numpy(), g_o) <= 1e-4
     sv.close()
 
 
-def test_c1_fp16s(Solver, c1_oracle):
-    w = c1_oracle["w"]
-    sv = Solver(w, "f16s")
-    sv.forward(2000)
-    g, Jw = sv.adjoint()
-    err_J = abs(Jw - c1_oracle["J4"]) / abs(c1_oracle["J4"])
-    err_g = rel_l2(g.cpu().numpy(), c1_oracle["g4"])
-    print(f"FP16S cylinder channel: J rel err {err_J:.3e}, dJ/dgamma rel-L2 {err_g:.3e}")
-    assert err_g <= 1e-2
+# ------------------------------------------------- replay, FD and autograd
+
+def test_replay_matches_forward_and_fd(Solver):
+    """lbm_window_replay with the unchanged design reproduces the window
+    objective (to FMA-contraction differences between kernels); central finite differences of the replay (FP64,
+    h = 1e-4) match the adjoint on seed-chosen entries."""
+    w = W.cylinder_channel(nx=96, ny=32, radius=5, center=(24, 16), window_len=40, sample_every=2,
+                           ckpt_every=10, n_windows=2)
+    sv = Solver(w, "f64")
+    rep = sv.forward(2 * w.window_len)
+    J_fwd = rep["J_eff"]
+    assert abs(sv.replay(w.gamma) - J_fwd) <= 1e-14 * abs(J_fwd)
+    g, J = sv.adjoint()
+    g = g.cpu().numpy()
+    rng = np.random.default_rng(0)
+    cand = np.argwhere((w.gamma > 0) & (w.gamma < 1))
+    pick = cand[rng.choice(len(cand), 8, replace=False)]
+    h = 1e-4
+    for ix, iy in pick:
+        gp = w.gamma.copy()
+        gm = w.gamma.copy()
+        gp[ix, iy] += h
+        gm[ix, iy] -= h
+        fd = (sv.replay(gp) - sv.replay(gm)) / (2 * h)
+        assert abs(fd - g[ix, iy]) <= 1e-5 * abs(g[ix, iy]) + 1e-12
+    # the forward state was not disturbed by the replays
+    rep2 = sv.forward(w.window_len)
+    assert rep2["windows_done"] == 3
+    sv.close()
+
+
+def test_autograd_windowed_objective(Solver):
+    """WindowedJ: the backward of gamma -> J is the adjoint gradient of the
+    representative window (here the criterion never passes, so W_eff is the
+    last of max_windows windows)."""
+    import torch
+    from paper_2608_19617_amd.autograd import windowed_objective
+    w = W.cylinder_channel(nx=64, ny=24, radius=4, center=(16, 12), window_len=30, sample_every=3,
+                           ckpt_every=10, n_windows=2)
+    sv = Solver(w, "f64")
+    gamma = torch.tensor(w.gamma, dtype=torch.float64, device="cuda", requires_grad=True)
+    J = windowed_objective(gamma, sv, 10 * w.window_len)
+    J.backward()
+    sv2 = Solver(w, "f64")
+    sv2.forward(2 * w.window_len)
+    g_ref, J_ref = sv2.adjoint()
+    assert float(J) == J_ref
+    assert torch.equal(gamma.grad, g_ref)
+    sv.close()
+    sv2.close()
+
+
+def test_error_states(Solver):
+    """Calls in the wrong state report LBM_E_STATE without touching the GPU state."""
+    from paper_2608_19617_amd.binding import LbmError
+    w = W.cylinder_channel(nx=40, ny=16, radius=3, center=(10, 8), window_len=10, ckpt_every=5,
+                           n_windows=1)
+    sv = Solver(w, "f32")
+    with pytest.raises(LbmError, match="LBM_E_STATE"):
+        sv.adjoint()
+    with pytest.raises(LbmError, match="LBM_E_STATE"):
+        sv.replay(w.gamma)
+    with pytest.raises(LbmError, match="LBM_E_INVALID"):
+        sv.set_state(np.zeros((9,) + w.shape), 3)
+    sv.forward(15)
+    with pytest.raises(LbmError, match="LBM_E_STATE"):
+        sv.adjoint(window=2)
+    g, J = sv.adjoint(window=1)
+    assert np.isfinite(g.cpu().numpy()).all()
+    sv.close()
+
+
+def test_unstable_run_is_reported(Solver):
+    """A run that blows up (tau near 1/2, no LES, large inlet speed) reports
+    LBM_E_UNSTABLE at the window end; further forward calls need a reset."""
+    from paper_2608_19617_amd.binding import LbmError
+    w = W.cylinder_channel(nx=64, ny=24, radius=4, center=(16, 12), window_len=50, ckpt_every=10,
+                           n_windows=4, c_smag=0.0)
+    w.tau = 0.5001
+    w.u_in = w.u_in * 0.45 / w.u_in.max()
+    sv = Solver(w, "f32")
+    with pytest.raises(LbmError, match="LBM_E_UNSTABLE"):
+        sv.forward(2000)
+    with pytest.raises(LbmError, match="LBM_E_STATE"):
+        sv.forward(1)
+    sv.reset()
     sv.close()
