@@ -191,11 +191,28 @@ lbm_status lbm_get_fields(lbm_ctx* ctx, double* rho_u_dev);
 /* HIP-event timing of the hot kernels: one event pair brackets each run of
  * back-to-back launches of the forward step kernel, of the adjoint step
  * kernel and of the recompute step launches. enable = 1 starts it (and
- * clears the counters), 0 stops it. If out is not NULL it receives 6
- * doubles: launches and total milliseconds of each of the three classes,
+ * clears the counters), 0 stops it. If out is not NULL it receives
+ * launches and total milliseconds of each class,
  * so ms / launches is the average launch duration including the dispatch
- * gaps between consecutive launches. */
+ * gaps between consecutive launches. A fourth pair counts the temporally
+ * blocked forward launches, and a ninth double the steps they advanced
+ * (9 doubles in all). */
 lbm_status lbm_timing(lbm_ctx* ctx, int enable, double* out);
+
+/* Temporal blocking of forward launches (D2Q9 only): each launch advances
+ * nsteps steps on output tiles of tile_x x tile_y nodes, keeping the
+ * intermediate populations of each tile and its halo in LDS. nsteps = 1
+ * turns it off. Samples, checkpoints and window ends always fall on the last
+ * step of a launch, so results are those of single steps up to the
+ * contraction of multiply-adds. Requires tile_x * tile_y >= 256 and
+ * 2 * 9 * (tile_x + 2(nsteps-1)) * (tile_y + 2(nsteps-1)) values of compute
+ * precision within 159 KB. A launch never runs past the next sample,
+ * checkpoint or window end, so shorter blocked launches occur. Defaults
+ * after lbm_init (measured on MI355X): grids of at most 400k nodes 5 steps
+ * (FP32, FP16S) or 4 steps (FP64) on 25 x 25 tiles; larger grids 4 steps on
+ * 16 x 16 (FP32), 2 steps on 24 x 16 (FP64), single steps (FP16S). Recompute
+ * steps of the adjoint are single steps. */
+lbm_status lbm_set_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y);
 
 /* Thread-local message of the last failing call on this thread. */
 const char* lbm_last_error(void);

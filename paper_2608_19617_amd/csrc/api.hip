@@ -41,6 +41,7 @@ struct Layout {
     int R;                     // checkpoint slots per window
     int nseg;                  // recompute slots
     long nblocks;
+    long pstride;
     int nsamp;                 // samples per window
     size_t off_G, off_ring, off_seg, off_s, off_srep, off_gamma, off_nu, off_sens, off_part, off_samples,
         off_acc, off_roww, off_rowe, off_uin, total;
@@ -109,6 +110,7 @@ void layout(const lbm_config* c, Layout& L) {
     L.R = c->window_len / c->ckpt_every;
     L.nseg = c->ckpt_every < 2 ? 2 : c->ckpt_every;
     L.nblocks = blocks_for(L.N);
+    L.pstride = 2 * L.nblocks + 64;      // partial slots per sample, for any launch grid
     L.nsamp = c->window_len / c->sample_every;
     size_t o = 0;
     L.off_G = o;       o += 2 * L.SB;
@@ -119,7 +121,7 @@ void layout(const lbm_config* c, Layout& L) {
     L.off_gamma = o;   o += align_up(L.N * 8);
     L.off_nu = o;      o += 2 * align_up((size_t)L.Q * L.N * L.as);   // >= Q N 8: FP64 staging
     L.off_sens = o;    o += align_up(L.N * 8);
-    L.off_part = o;    o += 2 * align_up((size_t)L.nsamp * L.nblocks * 3 * 8);
+    L.off_part = o;    o += 2 * align_up((size_t)L.nsamp * L.pstride * 3 * 8);
     L.off_samples = o; o += align_up((size_t)L.nsamp * 3 * 8);
     L.off_acc = o;     o += align_up(8 * 8);
     L.off_roww = o;    o += align_up(c->ny);
@@ -137,9 +139,10 @@ struct Timer {
     std::vector<hipEvent_t> ev;      // pool of start/stop pairs
     std::vector<int> cls;            // class of each closed or open run
     std::vector<long> cnt;           // launches in each run
+    std::vector<long> steps;         // steps in each run
     int used = 0;                    // runs in the pool
     int open = -1;                   // class of the open run, -1 if none
-    double n[3] = {0, 0, 0}, ms[3] = {0, 0, 0};
+    double n[4] = {0, 0, 0, 0}, ms[4] = {0, 0, 0, 0}, st[4] = {0, 0, 0, 0};
 };
 
 }  // namespace
@@ -165,6 +168,7 @@ struct lbm_ctx {
     std::vector<double> J, M, rel;
     std::vector<int> conv;
     bool unstable;
+    int tb_steps, tile_x, tile_y;    // temporal blocking of forward launches (1 = off)
     Timer tm;
 };
 
@@ -189,18 +193,20 @@ lbm_status t_drain(lbm_ctx* c) {
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, c->tm.ev[2 * i], c->tm.ev[2 * i + 1]));
         c->tm.n[c->tm.cls[i]] += (double)c->tm.cnt[i];
+        c->tm.st[c->tm.cls[i]] += (double)c->tm.steps[i];
         c->tm.ms[c->tm.cls[i]] += ms;
     }
     c->tm.used = 0;
     return LBM_OK;
 }
 
-// Called before each hot launch of class cls: extends the open run or
-// starts a new one.
-lbm_status t_launch(lbm_ctx* c, int cls) {
+// Called before each hot launch of class cls (advancing nsteps steps):
+// extends the open run or starts a new one.
+lbm_status t_launch(lbm_ctx* c, int cls, long nsteps = 1) {
     if (!c->tm.on) return LBM_OK;
     if (c->tm.open == cls) {
         c->tm.cnt[c->tm.used - 1] += 1;
+        c->tm.steps[c->tm.used - 1] += nsteps;
         return LBM_OK;
     }
     lbm_status st = t_close(c);
@@ -211,6 +217,7 @@ lbm_status t_launch(lbm_ctx* c, int cls) {
     const int r = c->tm.used++;
     c->tm.cls[r] = cls;
     c->tm.cnt[r] = 1;
+    c->tm.steps[r] = nsteps;
     c->tm.open = cls;
     HIPCHK(hipEventRecord(c->tm.ev[2 * r], c->stream));
     return LBM_OK;
@@ -227,6 +234,10 @@ StepLaunch step_args(lbm_ctx* c) {
     a.pre = nullptr;
     a.sample = 0;
     a.partials = nullptr;
+    a.part_stride = (int)c->L.pstride;
+    a.nsteps = 1;
+    a.tile_x = c->tile_x;
+    a.tile_y = c->tile_y;
     return a;
 }
 
@@ -304,7 +315,7 @@ lbm_status do_reset(lbm_ctx* c) {
 lbm_status window_end(lbm_ctx* c, double* accbuf, double* part, double out[3]) {
     const Layout& L = c->L;
     const double wgt = (double)c->cfg.sample_every / c->cfg.window_len;
-    HIPCHK(launch_reduce(part, L.nblocks, L.nsamp, c->samples, wgt, accbuf, c->stream));
+    HIPCHK(launch_reduce(part, L.pstride, L.nsamp, c->samples, wgt, accbuf, c->stream));
     HIPCHK(hipMemcpyAsync(out, accbuf, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return LBM_OK;
@@ -322,15 +333,65 @@ void criterion(double prev, double cur, double eps, double& rel, int& conv) {
     conv = (eps >= 0.0 && rel < eps) ? 1 : 0;
 }
 
+long gcd_l(long a, long b) {
+    while (b) {
+        const long t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// Steps of the next forward launch from `step`: a temporally blocked launch
+// of up to tb_steps steps that ends no later than the next event step (a
+// multiple of gev: sample, checkpoint or window end), else one step. Events
+// therefore only fall on the last step of a launch. With `reserve`, the
+// step that ends a window (a multiple of W) or the budget is always a
+// single-step launch, so that the buffer not holding G^k holds G^{k-1},
+// from which the post-boundary state f^k is exported.
+long plan_launch(lbm_ctx* c, long step, long gev, long W, long budget, bool reserve) {
+    const long nt = c->tb_steps;
+    if (nt <= 1 || budget <= 1) return 1;
+    long lim = gev - (step % gev);
+    if (lim > budget) lim = budget;
+    if (reserve && (lim == budget || (step + lim) % W == 0)) lim -= 1;
+    const long n = lim < nt ? lim : nt;
+    return n >= 2 ? n : 1;
+}
+
 long last_window(lbm_ctx* c) {
     const long W = c->cfg.window_len;
     const long g = c->step / W;
     return g > c->base / W ? g : 0;
 }
 
+lbm_status set_blocking(lbm_ctx* c, int nsteps, int tile_x, int tile_y) {
+    if (nsteps < 1 || nsteps > 16) return fail(LBM_E_INVALID, "nsteps must be in [1, 16]");
+    if (nsteps > 1 && c->cfg.lattice != LBM_D2Q9) return fail(LBM_E_INVALID, "temporal blocking is D2Q9 only");
+    if (nsteps > 1) {
+        if (tile_x < 1 || tile_y < 1 || (long)tile_x * tile_y < 256)
+            return fail(LBM_E_INVALID, "tile must hold at least 256 nodes");
+        const size_t lds = tb_lds_bytes(nsteps, tile_x, tile_y, c->L.cs);
+        if (lds > 159 * 1024) return fail(LBM_E_INVALID, "tile and nsteps need more than 159 KB of LDS");
+        if (tb_blocks(c->cfg.nx, c->cfg.ny, tile_x, tile_y) > c->L.pstride)
+            return fail(LBM_E_INVALID, "too many tiles");
+        HIPCHK(tb_prepare(c->cfg.prec, lds));
+        c->tile_x = tile_x;
+        c->tile_y = tile_y;
+    }
+    c->tb_steps = nsteps;
+    return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+lbm_status lbm_set_blocking(lbm_ctx* c, int nsteps, int tile_x, int tile_y) {
+    if (!c) return fail(LBM_E_INVALID, "NULL context");
+    return set_blocking(c, nsteps, tile_x, tile_y);
+}
+
 
 lbm_status lbm_workspace_bytes(const lbm_config* cfg, size_t* bytes) {
     lbm_status st = validate(cfg);
@@ -385,7 +446,7 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
     c->nu[0] = at(c, L.off_nu);
     c->nu[1] = at(c, L.off_nu + nub);
     c->sens = (double*)at(c, L.off_sens);
-    const size_t pb = align_up((size_t)L.nsamp * L.nblocks * 3 * 8);
+    const size_t pb = align_up((size_t)L.nsamp * L.pstride * 3 * 8);
     c->partials[0] = (double*)at(c, L.off_part);
     c->partials[1] = (double*)at(c, L.off_part + pb);
     c->samples = (double*)at(c, L.off_samples);
@@ -398,6 +459,8 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
     c->geo.ny = cfg->ny;
     c->geo.nz = cfg->nz;
     c->geo.N = (int)L.N;
+    c->geo.inv_nx = 1.0 / cfg->nx;
+    c->geo.inv_ny = 1.0 / cfg->ny;
     c->geo.per_x = cfg->periodic_x ? 1 : 0;
     c->geo.per_y = cfg->periodic_y ? 1 : 0;
     c->geo.per_z = cfg->periodic_z ? 1 : 0;
@@ -420,6 +483,9 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
     c->step = c->base = 0;
     c->cur = 0;
     c->unstable = false;
+    c->tb_steps = 1;
+    c->tile_x = 32;
+    c->tile_y = 16;
 
     auto bail = [&](lbm_status s2) {
         std::string keep = g_err;
@@ -444,6 +510,28 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
     if ((st = check_gamma(c, c->gamma)) != LBM_OK) return bail(st);
     if ((st = apply_design(c, c->gamma, c->s)) != LBM_OK) return bail(st);
     if ((st = do_reset(c)) != LBM_OK) return bail(st);
+    if (cfg->lattice == LBM_D2Q9) {
+        // default temporal blocking of forward launches, from measurements on
+        // MI355X: latency-bound grids gain most from several steps per launch
+        // on 25 x 25 tiles; on large grids the halo recomputation makes the
+        // blocked kernel ALU-bound and shorter blocks (or none) win.
+        int nt, tx, ty;
+        if (L.N <= 400000) {
+            nt = cfg->prec == LBM_F64 ? 4 : 5;
+            tx = ty = 25;
+        } else if (cfg->prec == LBM_F32) {
+            nt = 4;
+            tx = ty = 16;
+        } else if (cfg->prec == LBM_F64) {
+            nt = 2;
+            tx = 24;
+            ty = 16;
+        } else {
+            nt = 1;
+            tx = ty = 16;
+        }
+        if ((st = set_blocking(c, nt, tx, ty)) != LBM_OK) return bail(st);
+    }
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         fail(LBM_E_HIP, std::string("init: ") + hipGetErrorString(e));
@@ -481,21 +569,26 @@ lbm_status lbm_forward(lbm_ctx* c, long n_steps, int stop_on_converge, lbm_fwd_r
     lbm_status st;
     StepLaunch a = step_args(c);
     a.s = c->s;
-    for (long it = 0; it < n_steps; ++it) {
-        const long m = c->step + 1;
+    const long gev = gcd_l(dW, K);             // samples, checkpoints and window ends fall on multiples
+    long done = 0;
+    while (done < n_steps) {
+        const long n = plan_launch(c, c->step, gev, W, n_steps - done, true);
+        const long m = c->step + n;            // last step of this launch
         const long mw = m % W;
+        a.nsteps = (int)n;
         a.gin = c->G[c->cur];
         a.gout = c->G[c->cur ^ 1];
         a.pre = (m % K == 0) ? ring_slot_for_step(c, m) : nullptr;
         a.sample = (m % dW == 0) ? 1 : 0;
         if (a.sample) {
             const long js = (mw == 0 ? W : mw) / dW - 1;
-            a.partials = c->partials[0] + js * L.nblocks * 3;
+            a.partials = c->partials[0] + js * L.pstride * 3;
         }
-        if ((st = t_launch(c, 0)) != LBM_OK) return st;
+        if ((st = t_launch(c, n > 1 ? 3 : 0, n)) != LBM_OK) return st;
         HIPCHK(launch_step(a));
         c->cur ^= 1;
         c->step = m;
+        done += n;
         if (mw == 0) {
             if ((st = t_close(c)) != LBM_OK) return st;
             double r[3];
@@ -642,13 +735,17 @@ lbm_status lbm_window_replay(lbm_ctx* c, const double* gamma_dev, double* J_out)
     StepLaunch a = step_args(c);
     a.s = c->s_rep;
     int cur = 0;
-    for (long m = 1; m <= W; ++m) {
+    for (long m0 = 0; m0 < W;) {
+        const long n = plan_launch(c, m0, dW, W, W - m0, false);
+        const long m = m0 + n;
+        a.nsteps = (int)n;
         a.gin = c->seg[cur];
         a.gout = c->seg[cur ^ 1];
         a.sample = (m % dW == 0) ? 1 : 0;
-        if (a.sample) a.partials = c->partials[1] + (m / dW - 1) * L.nblocks * 3;
+        if (a.sample) a.partials = c->partials[1] + (m / dW - 1) * L.pstride * 3;
         HIPCHK(launch_step(a));
         cur ^= 1;
+        m0 = m;
     }
     double r[3];
     if ((st = window_end(c, c->acc + 4, c->partials[1], r)) != LBM_OK) return st;
@@ -702,19 +799,21 @@ lbm_status lbm_timing(lbm_ctx* c, int enable, double* out) {
     lbm_status st = t_drain(c);
     if (st != LBM_OK) return st;
     if (out) {
-        for (int i = 0; i < 3; ++i) {
+        for (int i = 0; i < 4; ++i) {
             out[2 * i] = c->tm.n[i];
             out[2 * i + 1] = c->tm.ms[i];
         }
+        out[8] = c->tm.st[3];
     }
     if (enable) {
         if (c->tm.ev.empty()) {
             c->tm.ev.resize(512);
             c->tm.cls.resize(256);
             c->tm.cnt.resize(256);
+            c->tm.steps.resize(256);
             for (auto& e : c->tm.ev) HIPCHK(hipEventCreate(&e));
         }
-        for (int i = 0; i < 3; ++i) c->tm.n[i] = c->tm.ms[i] = 0.0;
+        for (int i = 0; i < 4; ++i) c->tm.n[i] = c->tm.ms[i] = c->tm.st[i] = 0.0;
         c->tm.used = 0;
         c->tm.open = -1;
     }

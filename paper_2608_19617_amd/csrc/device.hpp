@@ -21,6 +21,7 @@ enum RowKind : int { ROW_WALL = 0, ROW_VELOCITY = 1, ROW_PRESSURE = 2 };
 struct Geo {
     int nx, ny, nz;
     int N;                     // nodes (the host keeps Q * N below 2^31)
+    double inv_nx, inv_ny;     // 1/nx, 1/ny for the node-index split
     int per_x, per_y, per_z;   // periodic axes
     const signed char* west;   // per row kind of the x = 0 face
     const signed char* east;   // per row kind of the x = nx-1 face
@@ -42,17 +43,36 @@ struct Obj {
     double inv_nin, inv_nout;  // 1 / section node counts
 };
 
-__device__ __forceinline__ void node_coords(const Geo& g, int n, int& x, int& y, int& z) {
-    const unsigned r = (unsigned)n / (unsigned)g.nx;
-    x = n - (int)r * g.nx;
-    if (g.nz == 1) {
-        y = (int)r;
-        z = 0;
-    } else {
-        z = (int)(r / (unsigned)g.ny);
-        y = (int)r - z * g.ny;
+// q = floor(n / d) through an FP64 product (exact to within one for
+// n < 2^31), corrected once.
+__device__ __forceinline__ void divmod(int n, int d, double inv_d, int& q, int& r) {
+    q = (int)((double)n * inv_d);
+    r = n - q * d;
+    if (r < 0) {
+        q -= 1;
+        r += d;
+    } else if (r >= d) {
+        q += 1;
+        r -= d;
     }
 }
+
+__device__ __forceinline__ void node_coords(const Geo& g, int n, int& x, int& y, int& z) {
+    int r;
+    divmod(n, g.nx, g.inv_nx, r, x);
+    if (g.nz == 1) {
+        y = r;
+        z = 0;
+    } else {
+        divmod(r, g.ny, g.inv_ny, z, y);
+    }
+}
+
+// Reciprocal and square root: hardware 1-ulp instructions in FP32, IEEE in FP64.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
 
 // Base pointer of population plane a (uniform across the wave).
 template <class P>
@@ -233,20 +253,22 @@ struct Sym<3> {
 // (Eq. Pi, with sum c c f^eq = rho c_s^2 I + rho u u).
 template <class L, class T>
 struct Moments {
-    T drho, rho;
+    T drho, rho, irho;
     T j[L::D];
     T Pi[Sym<L::D>::K];
     T PP;       // Pi : Pi (full contraction)
     T norm;     // ||Pi|| = sqrt(2 Pi:Pi)
     T R;        // sqrt(tau^2 + 2 C^2 ||Pi|| / (rho c_s^4))
-    T te;       // tau_eff (Eq. tau_eff)
+    T te, ite;  // tau_eff (Eq. tau_eff) and its reciprocal
 };
 
+// Directions come in opposite pairs (a, opp(a)); sums over a pair of the
+// even (c c) and odd (c) moments share h_a + h_opp and h_a - h_opp.
 template <class L, class T>
 __device__ __forceinline__ void moments(const T h[L::Q], const Phys& ph, Moments<L, T>& m) {
     constexpr int D = L::D;
     using SY = Sym<D>;
-    T drho = 0;
+    T drho = h[0];
     T j[D];
     T M[SY::K];
 #pragma unroll
@@ -254,21 +276,26 @@ __device__ __forceinline__ void moments(const T h[L::Q], const Phys& ph, Moments
 #pragma unroll
     for (int k = 0; k < SY::K; ++k) M[k] = 0;
 #pragma unroll
-    for (int a = 0; a < L::Q; ++a) {
-        drho += h[a];
+    for (int a = 1; a < L::Q; ++a) {
+        if (L::opp[a] < a) continue;
+        const T sp = h[a] + h[L::opp[a]];
+        const T dm = h[a] - h[L::opp[a]];
+        drho += sp;
 #pragma unroll
         for (int p = 0; p < D; ++p) {
             const int cp = comp<L>(a, p);
-            if (cp != 0) j[p] += (T)cp * h[a];
+            if (cp == 1) j[p] += dm;
+            if (cp == -1) j[p] -= dm;
 #pragma unroll
             for (int q = p; q < D; ++q) {
                 const int cc = cp * comp<L>(a, q);
-                if (cc != 0) M[SY::idx[p][q]] += (T)cc * h[a];
+                if (cc == 1) M[SY::idx[p][q]] += sp;
+                if (cc == -1) M[SY::idx[p][q]] -= sp;
             }
         }
     }
     const T rho = (T)1 + drho;
-    const T irho = (T)1 / rho;
+    const T irho = rcp(rho);
     T PP = 0;
 #pragma unroll
     for (int p = 0; p < D; ++p) {
@@ -283,13 +310,15 @@ __device__ __forceinline__ void moments(const T h[L::Q], const Phys& ph, Moments
     }
     m.drho = drho;
     m.rho = rho;
+    m.irho = irho;
 #pragma unroll
     for (int p = 0; p < D; ++p) m.j[p] = j[p];
     m.PP = PP;
-    m.norm = sqrt((T)2 * PP);
+    m.norm = fsqrt((T)2 * PP);
     const T tau = (T)ph.tau;
-    m.R = sqrt(tau * tau + (T)(18.0 * ph.c2) * m.norm * irho);
+    m.R = fsqrt(tau * tau + (T)(18.0 * ph.c2) * m.norm * irho);
     m.te = (T)0.5 * (tau + m.R);
+    m.ite = rcp(m.te);
 }
 
 // Regularized collision (Eq. modified_collision) followed by the partial
@@ -297,36 +326,43 @@ __device__ __forceinline__ void moments(const T h[L::Q], const Phys& ph, Moments
 //   f**_a - w_a = w_a [drho + 3(1 - 2s) c.j + 4.5 (c.j)^2/rho - 1.5 j.j/rho]
 //               + 4.5 a w_a (c c - c_s^2 I) : Pi,
 // since f*_opp - f*_a = -6 w_a c_a.j for the regularized post-collision state.
+// The even part is shared by a and opp(a); the odd part changes sign.
 template <class L, class T>
 __device__ __forceinline__ void collide(const Moments<L, T>& m, T s, T out[L::Q]) {
     constexpr int D = L::D;
     using SY = Sym<D>;
-    const T irho = (T)1 / m.rho;
-    const T a = (T)1 - (T)1 / m.te;
+    const T ev = (T)4.5 * ((T)1 - m.ite);
     T jj = 0, tr = 0;
 #pragma unroll
     for (int p = 0; p < D; ++p) {
         jj += m.j[p] * m.j[p];
         tr += m.Pi[SY::idx[p][p]];
     }
-    const T base = m.drho - (T)1.5 * jj * irho;
-    const T odd = (T)3 * ((T)1 - (T)2 * s);
-    const T ev = (T)4.5 * a;
+    const T A = m.drho - (T)1.5 * jj * m.irho - ev * (T)(1.0 / 3.0) * tr;
+    const T B = (T)4.5 * m.irho;
+    const T odd = (T)3 - (T)6 * s;
+    out[0] = (T)L::w[0] * A;
 #pragma unroll
-    for (int al = 0; al < L::Q; ++al) {
+    for (int al = 1; al < L::Q; ++al) {
+        if (L::opp[al] < al) continue;
         T cj = 0, cPc = 0;
 #pragma unroll
         for (int p = 0; p < D; ++p) {
             const int cp = comp<L>(al, p);
-            if (cp != 0) cj += (T)cp * m.j[p];
+            if (cp == 1) cj += m.j[p];
+            if (cp == -1) cj -= m.j[p];
 #pragma unroll
             for (int q = 0; q < D; ++q) {
                 const int cc = cp * comp<L>(al, q);
-                if (cc != 0) cPc += (T)cc * m.Pi[SY::idx[p][q]];
+                if (cc == 1) cPc += m.Pi[SY::idx[p][q]];
+                if (cc == -1) cPc -= m.Pi[SY::idx[p][q]];
             }
         }
         const T wa = (T)L::w[al];
-        out[al] = wa * (base + odd * cj + (T)4.5 * cj * cj * irho + ev * (cPc - (T)(1.0 / 3.0) * tr));
+        const T E = A + B * cj * cj + ev * cPc;
+        const T O = odd * cj;
+        out[al] = wa * (E + O);
+        out[L::opp[al]] = wa * (E - O);
     }
 }
 
@@ -334,7 +370,7 @@ __device__ __forceinline__ void collide(const Moments<L, T>& m, T s, T out[L::Q]
 // (tau_eff - 1/2) Pi:Pi / (2 rho c_s^2 tau_eff^2).
 template <class L, class T>
 __device__ __forceinline__ T dissipation(const Moments<L, T>& m) {
-    return (T)1.5 * (m.te - (T)0.5) * m.PP / (m.rho * m.te * m.te);
+    return (T)1.5 * (m.te - (T)0.5) * m.PP * m.irho * m.ite * m.ite;
 }
 
 // Gradient of a scalar with respect to the node moments (rho, j, Pi), with
@@ -354,11 +390,11 @@ __device__ __forceinline__ void add_tau_grad(const Moments<L, T>& m, const Phys&
     // tau_eff = (tau + R)/2, R^2 = tau^2 + 18 C^2 ||Pi|| / rho
     // d tau_eff / d||Pi|| = 4.5 C^2 / (rho R);  d tau_eff / d rho = -4.5 C^2 ||Pi|| / (rho^2 R)
     if (ph.c2 == 0.0) return;
-    const T k = (T)(4.5 * ph.c2) / (m.rho * m.R);
-    g.gr += -dT * k * m.norm / m.rho;
+    const T k = (T)(4.5 * ph.c2) * m.irho * rcp(m.R);
+    g.gr += -dT * k * m.norm * m.irho;
     if (m.norm > (T)0) {
         // d||Pi|| / dPi = 2 Pi / ||Pi||
-        const T f = dT * k * (T)2 / m.norm;
+        const T f = dT * k * (T)2 * rcp(m.norm);
 #pragma unroll
         for (int k2 = 0; k2 < Sym<L::D>::K; ++k2) g.GP[k2] += f * m.Pi[k2];
     }
@@ -372,7 +408,8 @@ __device__ __forceinline__ T collide_adjoint(const Moments<L, T>& m, const Phys&
                                              const T kappa[L::Q], MomentGrad<L, T>& g) {
     constexpr int D = L::D;
     using SY = Sym<D>;
-    T K0 = 0;
+    // K0 = sum w kappa, K1 = sum w kappa c, K2 = sum w kappa c c (pairwise)
+    T K0 = (T)L::w[0] * kappa[0];
     T K1[D];
     T K2[SY::K];
 #pragma unroll
@@ -380,22 +417,26 @@ __device__ __forceinline__ T collide_adjoint(const Moments<L, T>& m, const Phys&
 #pragma unroll
     for (int k = 0; k < SY::K; ++k) K2[k] = 0;
 #pragma unroll
-    for (int a = 0; a < L::Q; ++a) {
-        const T wk = (T)L::w[a] * kappa[a];
-        K0 += wk;
+    for (int a = 1; a < L::Q; ++a) {
+        if (L::opp[a] < a) continue;
+        const T sp = (T)L::w[a] * (kappa[a] + kappa[L::opp[a]]);
+        const T dm = (T)L::w[a] * (kappa[a] - kappa[L::opp[a]]);
+        K0 += sp;
 #pragma unroll
         for (int p = 0; p < D; ++p) {
             const int cp = comp<L>(a, p);
-            if (cp != 0) K1[p] += (T)cp * wk;
+            if (cp == 1) K1[p] += dm;
+            if (cp == -1) K1[p] -= dm;
 #pragma unroll
             for (int q = p; q < D; ++q) {
                 const int cc = cp * comp<L>(a, q);
-                if (cc != 0) K2[SY::idx[p][q]] += (T)cc * wk;
+                if (cc == 1) K2[SY::idx[p][q]] += sp;
+                if (cc == -1) K2[SY::idx[p][q]] -= sp;
             }
         }
     }
-    const T irho = (T)1 / m.rho;
-    const T a = (T)1 - (T)1 / m.te;
+    const T irho = m.irho;
+    const T a = (T)1 - m.ite;
     // T = K2 - K0/3 I ; P = T : Pi
     T Tt[SY::K];
 #pragma unroll
@@ -421,14 +462,14 @@ __device__ __forceinline__ T collide_adjoint(const Moments<L, T>& m, const Phys&
         K1j += K1[p] * m.j[p];
     }
     g.gr += K0 - ((T)4.5 * jK2j - (T)1.5 * K0 * jj) * irho * irho;
-    const T odd = (T)3 * ((T)1 - (T)2 * s);
+    const T odd = (T)3 - (T)6 * s;
 #pragma unroll
     for (int p = 0; p < D; ++p)
         g.gj[p] += odd * K1[p] + ((T)9 * K2j[p] - (T)3 * K0 * m.j[p]) * irho;
     // direct Pi dependence: 4.5 a T ; through a(tau_eff): 4.5 P / tau_eff^2
 #pragma unroll
     for (int k = 0; k < SY::K; ++k) g.GP[k] += (T)4.5 * a * Tt[k];
-    add_tau_grad<L, T>(m, ph, (T)4.5 * P / (m.te * m.te), g);
+    add_tau_grad<L, T>(m, ph, (T)4.5 * P * m.ite * m.ite, g);
     return (T)-6 * K1j;
 }
 
@@ -437,23 +478,24 @@ template <class L, class T>
 __device__ __forceinline__ void dissipation_adjoint(const Moments<L, T>& m, const Phys& ph, T wgt,
                                                     MomentGrad<L, T>& g) {
     // D = 1.5 (te - 1/2) Z / (rho te^2), Z = Pi:Pi
-    const T te = m.te;
-    const T dZ = wgt * (T)1.5 * (te - (T)0.5) / (m.rho * te * te);
+    const T te = m.te, ite = m.ite;
+    const T dZ = wgt * (T)1.5 * (te - (T)0.5) * m.irho * ite * ite;
 #pragma unroll
     for (int k = 0; k < Sym<L::D>::K; ++k) g.GP[k] += dZ * (T)2 * m.Pi[k];
-    const T D = (T)1.5 * (te - (T)0.5) * m.PP / (m.rho * te * te);
-    g.gr += -wgt * D / m.rho;
-    const T dte = wgt * (T)1.5 * m.PP * ((T)1 - te) / (m.rho * te * te * te);
+    const T D = (T)1.5 * (te - (T)0.5) * m.PP * m.irho * ite * ite;
+    g.gr += -wgt * D * m.irho;
+    const T dte = wgt * (T)1.5 * m.PP * ((T)1 - te) * m.irho * ite * ite * ite;
     add_tau_grad<L, T>(m, ph, dte, g);
 }
 
-// Maps a gradient in (rho, j, Pi) to (rho, j, M) through
-// Pi = M - c_s^2 rho I - j j / rho, then to the populations.
+// Maps a gradient in (rho, j, Pi) to (rho, j, M = sum c c f) through
+// Pi = M - c_s^2 rho I - j j / rho, then to the populations:
+// mu_a = g_rho + g_j . c_a + c_a . G_M . c_a (even part shared by a pair).
 template <class L, class T>
 __device__ __forceinline__ void expand(const Moments<L, T>& m, MomentGrad<L, T>& g, T mu[L::Q]) {
     constexpr int D = L::D;
     using SY = Sym<D>;
-    const T irho = (T)1 / m.rho;
+    const T irho = m.irho;
     T tr = 0, jGj = 0;
     T Gj[D];
 #pragma unroll
@@ -469,20 +511,25 @@ __device__ __forceinline__ void expand(const Moments<L, T>& m, MomentGrad<L, T>&
     T gj[D];
 #pragma unroll
     for (int p = 0; p < D; ++p) gj[p] = g.gj[p] - (T)2 * Gj[p] * irho;
+    mu[0] = gr;
 #pragma unroll
-    for (int a = 0; a < L::Q; ++a) {
-        T v = gr;
+    for (int a = 1; a < L::Q; ++a) {
+        if (L::opp[a] < a) continue;
+        T E = gr, O = 0;
 #pragma unroll
         for (int p = 0; p < D; ++p) {
             const int cp = comp<L>(a, p);
-            if (cp != 0) v += (T)cp * gj[p];
+            if (cp == 1) O += gj[p];
+            if (cp == -1) O -= gj[p];
 #pragma unroll
             for (int q = 0; q < D; ++q) {
                 const int cc = cp * comp<L>(a, q);
-                if (cc != 0) v += (T)cc * g.GP[SY::idx[p][q]];
+                if (cc == 1) E += g.GP[SY::idx[p][q]];
+                if (cc == -1) E -= g.GP[SY::idx[p][q]];
             }
         }
-        mu[a] = v;
+        mu[a] = E + O;
+        mu[L::opp[a]] = E - O;
     }
 }
 

@@ -20,10 +20,11 @@ namespace lbm {
 
 constexpr int BLOCK = 256;
 
-// Block-wide FP64 sum of NC channels; thread 0 writes them to out[0..NC).
-template <int NC>
-__device__ __forceinline__ void block_sum(double v[NC], double* out) {
-    __shared__ double red[NC][BLOCK / 64];
+// Block-wide FP64 sum of NC channels over NT threads; thread 0 writes them
+// to out[0..NC).
+template <int NC, int NT>
+__device__ __forceinline__ void block_sum_n(double v[NC], double* out) {
+    __shared__ double red[NC][NT / 64];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         double x = v[c];
@@ -42,10 +43,15 @@ __device__ __forceinline__ void block_sum(double v[NC], double* out) {
         for (int c = 0; c < NC; ++c) {
             double acc = 0;
 #pragma unroll
-            for (int w = 0; w < BLOCK / 64; ++w) acc += red[c][w];
+            for (int w = 0; w < NT / 64; ++w) acc += red[c][w];
             out[c] = acc;
         }
     }
+}
+
+template <int NC>
+__device__ __forceinline__ void block_sum(double v[NC], double* out) {
+    block_sum_n<NC, BLOCK>(v, out);
 }
 
 // Per-node objective and monitor contributions on the post-boundary state
@@ -64,17 +70,34 @@ __device__ __forceinline__ void node_samples(const Obj& ob, int x, int y, const 
     T uu = 0;
 #pragma unroll
     for (int p = 0; p < L::D; ++p) uu += m.j[p] * m.j[p];
-    uu /= m.rho * m.rho;
+    uu *= m.irho * m.irho;
     v[2] = (uu < (T)0.16) ? 0.0 : 1.0;   // also catches NaN
 }
 
 // Forward step k: G_out = C(BC(S(G_in))). SAMPLE: write the block partials
 // of the sampled quantities of f^k. WPRE: also store f^k (pre-collision,
 // shifted) as a checkpoint.
+// Zeroes the partial slots [gridDim.x, stride) that this launch does not
+// write, so that launches with different grids share one partials layout.
+template <int NT>
+__device__ __forceinline__ void zero_unused_partials_n(double* partials, int stride) {
+    if (blockIdx.x != 0) return;
+    for (int i = (int)gridDim.x + (int)threadIdx.x; i < stride; i += NT) {
+        partials[3 * i + 0] = 0.0;
+        partials[3 * i + 1] = 0.0;
+        partials[3 * i + 2] = 0.0;
+    }
+}
+
+__device__ __forceinline__ void zero_unused_partials(double* partials, int stride) {
+    zero_unused_partials_n<BLOCK>(partials, stride);
+}
+
 template <class L, class S, class T, bool SAMPLE, bool WPRE>
 __global__ __launch_bounds__(BLOCK) void k_step(const S* __restrict__ gin, S* __restrict__ gout,
                                                 S* __restrict__ pre, const T* __restrict__ sfield,
-                                                Geo g, Phys ph, Obj ob, double* __restrict__ partials) {
+                                                Geo g, Phys ph, Obj ob, double* __restrict__ partials,
+                                                int part_stride) {
     const int n = (int)(blockIdx.x * BLOCK + threadIdx.x);
     const bool active = n < g.N;
     double v[3] = {0.0, 0.0, 0.0};
@@ -97,7 +120,109 @@ __global__ __launch_bounds__(BLOCK) void k_step(const S* __restrict__ gin, S* __
 #pragma unroll
         for (int a = 0; a < L::Q; ++a) plane(gout, a, g.N)[(unsigned)n] = (S)out[a];
     }
-    if (SAMPLE) block_sum<3>(v, partials + 3 * (size_t)blockIdx.x);
+    if (SAMPLE) {
+        block_sum<3>(v, partials + 3 * (size_t)blockIdx.x);
+        zero_unused_partials(partials, part_stride);
+    }
+}
+
+// Temporally blocked forward steps (D2Q9): one launch advances NT steps.
+// Each workgroup owns an output tile of ox x oy nodes. Step 1 pulls from
+// the post-collision state in global memory over the tile grown by NT - 1
+// nodes per side and keeps the new post-collision populations in LDS; each
+// further step pulls from LDS over a region one node smaller per side; the
+// last step writes the tile to global memory. Only the last step may be a
+// sampled step (SAMPLE) or a checkpoint step (WPRE). Halo nodes are
+// recomputed by neighbouring tiles; every node update uses the same device
+// functions as the single-step kernel. LDS: two buffers of Q planes of
+// (ox + 2(NT-1)) x (oy + 2(NT-1)) values in compute precision. TB threads
+// (512 or 1024, whichever covers the first region in one round) update the
+// nodes of a region.
+template <class S, class T, bool SAMPLE, bool WPRE, int TB>
+__global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __restrict__ gout,
+                                                S* __restrict__ pre, const T* __restrict__ sfield,
+                                                Geo g, Phys ph, Obj ob, double* __restrict__ partials,
+                                                int part_stride, int nt, int ox, int oy, int tiles_x) {
+    using L = D2Q9;
+    extern __shared__ unsigned char lds_raw[];
+    T* lds = reinterpret_cast<T*>(lds_raw);
+    const int H = nt - 1;
+    const int LW = ox + 2 * H, LH = oy + 2 * H;
+    const int plane_sz = LW * LH;
+    T* buf[2] = {lds, lds + (size_t)L::Q * plane_sz};
+    const int tx = (int)blockIdx.x % tiles_x, ty = (int)blockIdx.x / tiles_x;
+    const int x0 = tx * ox - H, y0 = ty * oy - H;     // global coords of LDS cell (0, 0)
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int t = 1; t <= nt; ++t) {
+        const int m = t - 1;                             // region: LDS cells [m, LW - m) x [m, LH - m)
+        const int rw = LW - 2 * m, rh = LH - 2 * m;
+        const int count = rw * rh;
+        const float inv_rw = 1.0f / (float)rw;
+        T* dst = buf[t & 1];
+        const T* srcb = buf[(t - 1) & 1];
+        const bool last = t == nt;
+        for (int i = (int)threadIdx.x; i < count; i += TB) {
+            int qy = (int)(((float)i + 0.5f) * inv_rw);  // exact: i < 2^12
+            const int ly = m + qy, lx = m + (i - qy * rw);
+            int x = x0 + lx, y = y0 + ly;
+            // the output tile owns only nodes inside the domain (no wrapped duplicates)
+            if (last && (x >= g.nx || y >= g.ny)) continue;
+            if (g.per_x) x = ((x % g.nx) + g.nx) % g.nx;
+            if (g.per_y) y = ((y % g.ny) + g.ny) % g.ny;
+            if (x < 0 || x >= g.nx || y < 0 || y >= g.ny) continue;   // outside the domain
+            const int n = y * g.nx + x;
+            const int oc = open_code<L>(g, x, y, 0);
+            T h[L::Q];
+            if (t == 1) {
+                pull<L, S, T>(gin, g, n, x, y, 0, oc, h);
+            } else {
+                const bool inner = (g.per_x || (x > 0 && x < g.nx - 1)) && (g.per_y || (y > 0 && y < g.ny - 1));
+                const int cell = ly * LW + lx;
+                if (inner) {
+#pragma unroll
+                    for (int a = 0; a < L::Q; ++a) h[a] = srcb[a * plane_sz + cell - L::cy[a] * LW - L::cx[a]];
+                } else {
+#pragma unroll
+                    for (int a = 0; a < L::Q; ++a) {
+                        const int xs = x - L::cx[a], ys = y - L::cy[a];
+                        const bool out = (!g.per_x && (xs < 0 || xs >= g.nx)) || (!g.per_y && (ys < 0 || ys >= g.ny));
+                        if (!out) h[a] = srcb[a * plane_sz + cell - L::cy[a] * LW - L::cx[a]];
+                        else if (oc == 0) h[a] = srcb[L::opp[a] * plane_sz + cell];
+                        else h[a] = (T)0;
+                    }
+                }
+            }
+            if (oc) zou_he<L, T>(g, oc, y, h);
+            if (last && WPRE) {
+#pragma unroll
+                for (int a = 0; a < L::Q; ++a) plane(pre, a, g.N)[(unsigned)n] = (S)h[a];
+            }
+            Moments<L, T> mo;
+            moments<L, T>(h, ph, mo);
+            if (last && SAMPLE) {
+                double vv[3];
+                node_samples<L, T>(ob, x, y, mo, vv);
+                v[0] += vv[0];
+                v[1] += vv[1];
+                v[2] += vv[2];
+            }
+            T out[L::Q];
+            collide<L, T>(mo, sfield[n], out);
+            if (last) {
+#pragma unroll
+                for (int a = 0; a < L::Q; ++a) plane(gout, a, g.N)[(unsigned)n] = (S)out[a];
+            } else {
+                const int cell = ly * LW + lx;
+#pragma unroll
+                for (int a = 0; a < L::Q; ++a) dst[a * plane_sz + cell] = out[a];
+            }
+        }
+        __syncthreads();
+    }
+    if (SAMPLE) {
+        block_sum_n<3, TB>(v, partials + 3 * (size_t)blockIdx.x);
+        zero_unused_partials_n<TB>(partials, part_stride);
+    }
 }
 
 // G = C(f) for a stored pre-collision state f (checkpoint restart).
@@ -335,6 +460,22 @@ __global__ __launch_bounds__(BLOCK) void k_copy_bytes(const unsigned int* __rest
 
 static inline dim3 grid_for(long n) { return dim3((unsigned)((n + BLOCK - 1) / BLOCK)); }
 
+template <class S, class T, bool SAMPLE, bool WPRE>
+static void launch_tb(const StepLaunch& a) {
+    const Geo& g = a.geo;
+    const int tiles_x = (g.nx + a.tile_x - 1) / a.tile_x;
+    const int tiles_y = (g.ny + a.tile_y - 1) / a.tile_y;
+    const size_t lds = tb_lds_bytes(a.nsteps, a.tile_x, a.tile_y, sizeof(T));
+    if (tb_threads(a.nsteps, a.tile_x, a.tile_y) == 512)
+        hipLaunchKernelGGL((k_step_tb<S, T, SAMPLE, WPRE, 512>), dim3(tiles_x * tiles_y), dim3(512), lds, a.stream,
+                           (const S*)a.gin, (S*)a.gout, (S*)a.pre, (const T*)a.s, g, a.ph, a.ob, a.partials,
+                           a.part_stride, a.nsteps, a.tile_x, a.tile_y, tiles_x);
+    else
+        hipLaunchKernelGGL((k_step_tb<S, T, SAMPLE, WPRE, 1024>), dim3(tiles_x * tiles_y), dim3(1024), lds, a.stream,
+                           (const S*)a.gin, (S*)a.gout, (S*)a.pre, (const T*)a.s, g, a.ph, a.ob, a.partials,
+                           a.part_stride, a.nsteps, a.tile_x, a.tile_y, tiles_x);
+}
+
 template <class L, class S, class T>
 static hipError_t step_t(const StepLaunch& a) {
     const Geo& g = a.geo;
@@ -342,13 +483,25 @@ static hipError_t step_t(const StepLaunch& a) {
     S* gout = (S*)a.gout;
     S* pre = (S*)a.pre;
     const T* sf = (const T*)a.s;
+    if (a.nsteps > 1) {
+        if (L::D != 2) return hipErrorInvalidValue;
+        if (a.sample) {
+            if (pre) launch_tb<S, T, true, true>(a);
+            else launch_tb<S, T, true, false>(a);
+        } else {
+            if (pre) launch_tb<S, T, false, true>(a);
+            else launch_tb<S, T, false, false>(a);
+        }
+        return hipGetLastError();
+    }
     dim3 gr = grid_for(g.N);
+    const int ps = a.part_stride;
     if (a.sample) {
-        if (pre) hipLaunchKernelGGL((k_step<L, S, T, true, true>), gr, dim3(BLOCK), 0, a.stream, gin, gout, pre, sf, g, a.ph, a.ob, a.partials);
-        else hipLaunchKernelGGL((k_step<L, S, T, true, false>), gr, dim3(BLOCK), 0, a.stream, gin, gout, pre, sf, g, a.ph, a.ob, a.partials);
+        if (pre) hipLaunchKernelGGL((k_step<L, S, T, true, true>), gr, dim3(BLOCK), 0, a.stream, gin, gout, pre, sf, g, a.ph, a.ob, a.partials, ps);
+        else hipLaunchKernelGGL((k_step<L, S, T, true, false>), gr, dim3(BLOCK), 0, a.stream, gin, gout, pre, sf, g, a.ph, a.ob, a.partials, ps);
     } else {
-        if (pre) hipLaunchKernelGGL((k_step<L, S, T, false, true>), gr, dim3(BLOCK), 0, a.stream, gin, gout, pre, sf, g, a.ph, a.ob, a.partials);
-        else hipLaunchKernelGGL((k_step<L, S, T, false, false>), gr, dim3(BLOCK), 0, a.stream, gin, gout, pre, sf, g, a.ph, a.ob, a.partials);
+        if (pre) hipLaunchKernelGGL((k_step<L, S, T, false, true>), gr, dim3(BLOCK), 0, a.stream, gin, gout, pre, sf, g, a.ph, a.ob, a.partials, ps);
+        else hipLaunchKernelGGL((k_step<L, S, T, false, false>), gr, dim3(BLOCK), 0, a.stream, gin, gout, pre, sf, g, a.ph, a.ob, a.partials, ps);
     }
     return hipGetLastError();
 }
@@ -461,5 +614,45 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t str
 }
 
 long blocks_for(long n) { return (n + BLOCK - 1) / BLOCK; }
+
+size_t tb_lds_bytes(int nsteps, int tile_x, int tile_y, size_t elem) {
+    const size_t lw = tile_x + 2 * (nsteps - 1), lh = tile_y + 2 * (nsteps - 1);
+    return 2 * 9 * lw * lh * elem;
+}
+
+long tb_blocks(int nx, int ny, int tile_x, int tile_y) {
+    return (long)((nx + tile_x - 1) / tile_x) * ((ny + tile_y - 1) / tile_y);
+}
+
+int tb_threads(int nsteps, int tile_x, int tile_y) {
+    const long lw = tile_x + 2 * (nsteps - 1), lh = tile_y + 2 * (nsteps - 1);
+    return lw * lh <= 512 ? 512 : 1024;
+}
+
+template <class S, class T, int NT>
+static hipError_t tb_attr(int b) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_step_tb<S, T, false, false, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, true, false, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, false, true, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, true, true, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    return e;
+}
+
+hipError_t tb_prepare(int prec, size_t lds_bytes) {
+    // opt in to more than 64 KB of dynamic LDS per workgroup
+    const int b = (int)lds_bytes;
+    hipError_t e;
+    if (prec == 0) {
+        e = tb_attr<double, double, 512>(b);
+        if (e == hipSuccess) e = tb_attr<double, double, 1024>(b);
+    } else if (prec == 1) {
+        e = tb_attr<float, float, 512>(b);
+        if (e == hipSuccess) e = tb_attr<float, float, 1024>(b);
+    } else {
+        e = tb_attr<_Float16, float, 512>(b);
+        if (e == hipSuccess) e = tb_attr<_Float16, float, 1024>(b);
+    }
+    return e;
+}
 
 }  // namespace lbm

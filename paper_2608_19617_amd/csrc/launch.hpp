@@ -13,8 +13,11 @@ struct StepLaunch {
     void* gout;            // post-collision state G^k
     void* pre;             // if not null: also store f^k here (checkpoint)
     const void* s;         // bounce-back fraction plane
-    int sample;            // write block partials of the samples of f^k
-    double* partials;      // [blocks][3]
+    int sample;            // write block partials of the samples of f^k (last step)
+    double* partials;      // [part_stride][3]
+    int part_stride;       // partial slots per sample (unused slots are zeroed)
+    int nsteps;            // 1: single step; > 1: temporally blocked launch (D2Q9)
+    int tile_x, tile_y;    // output tile of a blocked launch
     Geo geo;
     Phys ph;
     Obj ob;
@@ -72,5 +75,9 @@ hipError_t launch_finalize(const double* gamma, const double* sens, double* out,
 hipError_t launch_fill(double* p, long n, double v, hipStream_t stream);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
 long blocks_for(long n);
+size_t tb_lds_bytes(int nsteps, int tile_x, int tile_y, size_t elem);
+long tb_blocks(int nx, int ny, int tile_x, int tile_y);
+hipError_t tb_prepare(int prec, size_t lds_bytes);
+int tb_threads(int nsteps, int tile_x, int tile_y);
 
 }  // namespace lbm

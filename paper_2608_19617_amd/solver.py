@@ -101,6 +101,7 @@ class Solver:
         B.check(B.lib.lbm_init(ctypes.byref(cfg), ctypes.c_void_p(g.data_ptr()),
                                ctypes.c_void_p(self._ws_ptr), ctypes.c_size_t(n.value),
                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._ctx)))
+        self.blocking = None      # library default (see lbm_set_blocking)
 
     # ------------------------------------------------------------ helpers
     def _gamma_tensor(self, gamma):
@@ -183,10 +184,16 @@ class Solver:
         return out.reshape(rev).permute(0, *range(len(rev) - 1, 0, -1))
 
     def timing(self, enable):
-        out = np.zeros(6)
+        out = np.zeros(9)
         B.check(B.lib.lbm_timing(self._ctx, int(bool(enable)), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return {"fwd_launches": out[0], "fwd_ms": out[1], "adj_launches": out[2], "adj_ms": out[3],
-                "rec_launches": out[4], "rec_ms": out[5]}
+                "rec_launches": out[4], "rec_ms": out[5], "tb_launches": out[6], "tb_ms": out[7],
+                "tb_steps": out[8]}
+
+    def set_blocking(self, nsteps, tile_x=32, tile_y=16):
+        """Temporal blocking of forward launches (D2Q9): nsteps per launch."""
+        B.check(B.lib.lbm_set_blocking(self._ctx, int(nsteps), int(tile_x), int(tile_y)))
+        self.blocking = (int(nsteps), int(tile_x), int(tile_y))
 
     def close(self):
         if getattr(self, "_ctx", None):

@@ -357,3 +357,37 @@ def test_unstable_run_is_reported(Solver):
         sv.forward(1)
     sv.reset()
     sv.close()
+
+
+# ------------------------------------------------------- temporal blocking
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("case", [0, 1, 2, 3])
+def test_blocked_launches_match_single_steps(Solver, prec, case):
+    """Temporally blocked forward launches (several steps per launch, halos in
+    LDS) give the states, window objectives and adjoint of single-step
+    launches: to rounding in FP64 (multiply-add contraction may differ
+    between the two kernels) and to the storage rounding in FP32 / FP16S."""
+    name, w = _small_cases()[case]
+    w.window_len, w.sample_every, w.ckpt_every, w.max_windows = 24, 12, 6, 2
+    prob = oracle_problem(w)
+    f0 = random_start_state(prob, seed=3)
+    tol = {"f64": 1e-13, "f32": 1e-6, "f16s": 1e-3}[prec]
+    res = {}
+    for nt, tile in ((1, (32, 16)), (3, (16, 16)), (4, (32, 8)), (6, (20, 13))):
+        sv = Solver(w, prec)
+        sv.set_blocking(nt, *tile)
+        sv.set_state(f0, 0)
+        sv.forward(2 * w.window_len)
+        f, step = sv.get_state()
+        J, M, _ = sv.history()
+        g, _ = sv.adjoint()
+        assert step == 2 * w.window_len
+        res[nt] = (f, J, g.cpu().numpy())
+        sv.close()
+    f1, J1, g1 = res[1]
+    for nt in (3, 4, 6):
+        f, J, g = res[nt]
+        assert rel_l2(f, f1) <= tol, (nt, rel_l2(f, f1))
+        assert np.max(np.abs(J - J1)) <= tol * np.max(np.abs(J1)) + 1e-15
+        assert rel_l2(g, g1) <= 100 * tol
