@@ -46,7 +46,55 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 / FP16S comparison")
     ap.add_argument("--max-windows", type=int, default=20)
+    ap.add_argument("--counters", action="store_true",
+                    help="run one window and its adjoint of the workload plus a 256 MiB device copy "
+                         "(for rocprofv3 --pmc byte counters) and exit")
     return ap.parse_args()
+
+
+def counters_run(args, torch):
+    """Workload for hardware-counter runs: one window forward and its adjoint,
+    then a plain 256 MiB device-to-device copy whose byte counters calibrate
+    FETCH_SIZE / WRITE_SIZE."""
+    from paper_2608_19617_amd import workloads as W
+    from paper_2608_19617_amd.solver import Solver
+    w = W.backward_facing_step(max_windows=args.max_windows)
+    sv = Solver(w, args.prec)
+    sv.forward(w.window_len)
+    sv.adjoint()
+    sv.close()
+    a = torch.ones(256 * 2 ** 20 // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"counters_run": True, "copy_bytes": a.numel() * 4}), flush=True)
+
+
+def kernel_source_digest():
+    """SHA-256 of the kernel sources: counter figures in profiles/ apply only
+    to the kernels they were measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    for fn in ("kernels.hip", "device.hpp", "lattice.hpp"):
+        with open(os.path.join(ROOT, "paper_2608_19617_amd", "csrc", fn), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, prec):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_bfs800x200_{prec}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    return float(vals["hbm_bytes_per_launch"])
 
 
 def bench_step(sv, w, max_windows):
@@ -171,6 +219,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.counters:
+        counters_run(args, torch)
+        return
     from paper_2608_19617_amd import workloads as W
     from paper_2608_19617_amd.solver import Solver
 
@@ -188,10 +239,12 @@ def main():
     # dominant kernel: the temporally blocked forward kernel when it is used
     if tm["tb_launches"] > 0 and tm["tb_ms"] >= tm["fwd_ms"]:
         kname = "k_step_tb (forward, temporally blocked)"
+        kfile = "k_step_tb"
         steps_per_launch = tm["tb_steps"] / tm["tb_launches"]
         launch_s = tm["tb_ms"] / tm["tb_launches"] * 1e-3
     else:
         kname = "k_step (forward)"
+        kfile = "k_step"
         steps_per_launch = 1.0
         launch_s = tm["fwd_ms"] / tm["fwd_launches"] * 1e-3
     bytes_per_launch = steps_per_launch * FWD_BYTES[args.prec] * N
@@ -211,7 +264,7 @@ def main():
                    "w_eff": res["rep"]["w_eff"], "converged": res["rep"]["converged"]},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "bytes_per_lup": FWD_BYTES[args.prec],
+                     "traffic": measured_traffic(kfile, args.prec), "bytes_per_lup": FWD_BYTES[args.prec],
                      "steps_per_launch": round(steps_per_launch, 3),
                      "avg_launch_us": round(launch_s * 1e6, 3)},
         "fwd_mlups": round(N / fwd_step_s / 1e6, 1),

@@ -205,7 +205,7 @@ lbm_status lbm_timing(lbm_ctx* ctx, int enable, double* out);
  * turns it off. Samples, checkpoints and window ends always fall on the last
  * step of a launch, so results are those of single steps up to the
  * contraction of multiply-adds. Requires tile_x * tile_y >= 256 and
- * 2 * 9 * (tile_x + 2(nsteps-1)) * (tile_y + 2(nsteps-1)) values of compute
+ * 19 * (tile_x + 2(nsteps-1)) * (tile_y + 2(nsteps-1)) values of compute
  * precision within 159 KB. A launch never runs past the next sample,
  * checkpoint or window end, so shorter blocked launches occur. Defaults
  * after lbm_init (measured on MI355X): grids of at most 400k nodes 5 steps

@@ -135,7 +135,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(const S* __restrict__ gin, S* __
 // sampled step (SAMPLE) or a checkpoint step (WPRE). Halo nodes are
 // recomputed by neighbouring tiles; every node update uses the same device
 // functions as the single-step kernel. LDS: two buffers of Q planes of
-// (ox + 2(NT-1)) x (oy + 2(NT-1)) values in compute precision. TB threads
+// (ox + 2(NT-1)) x (oy + 2(NT-1)) values in compute precision and one plane
+// of the bounce-back fraction, read from global memory once. TB threads
 // (512 or 1024, whichever covers the first region in one round) update the
 // nodes of a region.
 template <class S, class T, bool SAMPLE, bool WPRE, int TB>
@@ -150,6 +151,7 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
     const int LW = ox + 2 * H, LH = oy + 2 * H;
     const int plane_sz = LW * LH;
     T* buf[2] = {lds, lds + (size_t)L::Q * plane_sz};
+    T* sbuf = lds + (size_t)2 * L::Q * plane_sz;      // s of the region, loaded at step 1
     const int tx = (int)blockIdx.x % tiles_x, ty = (int)blockIdx.x / tiles_x;
     const int x0 = tx * ox - H, y0 = ty * oy - H;     // global coords of LDS cell (0, 0)
     double v[3] = {0.0, 0.0, 0.0};
@@ -206,13 +208,20 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
                 v[1] += vv[1];
                 v[2] += vv[2];
             }
+            const int cell = ly * LW + lx;
+            T sv;
+            if (t == 1) {
+                sv = sfield[n];
+                sbuf[cell] = sv;
+            } else {
+                sv = sbuf[cell];
+            }
             T out[L::Q];
-            collide<L, T>(mo, sfield[n], out);
+            collide<L, T>(mo, sv, out);
             if (last) {
 #pragma unroll
                 for (int a = 0; a < L::Q; ++a) plane(gout, a, g.N)[(unsigned)n] = (S)out[a];
             } else {
-                const int cell = ly * LW + lx;
 #pragma unroll
                 for (int a = 0; a < L::Q; ++a) dst[a * plane_sz + cell] = out[a];
             }
@@ -617,7 +626,7 @@ long blocks_for(long n) { return (n + BLOCK - 1) / BLOCK; }
 
 size_t tb_lds_bytes(int nsteps, int tile_x, int tile_y, size_t elem) {
     const size_t lw = tile_x + 2 * (nsteps - 1), lh = tile_y + 2 * (nsteps - 1);
-    return 2 * 9 * lw * lh * elem;
+    return (2 * 9 + 1) * lw * lh * elem;
 }
 
 long tb_blocks(int nx, int ny, int tile_x, int tile_y) {

@@ -391,3 +391,198 @@ def test_blocked_launches_match_single_steps(Solver, prec, case):
         assert rel_l2(f, f1) <= tol, (nt, rel_l2(f, f1))
         assert np.max(np.abs(J - J1)) <= tol * np.max(np.abs(J1)) + 1e-15
         assert rel_l2(g, g1) <= 100 * tol
+
+
+# ------------------------------------------------- full-size configurations
+#
+# At full size the oracle cannot replay whole windows in a test, so the GPU
+# (in the launch configuration the benchmark times) is compared with the
+# oracle over a bounded number of steps from a shared state, and through
+# properties that hold at any size.
+
+def _share_state(Solver, w, steps, prec="f64"):
+    """GPU state after `steps` steps (a multiple of the window length)."""
+    sv = Solver(w, prec)
+    sv.forward(steps)
+    f, step = sv.get_state()
+    sv.close()
+    assert step == steps
+    return f
+
+
+def _oracle_steps(prob, gamma, f, n):
+    s = fw.design_map(prob, gamma)
+    for _ in range(n):
+        f = fw.step(prob, f, s)
+    return f
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5), ("f16s", 2e-3)])
+def test_bfs_full_size_steps(Solver, prec, tol):
+    """Backward-facing step 800 x 200 (benchmark workload, default blocked
+    launches): 100 steps from a shared FP64 state at step 2000, against the
+    oracle; and the single sampled pressure drop of a 100-step window."""
+    w = W.backward_facing_step()
+    f0 = _share_state(Solver, w, 2000)
+    w1 = W.backward_facing_step()
+    w1.window_len, w1.sample_every, w1.ckpt_every, w1.max_windows = 100, 100, 100, 1
+    prob = oracle_problem(w1)
+    f_o = _oracle_steps(prob, w1.gamma, f0, 100)
+    sv = Solver(w1, prec)
+    sv.set_state(f0, 0)
+    rep = sv.forward(100)
+    f_g, _ = sv.get_state()
+    J_o = fw.pressure_drop(prob, f_o)
+    e_f = rel_l2(f_g, f_o)
+    e_J = abs(rep["J_eff"] - J_o) / abs(J_o)
+    print(f"BFS 800x200 {prec}: fields after 100 steps {e_f:.2e}, sampled dp {e_J:.2e} (dp = {J_o:.3e})")
+    assert e_f <= tol
+    assert e_J <= (1e-10 if prec == "f64" else 50 * tol)
+    sv.close()
+
+
+def test_bfs_window_criterion_fp32_vs_fp64(Solver):
+    """The consecutive-window test on the benchmark workload: FP32 and FP64
+    take the same decision for every window whose FP64 relative change is not
+    within the FP32 error margin of eps (Eq. statistical_criterion)."""
+    w = W.backward_facing_step()
+    hist = {}
+    for prec in ("f64", "f32"):
+        sv = Solver(w, prec)
+        rep = sv.forward(w.max_windows * w.window_len, stop_on_converge=True)
+        hist[prec] = (rep, sv.history())
+        sv.close()
+    rep64, (J64, M64, R64) = hist["f64"]
+    rep32, (J32, M32, R32) = hist["f32"]
+    print(f"BFS windows: FP64 converged={rep64['converged']} w_eff={rep64['w_eff']}; "
+          f"FP32 converged={rep32['converged']} w_eff={rep32['w_eff']}; "
+          f"FP64 rel changes {np.round(R64[1:6], 4)}")
+    n = min(len(R64), len(R32))
+    for i in range(1, n):
+        if abs(R64[i] - w.eps) > 0.5 * abs(R64[i]) + 1e-3:
+            assert (R64[i] < w.eps) == (R32[i] < w.eps)
+    assert np.all(np.isfinite(J32)) and np.all(np.isfinite(J64))
+
+
+def test_cylinder_wake_full_size_fp32(Solver):
+    """Cylinder wake 2048 x 512 (Re 1000, LES): 10 steps from a shared FP64
+    state at step 1000 in FP32 against the oracle."""
+    w = W.cylinder_wake(window_len=1000, ckpt_every=100, sample_every=20, max_windows=1)
+    f0 = _share_state(Solver, w, 1000)
+    w1 = W.cylinder_wake(window_len=10, ckpt_every=10, sample_every=10, max_windows=1)
+    prob = oracle_problem(w1)
+    f_o = _oracle_steps(prob, w1.gamma, f0, 10)
+    sv = Solver(w1, "f32")
+    sv.set_state(f0, 0)
+    sv.forward(10)
+    f_g, _ = sv.get_state()
+    e = rel_l2(f_g, f_o)
+    print(f"cylinder wake 2048x512 FP32: fields after 10 steps {e:.2e}")
+    assert e <= 1e-5
+    sv.close()
+
+
+def test_cylinder_wake_fd_check(Solver):
+    """Cylinder wake 2048 x 512, FP64: central finite differences (h = 1e-4)
+    of the replayed window objective on 16 seed-chosen design entries (disk
+    ramp and near wake) against the adjoint, with the paper's < 1% bar
+    (Sec. 4.2.1). Window of 2000 steps after 2000 steps of spin-up: long
+    enough for sound to carry the disk's influence to both pressure sections
+    (a shorter window has dJ/dgamma = 0 there)."""
+    w = W.cylinder_wake(window_len=2000, ckpt_every=100, sample_every=20, max_windows=2)
+    sv = Solver(w, "f64")
+    sv.forward(4000)
+    g, J = sv.adjoint()
+    g = g.cpu().numpy()
+    rng = np.random.default_rng(0)
+    X, Y = np.meshgrid(np.arange(2048), np.arange(512), indexing="ij")
+    cand = np.argwhere(((w.gamma > 0) & (w.gamma < 1)) |
+                       ((X >= 544) & (X < 704) & (np.abs(Y - 256) <= 64)))
+    pick = cand[rng.choice(len(cand), 16, replace=False)]
+    errs = []
+    for ix, iy in pick:
+        gp = w.gamma.copy()
+        gm = w.gamma.copy()
+        gp[ix, iy] += 1e-4
+        gm[ix, iy] -= 1e-4
+        fd = (sv.replay(gp) - sv.replay(gm)) / 2e-4
+        assert g[ix, iy] != 0.0
+        errs.append(abs(fd - g[ix, iy]) / abs(g[ix, iy]))
+    errs = np.array(errs)
+    print(f"cylinder wake FD check: max rel err {errs.max():.2e}, median {np.median(errs):.2e}, "
+          f"|dJ/dgamma| of the entries {np.abs(g[tuple(pick.T)]).min():.2e}..{np.abs(g[tuple(pick.T)]).max():.2e}")
+    assert np.median(errs) <= 1e-2
+    sv.close()
+
+
+def test_u_bend_full_size_precisions(Solver):
+    """U-bend 1024 x 1024 (dissipation + pressure drop objective, west inlet
+    and west outlet): dJ/dgamma over a 200-step window from a shared FP64
+    state, FP32 and FP16S against FP64 (<= 1e-4 and <= 1e-2)."""
+    w = W.u_bend(window_len=200, sample_every=20, ckpt_every=20, max_windows=1)
+    f0 = _share_state(Solver, w, 1000)
+    res = {}
+    for prec in ("f64", "f32", "f16s"):
+        sv = Solver(w, prec)
+        sv.set_state(f0, 0)
+        sv.forward(w.window_len)
+        g, J = sv.adjoint()
+        res[prec] = (g.cpu().numpy(), J)
+        sv.close()
+    g64, J64 = res["f64"]
+    e32 = rel_l2(res["f32"][0], g64)
+    e16 = rel_l2(res["f16s"][0], g64)
+    print(f"U-bend 1024x1024 dJ/dgamma vs FP64: FP32 {e32:.2e}, FP16S {e16:.2e}; J FP32 "
+          f"{abs(res['f32'][1] - J64) / abs(J64):.2e}, FP16S {abs(res['f16s'][1] - J64) / abs(J64):.2e}")
+    assert e32 <= 1e-4
+    assert e16 <= 1e-2
+
+
+def test_u_bend_oracle_one_step(Solver):
+    """U-bend at full size: one step from a shared state against the oracle
+    (FP64), covering the west velocity and west pressure rows at scale."""
+    w = W.u_bend(window_len=200, sample_every=20, ckpt_every=20, max_windows=1)
+    f0 = _share_state(Solver, w, 200)
+    w1 = W.u_bend(window_len=2, sample_every=2, ckpt_every=2, max_windows=1)
+    prob = oracle_problem(w1)
+    f_o = _oracle_steps(prob, w1.gamma, f0, 2)
+    sv = Solver(w1, "f64")
+    sv.set_state(f0, 0)
+    rep = sv.forward(2)
+    f_g, _ = sv.get_state()
+    assert rel_l2(f_g, f_o) <= 1e-13
+    J_o = fw.sample(prob, f_o, "diss_dp")
+    assert abs(rep["J_eff"] - J_o) <= 1e-11 * abs(J_o)
+    sv.close()
+
+
+def test_cylinder_3d_full_size(Solver):
+    """D3Q19 channel 384 x 128 x 128: 2 steps from a shared FP64 state against
+    the oracle (FP64 and FP32), and dJ/dgamma of a 40-step window from the
+    shared state, FP32 against FP64 (<= 1e-4)."""
+    w = W.cylinder_3d(window_len=40, sample_every=20, ckpt_every=10, n_windows=1)
+    f0 = _share_state(Solver, w, 200)
+    w1 = W.cylinder_3d(window_len=2, sample_every=2, ckpt_every=2, n_windows=1)
+    prob = oracle_problem(w1)
+    f_o = _oracle_steps(prob, w1.gamma, f0, 2)
+    for prec, tol in (("f64", 1e-13), ("f32", 1e-6)):
+        sv = Solver(w1, prec)
+        sv.set_state(f0, 0)
+        sv.forward(2)
+        f_g, _ = sv.get_state()
+        e = rel_l2(f_g, f_o)
+        print(f"cylinder 3D {prec}: 2 steps {e:.2e}")
+        assert e <= tol
+        sv.close()
+    del f_o
+    res = {}
+    for prec in ("f64", "f32"):
+        sv = Solver(w, prec)
+        sv.set_state(f0, 0)
+        sv.forward(w.window_len)
+        g, J = sv.adjoint()
+        res[prec] = g.cpu().numpy()
+        sv.close()
+    e = rel_l2(res["f32"], res["f64"])
+    print(f"cylinder 3D dJ/dgamma FP32 vs FP64: {e:.2e}")
+    assert e <= 1e-4
