@@ -208,8 +208,8 @@ lbm_status lbm_timing(lbm_ctx* ctx, int enable, double* out);
  * 19 * (tile_x + 2(nsteps-1)) * (tile_y + 2(nsteps-1)) values of compute
  * precision within 159 KB. A launch never runs past the next sample,
  * checkpoint or window end, so shorter blocked launches occur. Defaults
- * after lbm_init (measured on MI355X): grids of at most 400k nodes 5 steps
- * (FP32, FP16S) or 4 steps (FP64) on 25 x 25 tiles; larger grids 4 steps on
+ * after lbm_init (measured on MI355X): grids of at most 400k nodes 6 steps
+ * (FP32), 8 steps (FP16S) or 4 steps (FP64) on 25 x 25 tiles; larger grids 4 steps on
  * 16 x 16 (FP32), 2 steps on 24 x 16 (FP64), single steps (FP16S). Recompute
  * steps of the adjoint are single steps. */
 lbm_status lbm_set_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y);

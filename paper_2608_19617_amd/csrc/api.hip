@@ -517,7 +517,7 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
         // blocked kernel ALU-bound and shorter blocks (or none) win.
         int nt, tx, ty;
         if (L.N <= 400000) {
-            nt = cfg->prec == LBM_F64 ? 4 : 5;
+            nt = cfg->prec == LBM_F64 ? 4 : (cfg->prec == LBM_F32 ? 6 : 8);
             tx = ty = 25;
         } else if (cfg->prec == LBM_F32) {
             nt = 4;

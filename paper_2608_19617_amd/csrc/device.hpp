@@ -151,11 +151,8 @@ __device__ __forceinline__ void pull(const S* __restrict__ G, const Geo& g, int 
 // (west) or (1 + b) - rho_0 (east) on a pressure row; each entering
 // population is h_a = h_opp(a) + 6 w_a c_ax rho u_x - 1/2 sum_p c_ap N_p with
 // N_p = sum_{c_x=0} c_p h.
-template <class L, class T>
-__device__ __forceinline__ void zou_he(const Geo& g, int oc, int y, T h[L::Q]) {
-    const int face = (oc - 1) / 3;
-    const int kind = (oc - 1) % 3;
-    const int sgn = face == 0 ? 1 : -1;
+template <class L, class T, int SGN>
+__device__ __forceinline__ void zou_he_face(const Geo& g, int kind, int y, T h[L::Q]) {
     T b = 0, Ny = 0, Nz = 0;
 #pragma unroll
     for (int a = 0; a < L::Q; ++a) {
@@ -163,7 +160,7 @@ __device__ __forceinline__ void zou_he(const Geo& g, int oc, int y, T h[L::Q]) {
             b += h[a];
             Ny += (T)L::cy[a] * h[a];
             if (L::D == 3) Nz += (T)L::cz[a] * h[a];
-        } else if (L::cx[a] == -sgn) {
+        } else if (L::cx[a] == -SGN) {
             b += (T)2 * h[a];
         }
     }
@@ -173,17 +170,34 @@ __device__ __forceinline__ void zou_he(const Geo& g, int oc, int y, T h[L::Q]) {
         rux = ((T)1 + b) * u0 / ((T)1 - u0);
     } else {
         const T d0 = (T)g.drho_out;
-        rux = face == 0 ? d0 - b : b - d0;
+        rux = SGN == 1 ? d0 - b : b - d0;
     }
 #pragma unroll
     for (int a = 0; a < L::Q; ++a) {
-        if (L::cx[a] == sgn) {
+        if (L::cx[a] == SGN) {
             T v = h[L::opp[a]] + (T)(6.0 * L::w[a] * L::cx[a]) * rux;
             if (L::cy[a] != 0) v -= (T)(0.5 * L::cy[a]) * Ny;
             if (L::D == 3 && L::cz[a] != 0) v -= (T)(0.5 * L::cz[a]) * Nz;
             h[a] = v;
         }
     }
+}
+
+// Both faces are evaluated and the result selected element by element, so
+// that every array index stays a compile-time constant (a branch per face
+// lets the compiler merge the two faces' stores into one with a selected
+// address, which moves the array to scratch memory).
+template <class L, class T>
+__device__ __forceinline__ void zou_he(const Geo& g, int oc, int y, T h[L::Q]) {
+    const int kind = (oc - 1) % 3;
+    const bool west = oc <= 3;
+    T hw[L::Q], he[L::Q];
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) hw[a] = he[a] = h[a];
+    zou_he_face<L, T, 1>(g, kind, y, hw);
+    zou_he_face<L, T, -1>(g, kind, y, he);
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) h[a] = west ? hw[a] : he[a];
 }
 
 // Transpose of zou_he on the adjoint populations mu of the post-boundary
@@ -193,22 +207,19 @@ __device__ __forceinline__ void zou_he(const Geo& g, int oc, int y, T h[L::Q]) {
 // and tangential directions lose sum_p c_bp B_p, where
 // A = 6 chi sum_{entering} w_a c_ax mu_a and B_p = 1/2 sum_{entering} c_ap mu_a.
 // For D2Q9 this is Eqs. adjoint_inlet_bc and adjoint_outlet_bc.
-template <class L, class T>
-__device__ __forceinline__ void zou_he_adjoint(const Geo& g, int oc, int y, T mu[L::Q]) {
-    const int face = (oc - 1) / 3;
-    const int kind = (oc - 1) % 3;
-    const int sgn = face == 0 ? 1 : -1;
+template <class L, class T, int SGN>
+__device__ __forceinline__ void zou_he_adjoint_face(const Geo& g, int kind, int y, T mu[L::Q]) {
     T chi;
     if (kind == ROW_VELOCITY) {
         const T u0 = (T)g.u_in[y];
         chi = u0 / ((T)1 - u0);
     } else {
-        chi = face == 0 ? (T)-1 : (T)1;
+        chi = SGN == 1 ? (T)-1 : (T)1;
     }
     T A = 0, By = 0, Bz = 0;
 #pragma unroll
     for (int a = 0; a < L::Q; ++a) {
-        if (L::cx[a] == sgn) {
+        if (L::cx[a] == SGN) {
             A += (T)(6.0 * L::w[a] * L::cx[a]) * mu[a];
             By += (T)(0.5 * L::cy[a]) * mu[a];
             if (L::D == 3) Bz += (T)(0.5 * L::cz[a]) * mu[a];
@@ -218,7 +229,7 @@ __device__ __forceinline__ void zou_he_adjoint(const Geo& g, int oc, int y, T mu
     T out[L::Q];
 #pragma unroll
     for (int a = 0; a < L::Q; ++a) {
-        if (L::cx[a] == sgn) {
+        if (L::cx[a] == SGN) {
             out[a] = 0;
         } else if (L::cx[a] == 0) {
             T v = mu[a] + A;
@@ -231,6 +242,19 @@ __device__ __forceinline__ void zou_he_adjoint(const Geo& g, int oc, int y, T mu
     }
 #pragma unroll
     for (int a = 0; a < L::Q; ++a) mu[a] = out[a];
+}
+
+template <class L, class T>
+__device__ __forceinline__ void zou_he_adjoint(const Geo& g, int oc, int y, T mu[L::Q]) {
+    const int kind = (oc - 1) % 3;
+    const bool west = oc <= 3;
+    T mw[L::Q], me[L::Q];
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) mw[a] = me[a] = mu[a];
+    zou_he_adjoint_face<L, T, 1>(g, kind, y, mw);
+    zou_he_adjoint_face<L, T, -1>(g, kind, y, me);
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) mu[a] = west ? mw[a] : me[a];
 }
 
 // Symmetric-tensor helpers over D x D, stored as the upper triangle in the

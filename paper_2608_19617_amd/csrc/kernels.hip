@@ -139,6 +139,54 @@ __global__ __launch_bounds__(BLOCK) void k_step(const S* __restrict__ gin, S* __
 // of the bounce-back fraction, read from global memory once. TB threads
 // (512 or 1024, whichever covers the first region in one round) update the
 // nodes of a region.
+// Cell i of the region [m, LW - m) x [m, LH - m): LDS coordinates and the
+// (wrapped) global node; false if the node lies outside the domain or, for
+// the output step, outside the tile's own part of the domain.
+struct TbCell {
+    int lx, ly, x, y, n, cell;
+};
+
+__device__ __forceinline__ bool tb_cell(const Geo& g, int i, int m, int rw, float inv_rw, int LW, int x0,
+                                        int y0, bool output, TbCell& c) {
+    const int qy = (int)(((float)i + 0.5f) * inv_rw);   // exact for i < 2^12
+    c.ly = m + qy;
+    c.lx = m + (i - qy * rw);
+    int x = x0 + c.lx, y = y0 + c.ly;
+    if (output && (x >= g.nx || y >= g.ny)) return false;   // no wrapped duplicates in the output
+    if (g.per_x) x = ((x % g.nx) + g.nx) % g.nx;
+    if (g.per_y) y = ((y % g.ny) + g.ny) % g.ny;
+    if (x < 0 || x >= g.nx || y < 0 || y >= g.ny) return false;
+    c.x = x;
+    c.y = y;
+    c.n = y * g.nx + x;
+    c.cell = c.ly * LW + c.lx;
+    return true;
+}
+
+// Pull of node c from the previous step's LDS buffer, with the halfway wall
+// rule and the Zou-He rows (the same rules as pull() + zou_he()).
+template <class T>
+__device__ __forceinline__ void tb_pull_lds(const Geo& g, const T* __restrict__ srcb, int plane_sz, int LW,
+                                            const TbCell& c, T h[9]) {
+    using L = D2Q9;
+    const int oc = open_code<L>(g, c.x, c.y, 0);
+    const bool inner = (g.per_x || (c.x > 0 && c.x < g.nx - 1)) && (g.per_y || (c.y > 0 && c.y < g.ny - 1));
+    if (inner) {
+#pragma unroll
+        for (int a = 0; a < L::Q; ++a) h[a] = srcb[a * plane_sz + c.cell - L::cy[a] * LW - L::cx[a]];
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) {
+        const int xs = c.x - L::cx[a], ys = c.y - L::cy[a];
+        const bool out = (!g.per_x && (xs < 0 || xs >= g.nx)) || (!g.per_y && (ys < 0 || ys >= g.ny));
+        if (!out) h[a] = srcb[a * plane_sz + c.cell - L::cy[a] * LW - L::cx[a]];
+        else if (oc == 0) h[a] = srcb[L::opp[a] * plane_sz + c.cell];
+        else h[a] = (T)0;
+    }
+    if (oc) zou_he<L, T>(g, oc, c.y, h);
+}
+
 template <class S, class T, bool SAMPLE, bool WPRE, int TB>
 __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __restrict__ gout,
                                                 S* __restrict__ pre, const T* __restrict__ sfield,
@@ -150,83 +198,85 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
     const int H = nt - 1;
     const int LW = ox + 2 * H, LH = oy + 2 * H;
     const int plane_sz = LW * LH;
-    T* buf[2] = {lds, lds + (size_t)L::Q * plane_sz};
-    T* sbuf = lds + (size_t)2 * L::Q * plane_sz;      // s of the region, loaded at step 1
+    const int bufsz = L::Q * plane_sz;                // buffer b starts at lds + b * bufsz
+    T* sbuf = lds + 2 * bufsz;                        // s of the region, loaded at step 1
     const int tx = (int)blockIdx.x % tiles_x, ty = (int)blockIdx.x / tiles_x;
     const int x0 = tx * ox - H, y0 = ty * oy - H;     // global coords of LDS cell (0, 0)
-    double v[3] = {0.0, 0.0, 0.0};
-    for (int t = 1; t <= nt; ++t) {
-        const int m = t - 1;                             // region: LDS cells [m, LW - m) x [m, LH - m)
-        const int rw = LW - 2 * m, rh = LH - 2 * m;
-        const int count = rw * rh;
+
+    // step 1: pull from global memory over the whole LDS region
+    {
+        const int rw = LW, count = LW * LH;
         const float inv_rw = 1.0f / (float)rw;
-        T* dst = buf[t & 1];
-        const T* srcb = buf[(t - 1) & 1];
-        const bool last = t == nt;
+        T* dst = lds + bufsz;
         for (int i = (int)threadIdx.x; i < count; i += TB) {
-            int qy = (int)(((float)i + 0.5f) * inv_rw);  // exact: i < 2^12
-            const int ly = m + qy, lx = m + (i - qy * rw);
-            int x = x0 + lx, y = y0 + ly;
-            // the output tile owns only nodes inside the domain (no wrapped duplicates)
-            if (last && (x >= g.nx || y >= g.ny)) continue;
-            if (g.per_x) x = ((x % g.nx) + g.nx) % g.nx;
-            if (g.per_y) y = ((y % g.ny) + g.ny) % g.ny;
-            if (x < 0 || x >= g.nx || y < 0 || y >= g.ny) continue;   // outside the domain
-            const int n = y * g.nx + x;
-            const int oc = open_code<L>(g, x, y, 0);
+            TbCell c;
+            if (!tb_cell(g, i, 0, rw, inv_rw, LW, x0, y0, false, c)) continue;
+            const int oc = open_code<L>(g, c.x, c.y, 0);
             T h[L::Q];
-            if (t == 1) {
-                pull<L, S, T>(gin, g, n, x, y, 0, oc, h);
-            } else {
-                const bool inner = (g.per_x || (x > 0 && x < g.nx - 1)) && (g.per_y || (y > 0 && y < g.ny - 1));
-                const int cell = ly * LW + lx;
-                if (inner) {
+            pull<L, S, T>(gin, g, c.n, c.x, c.y, 0, oc, h);
+            if (oc) zou_he<L, T>(g, oc, c.y, h);
+            Moments<L, T> mo;
+            moments<L, T>(h, ph, mo);
+            const T sv = sfield[c.n];
+            sbuf[c.cell] = sv;
+            T out[L::Q];
+            collide<L, T>(mo, sv, out);
 #pragma unroll
-                    for (int a = 0; a < L::Q; ++a) h[a] = srcb[a * plane_sz + cell - L::cy[a] * LW - L::cx[a]];
-                } else {
+            for (int a = 0; a < L::Q; ++a) dst[a * plane_sz + c.cell] = out[a];
+        }
+        __syncthreads();
+    }
+    // steps 2 .. nt-1: LDS to LDS over shrinking regions
+    for (int t = 2; t < nt; ++t) {
+        const int m = t - 1;
+        const int rw = LW - 2 * m, count = rw * (LH - 2 * m);
+        const float inv_rw = 1.0f / (float)rw;
+        T* dst = lds + (t & 1) * bufsz;
+        const T* srcb = lds + ((t - 1) & 1) * bufsz;
+        for (int i = (int)threadIdx.x; i < count; i += TB) {
+            TbCell c;
+            if (!tb_cell(g, i, m, rw, inv_rw, LW, x0, y0, false, c)) continue;
+            T h[L::Q];
+            tb_pull_lds<T>(g, srcb, plane_sz, LW, c, h);
+            Moments<L, T> mo;
+            moments<L, T>(h, ph, mo);
+            T out[L::Q];
+            collide<L, T>(mo, sbuf[c.cell], out);
 #pragma unroll
-                    for (int a = 0; a < L::Q; ++a) {
-                        const int xs = x - L::cx[a], ys = y - L::cy[a];
-                        const bool out = (!g.per_x && (xs < 0 || xs >= g.nx)) || (!g.per_y && (ys < 0 || ys >= g.ny));
-                        if (!out) h[a] = srcb[a * plane_sz + cell - L::cy[a] * LW - L::cx[a]];
-                        else if (oc == 0) h[a] = srcb[L::opp[a] * plane_sz + cell];
-                        else h[a] = (T)0;
-                    }
-                }
-            }
-            if (oc) zou_he<L, T>(g, oc, y, h);
-            if (last && WPRE) {
+            for (int a = 0; a < L::Q; ++a) dst[a * plane_sz + c.cell] = out[a];
+        }
+        __syncthreads();
+    }
+    // step nt: the output tile, from LDS to global memory (samples, checkpoint)
+    double v[3] = {0.0, 0.0, 0.0};
+    {
+        const int m = nt - 1;
+        const int rw = LW - 2 * m, count = rw * (LH - 2 * m);
+        const float inv_rw = 1.0f / (float)rw;
+        const T* srcb = lds + ((nt - 1) & 1) * bufsz;
+        for (int i = (int)threadIdx.x; i < count; i += TB) {
+            TbCell c;
+            if (!tb_cell(g, i, m, rw, inv_rw, LW, x0, y0, true, c)) continue;
+            T h[L::Q];
+            tb_pull_lds<T>(g, srcb, plane_sz, LW, c, h);
+            if (WPRE) {
 #pragma unroll
-                for (int a = 0; a < L::Q; ++a) plane(pre, a, g.N)[(unsigned)n] = (S)h[a];
+                for (int a = 0; a < L::Q; ++a) plane(pre, a, g.N)[(unsigned)c.n] = (S)h[a];
             }
             Moments<L, T> mo;
             moments<L, T>(h, ph, mo);
-            if (last && SAMPLE) {
+            if (SAMPLE) {
                 double vv[3];
-                node_samples<L, T>(ob, x, y, mo, vv);
+                node_samples<L, T>(ob, c.x, c.y, mo, vv);
                 v[0] += vv[0];
                 v[1] += vv[1];
                 v[2] += vv[2];
             }
-            const int cell = ly * LW + lx;
-            T sv;
-            if (t == 1) {
-                sv = sfield[n];
-                sbuf[cell] = sv;
-            } else {
-                sv = sbuf[cell];
-            }
             T out[L::Q];
-            collide<L, T>(mo, sv, out);
-            if (last) {
+            collide<L, T>(mo, sbuf[c.cell], out);
 #pragma unroll
-                for (int a = 0; a < L::Q; ++a) plane(gout, a, g.N)[(unsigned)n] = (S)out[a];
-            } else {
-#pragma unroll
-                for (int a = 0; a < L::Q; ++a) dst[a * plane_sz + cell] = out[a];
-            }
+            for (int a = 0; a < L::Q; ++a) plane(gout, a, g.N)[(unsigned)c.n] = (S)out[a];
         }
-        __syncthreads();
     }
     if (SAMPLE) {
         block_sum_n<3, TB>(v, partials + 3 * (size_t)blockIdx.x);
