@@ -271,7 +271,9 @@ def main():
         "adj_kernel_mlups": round(N / adj_avg_s / 1e6, 1),
         "adj_kernel": {"avg_launch_us": round(adj_avg_s * 1e6, 3), "bytes_per_lup": ADJ_BYTES[args.prec],
                        "achieved_GBs": round(ADJ_BYTES[args.prec] * N / adj_avg_s / 1e9, 1)},
-        "recompute_avg_launch_us": round(tm["rec_ms"] / max(tm["rec_launches"], 1) * 1e3, 3),
+        "recompute": {"avg_launch_us": round(tm["rec_ms"] / max(tm["rec_launches"], 1) * 1e3, 3),
+                      "us_per_step": round(tm["rec_ms"] / max(tm["rec_steps"], 1) * 1e3, 3),
+                      "steps_per_launch": round(tm["rec_steps"] / max(tm["rec_launches"], 1), 3)},
         "J": res["J"],
     }
     sv.close()

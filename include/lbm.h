@@ -195,8 +195,9 @@ lbm_status lbm_get_fields(lbm_ctx* ctx, double* rho_u_dev);
  * launches and total milliseconds of each class,
  * so ms / launches is the average launch duration including the dispatch
  * gaps between consecutive launches. A fourth pair counts the temporally
- * blocked forward launches, and a ninth double the steps they advanced
- * (9 doubles in all). */
+ * blocked forward launches; the ninth double is the steps they advanced and
+ * the tenth the steps advanced by the recompute launches, which are also
+ * blocked where the forward is (10 doubles in all). */
 lbm_status lbm_timing(lbm_ctx* ctx, int enable, double* out);
 
 /* Temporal blocking of forward launches (D2Q9 only): each launch advances
@@ -206,12 +207,16 @@ lbm_status lbm_timing(lbm_ctx* ctx, int enable, double* out);
  * step of a launch, so results are those of single steps up to the
  * contraction of multiply-adds. Requires tile_x * tile_y >= 256 and
  * 19 * (tile_x + 2(nsteps-1)) * (tile_y + 2(nsteps-1)) values of compute
- * precision within 159 KB. A launch never runs past the next sample,
+ * precision, 1024 more (per-thread dump slots) and a row cache of
+ * (tile_y + 2(nsteps-1)) * (value + 2 bytes)
+ * within 159 KB. A launch never runs past the next sample,
  * checkpoint or window end, so shorter blocked launches occur. Defaults
- * after lbm_init (measured on MI355X): grids of at most 400k nodes 6 steps
- * (FP32), 8 steps (FP16S) or 4 steps (FP64) on 25 x 25 tiles; larger grids 4 steps on
- * 16 x 16 (FP32), 2 steps on 24 x 16 (FP64), single steps (FP16S). Recompute
- * steps of the adjoint are single steps. */
+ * after lbm_init (measured on MI355X): grids of at most 400k nodes use
+ * square tiles of about N / 256 nodes (16 to 25 per side) and 10 steps
+ * (FP32, FP16S) or 4 steps (FP64); larger grids 6 steps on 64 x 16 tiles
+ * (FP32), 6 steps on 32 x 32 (FP16S), 3 steps on 32 x 8 (FP64). The
+ * recompute of the adjoint sweep uses the same blocking, storing every
+ * intermediate state. */
 lbm_status lbm_set_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y);
 
 /* Thread-local message of the last failing call on this thread. */

@@ -238,6 +238,8 @@ StepLaunch step_args(lbm_ctx* c) {
     a.nsteps = 1;
     a.tile_x = c->tile_x;
     a.tile_y = c->tile_y;
+    a.allout = nullptr;
+    a.allout_slot = 0;
     return a;
 }
 
@@ -512,23 +514,28 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
     if ((st = do_reset(c)) != LBM_OK) return bail(st);
     if (cfg->lattice == LBM_D2Q9) {
         // default temporal blocking of forward launches, from measurements on
-        // MI355X: latency-bound grids gain most from several steps per launch
-        // on 25 x 25 tiles; on large grids the halo recomputation makes the
-        // blocked kernel ALU-bound and shorter blocks (or none) win.
+        // MI355X. Small grids are latency-bound: one tile per compute unit
+        // (about N / 256 nodes, at least 16 x 16) and long blocks amortise
+        // the fixed cost of a launch. On large grids the halo recomputation
+        // makes the blocked kernel ALU-bound and wide, shorter blocks win.
         int nt, tx, ty;
         if (L.N <= 400000) {
-            nt = cfg->prec == LBM_F64 ? 4 : (cfg->prec == LBM_F32 ? 6 : 8);
-            tx = ty = 25;
+            int t = (int)std::lround(std::sqrt((double)L.N / 256.0));
+            t = t < 16 ? 16 : (t > 25 ? 25 : t);
+            tx = ty = t;
+            nt = cfg->prec == LBM_F64 ? 4 : 10;
+            while (nt > 2 && tb_lds_bytes(nt, tx, ty, L.cs) > 159 * 1024) --nt;
         } else if (cfg->prec == LBM_F32) {
-            nt = 4;
-            tx = ty = 16;
-        } else if (cfg->prec == LBM_F64) {
-            nt = 2;
-            tx = 24;
+            nt = 6;
+            tx = 64;
             ty = 16;
+        } else if (cfg->prec == LBM_F64) {
+            nt = 3;
+            tx = 32;
+            ty = 8;
         } else {
-            nt = 1;
-            tx = ty = 16;
+            nt = 6;
+            tx = ty = 32;
         }
         if ((st = set_blocking(c, nt, tx, ty)) != LBM_OK) return bail(st);
     }
@@ -675,12 +682,22 @@ lbm_status lbm_adjoint(lbm_ctx* c, int window, double* dJdgamma_dev, double* J_o
             ca.src = c->ring[p][seg];
             ca.dst = c->seg[0];
             HIPCHK(launch_aux(ca));
-            for (long j = 1; j <= nrec; ++j) {
+            // recompute G^{c0+1} .. G^{c0+nrec} into seg[1 .. nrec]; blocked
+            // launches keep every intermediate state (seg slots are SB apart)
+            for (long j = 1; j <= nrec;) {
+                long n = nrec - j + 1;
+                if (n > c->tb_steps) n = c->tb_steps;
+                sa.nsteps = (int)n;
                 sa.gin = c->seg[j - 1];
-                sa.gout = c->seg[j];
-                if ((st = t_launch(c, 2)) != LBM_OK) return st;
+                sa.gout = c->seg[j + n - 1];
+                sa.allout = n > 1 ? c->seg[j] : nullptr;
+                sa.allout_slot = L.SB;
+                if ((st = t_launch(c, 2, n)) != LBM_OK) return st;
                 HIPCHK(launch_step(sa));
+                j += n;
             }
+            sa.allout = nullptr;
+            sa.nsteps = 1;
             if ((st = t_close(c)) != LBM_OK) return st;
         }
         if (last) {
@@ -804,6 +821,7 @@ lbm_status lbm_timing(lbm_ctx* c, int enable, double* out) {
             out[2 * i + 1] = c->tm.ms[i];
         }
         out[8] = c->tm.st[3];
+        out[9] = c->tm.st[2];
     }
     if (enable) {
         if (c->tm.ev.empty()) {

@@ -101,11 +101,13 @@ __device__ __forceinline__ float to_f(S v) { return (float)v; }
 
 // Pull of the post-collision populations into node (x, y, z) (Eq.
 // streaming_step): h_a(x) = G_a(x - c_a). A source outside a non-periodic
-// axis is the halfway bounce-back of Eq. wall, h_a(x) = G_opp(a)(x), unless
-// the node is open, where the value is left for the Zou-He rule.
+// axis is the halfway bounce-back of Eq. wall, h_a(x) = G_opp(a)(x). On an
+// open node those directions are exactly the unknowns that the Zou-He rule
+// overwrites afterwards (rows touching a wall face are wall rows), so the
+// same rule serves every node and the load never depends on the row kind.
 template <class L, class S, class T>
 __device__ __forceinline__ void pull(const S* __restrict__ G, const Geo& g, int n, int x, int y,
-                                     int z, int oc, T h[L::Q]) {
+                                     int z, T h[L::Q]) {
     const int N = g.N;
     const bool interior = x > 0 && x < g.nx - 1 && y > 0 && y < g.ny - 1 &&
                           (L::D == 2 || (z > 0 && z < g.nz - 1));
@@ -133,13 +135,11 @@ __device__ __forceinline__ void pull(const S* __restrict__ G, const Geo& g, int 
             if (g.per_z) zs = zs < 0 ? zs + g.nz : zs - g.nz;
             else out = true;
         }
-        if (!out) {
-            h[a] = (T)plane(G, a, N)[(unsigned)((zs * g.ny + ys) * g.nx + xs)];
-        } else if (oc == 0) {
-            h[a] = (T)plane(G, L::opp[a], N)[(unsigned)n];
-        } else {
-            h[a] = (T)0;
-        }
+        // the plane is chosen by value (pointer arithmetic), so h keeps
+        // compile-time indices
+        const unsigned src = out ? (unsigned)n : (unsigned)((zs * g.ny + ys) * g.nx + xs);
+        const int pa = out ? L::opp[a] : a;
+        h[a] = (T)plane(G, pa, N)[src];
     }
 }
 
@@ -152,7 +152,7 @@ __device__ __forceinline__ void pull(const S* __restrict__ G, const Geo& g, int 
 // population is h_a = h_opp(a) + 6 w_a c_ax rho u_x - 1/2 sum_p c_ap N_p with
 // N_p = sum_{c_x=0} c_p h.
 template <class L, class T, int SGN>
-__device__ __forceinline__ void zou_he_face(const Geo& g, int kind, int y, T h[L::Q]) {
+__device__ __forceinline__ void zou_he_face(int kind, T u0, T d0, T h[L::Q]) {
     T b = 0, Ny = 0, Nz = 0;
 #pragma unroll
     for (int a = 0; a < L::Q; ++a) {
@@ -166,10 +166,8 @@ __device__ __forceinline__ void zou_he_face(const Geo& g, int kind, int y, T h[L
     }
     T rux;
     if (kind == ROW_VELOCITY) {
-        const T u0 = (T)g.u_in[y];
         rux = ((T)1 + b) * u0 / ((T)1 - u0);
     } else {
-        const T d0 = (T)g.drho_out;
         rux = SGN == 1 ? d0 - b : b - d0;
     }
 #pragma unroll
@@ -186,18 +184,24 @@ __device__ __forceinline__ void zou_he_face(const Geo& g, int kind, int y, T h[L
 // Both faces are evaluated and the result selected element by element, so
 // that every array index stays a compile-time constant (a branch per face
 // lets the compiler merge the two faces' stores into one with a selected
-// address, which moves the array to scratch memory).
+// address, which moves the array to scratch memory). u0 is the row's inlet
+// speed, d0 = rho_0 - 1 of the pressure rows.
 template <class L, class T>
-__device__ __forceinline__ void zou_he(const Geo& g, int oc, int y, T h[L::Q]) {
+__device__ __forceinline__ void zou_he_rows(int oc, T u0, T d0, T h[L::Q]) {
     const int kind = (oc - 1) % 3;
     const bool west = oc <= 3;
     T hw[L::Q], he[L::Q];
 #pragma unroll
     for (int a = 0; a < L::Q; ++a) hw[a] = he[a] = h[a];
-    zou_he_face<L, T, 1>(g, kind, y, hw);
-    zou_he_face<L, T, -1>(g, kind, y, he);
+    zou_he_face<L, T, 1>(kind, u0, d0, hw);
+    zou_he_face<L, T, -1>(kind, u0, d0, he);
 #pragma unroll
     for (int a = 0; a < L::Q; ++a) h[a] = west ? hw[a] : he[a];
+}
+
+template <class L, class T>
+__device__ __forceinline__ void zou_he(const Geo& g, int oc, int y, T h[L::Q]) {
+    zou_he_rows<L, T>(oc, (T)g.u_in[y], (T)g.drho_out, h);
 }
 
 // Transpose of zou_he on the adjoint populations mu of the post-boundary

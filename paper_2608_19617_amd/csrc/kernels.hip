@@ -106,7 +106,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const S* __restrict__ gin, S* __
         node_coords(g, n, x, y, z);
         const int oc = open_code<L>(g, x, y, z);
         T h[L::Q];
-        pull<L, S, T>(gin, g, n, x, y, z, oc, h);
+        pull<L, S, T>(gin, g, n, x, y, z, h);
         if (oc) zou_he<L, T>(g, oc, y, h);
         if (WPRE) {
 #pragma unroll
@@ -134,23 +134,61 @@ __global__ __launch_bounds__(BLOCK) void k_step(const S* __restrict__ gin, S* __
 // last step writes the tile to global memory. Only the last step may be a
 // sampled step (SAMPLE) or a checkpoint step (WPRE). Halo nodes are
 // recomputed by neighbouring tiles; every node update uses the same device
-// functions as the single-step kernel. LDS: two buffers of Q planes of
-// (ox + 2(NT-1)) x (oy + 2(NT-1)) values in compute precision and one plane
-// of the bounce-back fraction, read from global memory once. TB threads
-// (512 or 1024, whichever covers the first region in one round) update the
-// nodes of a region.
-// Cell i of the region [m, LW - m) x [m, LH - m): LDS coordinates and the
-// (wrapped) global node; false if the node lies outside the domain or, for
-// the output step, outside the tile's own part of the domain.
+// functions as the single-step kernel.
+//
+// Walls inside LDS: the LDS region keeps the cells beyond a non-periodic
+// face as ghost cells. A node on such a face stores every population that
+// would leave the domain into the ghost cell it would stream to, in the
+// plane of the opposite direction; the pull of that node at the next step
+// reads exactly that slot, which is the halfway bounce-back of Eq. wall.
+// The LDS pull is therefore the same gather for every node, with no
+// per-direction tests. The open-row codes and inlet speeds of the region's
+// rows are cached in LDS during step 1.
+//
+// LDS: two buffers of Q planes of (ox + 2(NT-1)) x (oy + 2(NT-1)) values in
+// compute precision, one plane of the bounce-back fraction (read from global
+// memory once), and the row cache. TB threads (512 or 1024, whichever
+// covers the first region in one round) update the nodes of a region.
+//
+// The region of a step is [m, LW - m) x [m, LH - m). Its cells are dealt
+// to threads row by row, except the column of an open x-face (at LDS x =
+// fc), which comes last: its nodes then share one or two wavefronts, so the
+// Zou-He and ghost-cell work does not diverge every wavefront of the tile.
+struct TbPhase {
+    int m, rwp, fc, nrow, count;   // margin, row width without column fc, fc or -1, cells before fc's
+    float inv;                     // 1 / rwp
+};
+
+__device__ __forceinline__ TbPhase tb_phase(int m, int LW, int LH, int fcol) {
+    TbPhase p;
+    p.m = m;
+    const int rw = LW - 2 * m, rh = LH - 2 * m;
+    p.fc = (fcol >= m && fcol < LW - m) ? fcol : -1;
+    p.rwp = p.fc >= 0 ? rw - 1 : rw;
+    p.nrow = p.rwp * rh;
+    p.count = rw * rh;
+    p.inv = 1.0f / (float)p.rwp;
+    return p;
+}
+
+// Cell i of a step's region: LDS coordinates and the (wrapped) global node;
+// false if the node lies outside the domain or, for the output step,
+// outside the tile's own part of the domain.
 struct TbCell {
     int lx, ly, x, y, n, cell;
 };
 
-__device__ __forceinline__ bool tb_cell(const Geo& g, int i, int m, int rw, float inv_rw, int LW, int x0,
-                                        int y0, bool output, TbCell& c) {
-    const int qy = (int)(((float)i + 0.5f) * inv_rw);   // exact for i < 2^12
-    c.ly = m + qy;
-    c.lx = m + (i - qy * rw);
+__device__ __forceinline__ bool tb_cell(const Geo& g, int i, const TbPhase& p, int LW, int x0, int y0,
+                                        bool output, TbCell& c) {
+    if (i < p.nrow) {
+        const int qy = (int)(((float)i + 0.5f) * p.inv);   // exact for i < 2^12
+        c.ly = p.m + qy;
+        c.lx = p.m + (i - qy * p.rwp);
+        if (p.fc >= 0 && c.lx >= p.fc) c.lx += 1;
+    } else {
+        c.ly = p.m + (i - p.nrow);
+        c.lx = p.fc;
+    }
     int x = x0 + c.lx, y = y0 + c.ly;
     if (output && (x >= g.nx || y >= g.ny)) return false;   // no wrapped duplicates in the output
     if (g.per_x) x = ((x % g.nx) + g.nx) % g.nx;
@@ -163,35 +201,101 @@ __device__ __forceinline__ bool tb_cell(const Geo& g, int i, int m, int rw, floa
     return true;
 }
 
-// Pull of node c from the previous step's LDS buffer, with the halfway wall
-// rule and the Zou-He rows (the same rules as pull() + zou_he()).
-template <class T>
-__device__ __forceinline__ void tb_pull_lds(const Geo& g, const T* __restrict__ srcb, int plane_sz, int LW,
-                                            const TbCell& c, T h[9]) {
-    using L = D2Q9;
-    const int oc = open_code<L>(g, c.x, c.y, 0);
-    const bool inner = (g.per_x || (c.x > 0 && c.x < g.nx - 1)) && (g.per_y || (c.y > 0 && c.y < g.ny - 1));
-    if (inner) {
-#pragma unroll
-        for (int a = 0; a < L::Q; ++a) h[a] = srcb[a * plane_sz + c.cell - L::cy[a] * LW - L::cx[a]];
-        return;
-    }
-#pragma unroll
-    for (int a = 0; a < L::Q; ++a) {
-        const int xs = c.x - L::cx[a], ys = c.y - L::cy[a];
-        const bool out = (!g.per_x && (xs < 0 || xs >= g.nx)) || (!g.per_y && (ys < 0 || ys >= g.ny));
-        if (!out) h[a] = srcb[a * plane_sz + c.cell - L::cy[a] * LW - L::cx[a]];
-        else if (oc == 0) h[a] = srcb[L::opp[a] * plane_sz + c.cell];
-        else h[a] = (T)0;
-    }
-    if (oc) zou_he<L, T>(g, oc, c.y, h);
+// True if cell c belongs to the tile's own output nodes (each node of the
+// domain is owned by exactly one tile).
+__device__ __forceinline__ bool tb_owned(const Geo& g, const TbCell& c, int H, int ox, int oy, int x0, int y0) {
+    const int ux = x0 + c.lx, uy = y0 + c.ly;
+    return c.lx >= H && c.lx < H + ox && c.ly >= H && c.ly < H + oy && ux < g.nx && uy < g.ny;
 }
 
-template <class S, class T, bool SAMPLE, bool WPRE, int TB>
+// Row cache of the LDS region (rows y0 .. y0 + LH - 1): Zou-He code of the
+// west and east face nodes (open_code's values) and the inlet speed.
+template <class T>
+struct TbRows {
+    T* u;
+    signed char* west;
+    signed char* east;
+};
+
+template <class T>
+__device__ __forceinline__ TbRows<T> tb_rows(T* base, int LH) {
+    TbRows<T> r;
+    r.u = base;
+    r.west = reinterpret_cast<signed char*>(base + LH);
+    r.east = r.west + LH;
+    return r;
+}
+
+template <class T, int TB>
+__device__ __forceinline__ void tb_fill_rows(const Geo& g, const TbRows<T>& r, int LH, int y0) {
+    for (int i = (int)threadIdx.x; i < LH; i += TB) {
+        int y = y0 + i;
+        if (g.per_y) y = ((y % g.ny) + g.ny) % g.ny;
+        signed char wc = 0, ec = 0;
+        T u = (T)0;
+        if (y >= 0 && y < g.ny) {
+            if (!g.per_x) {
+                const int kw = g.west[y], ke = g.east[y];
+                wc = (signed char)(kw ? 1 + kw : 0);
+                ec = (signed char)(ke ? 4 + ke : 0);
+            }
+            u = (T)g.u_in[y];
+        }
+        r.u[i] = u;
+        r.west[i] = wc;
+        r.east[i] = ec;
+    }
+}
+
+template <class T>
+__device__ __forceinline__ int tb_open(const Geo& g, const TbRows<T>& r, const TbCell& c) {
+    if (c.x == 0) return r.west[c.ly];
+    if (c.x == g.nx - 1) return r.east[c.ly];
+    return 0;
+}
+
+// Pull of node c from the previous step's LDS buffer (walls come from the
+// ghost cells), then the Zou-He rule on open nodes.
+template <class T>
+__device__ __forceinline__ void tb_pull_lds(const Geo& g, const T* __restrict__ srcb, int plane_sz, int LW,
+                                            const TbRows<T>& rows, T d0, const TbCell& c, T h[9]) {
+    using L = D2Q9;
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) h[a] = srcb[a * plane_sz + c.cell - L::cy[a] * LW - L::cx[a]];
+    const int oc = tb_open<T>(g, rows, c);
+    if (oc) zou_he_rows<L, T>(oc, rows.u[c.ly], d0, h);
+}
+
+// Ghost-cell stores of a node on a non-periodic face (see above). Every
+// direction is stored, the ones that stay in the domain to the thread's own
+// dump slot, so there is no branch per direction. Nodes on the region's
+// edge (only computed at step 1) pull nothing from LDS later and skip this.
+template <class T>
+__device__ __forceinline__ void tb_ghosts(const Geo& g, T* __restrict__ dst, T* __restrict__ dump, int plane_sz,
+                                          int LW, int LH, const TbCell& c, const T out[9]) {
+    using L = D2Q9;
+    const bool w = !g.per_x && c.x == 0, e = !g.per_x && c.x == g.nx - 1;
+    const bool s = !g.per_y && c.y == 0, n = !g.per_y && c.y == g.ny - 1;
+    const bool inner = c.lx >= 1 && c.ly >= 1 && c.lx <= LW - 2 && c.ly <= LH - 2;
+    if (!((w || e || s || n) && inner)) return;
+#pragma unroll
+    for (int a = 1; a < L::Q; ++a) {
+        const bool leaves = (L::cx[a] < 0 && w) || (L::cx[a] > 0 && e) || (L::cy[a] < 0 && s) ||
+                            (L::cy[a] > 0 && n);
+        T* p = leaves ? dst + L::opp[a] * plane_sz + c.cell + L::cy[a] * LW + L::cx[a] : dump;
+        *p = out[a];
+    }
+}
+
+// ALLOUT (recompute of an adjoint segment): every step t < nt also stores
+// the tile's post-collision state to allout + (t - 1) * slot (the step nt
+// state goes to gout as usual), so that each intermediate state is kept.
+template <class S, class T, bool SAMPLE, bool WPRE, int TB, bool ALLOUT>
 __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __restrict__ gout,
                                                 S* __restrict__ pre, const T* __restrict__ sfield,
                                                 Geo g, Phys ph, Obj ob, double* __restrict__ partials,
-                                                int part_stride, int nt, int ox, int oy, int tiles_x) {
+                                                int part_stride, int nt, int ox, int oy, int tiles_x,
+                                                S* __restrict__ allout, size_t slot) {
     using L = D2Q9;
     extern __shared__ unsigned char lds_raw[];
     T* lds = reinterpret_cast<T*>(lds_raw);
@@ -200,20 +304,29 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
     const int plane_sz = LW * LH;
     const int bufsz = L::Q * plane_sz;                // buffer b starts at lds + b * bufsz
     T* sbuf = lds + 2 * bufsz;                        // s of the region, loaded at step 1
+    T* dump = sbuf + plane_sz + threadIdx.x;          // this thread's dump slot
+    const TbRows<T> rows = tb_rows<T>(sbuf + plane_sz + TB, LH);
+    const T d0 = (T)g.drho_out;
     const int tx = (int)blockIdx.x % tiles_x, ty = (int)blockIdx.x / tiles_x;
     const int x0 = tx * ox - H, y0 = ty * oy - H;     // global coords of LDS cell (0, 0)
+    // LDS column of an open x-face in the region (west first), or -1
+    int fcol = -1;
+    if (!g.per_x) {
+        if (x0 <= 0) fcol = -x0;
+        else if (x0 + LW - 1 >= g.nx - 1) fcol = g.nx - 1 - x0;
+    }
 
     // step 1: pull from global memory over the whole LDS region
+    tb_fill_rows<T, TB>(g, rows, LH, y0);
     {
-        const int rw = LW, count = LW * LH;
-        const float inv_rw = 1.0f / (float)rw;
+        const TbPhase ph1 = tb_phase(0, LW, LH, fcol);
         T* dst = lds + bufsz;
-        for (int i = (int)threadIdx.x; i < count; i += TB) {
+        for (int i = (int)threadIdx.x; i < ph1.count; i += TB) {
             TbCell c;
-            if (!tb_cell(g, i, 0, rw, inv_rw, LW, x0, y0, false, c)) continue;
+            if (!tb_cell(g, i, ph1, LW, x0, y0, false, c)) continue;
             const int oc = open_code<L>(g, c.x, c.y, 0);
             T h[L::Q];
-            pull<L, S, T>(gin, g, c.n, c.x, c.y, 0, oc, h);
+            pull<L, S, T>(gin, g, c.n, c.x, c.y, 0, h);
             if (oc) zou_he<L, T>(g, oc, c.y, h);
             Moments<L, T> mo;
             moments<L, T>(h, ph, mo);
@@ -223,42 +336,49 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
             collide<L, T>(mo, sv, out);
 #pragma unroll
             for (int a = 0; a < L::Q; ++a) dst[a * plane_sz + c.cell] = out[a];
+            tb_ghosts<T>(g, dst, dump, plane_sz, LW, LH, c, out);
+            if (ALLOUT && tb_owned(g, c, H, ox, oy, x0, y0)) {
+#pragma unroll
+                for (int a = 0; a < L::Q; ++a) plane(allout, a, g.N)[(unsigned)c.n] = (S)out[a];
+            }
         }
         __syncthreads();
     }
     // steps 2 .. nt-1: LDS to LDS over shrinking regions
     for (int t = 2; t < nt; ++t) {
-        const int m = t - 1;
-        const int rw = LW - 2 * m, count = rw * (LH - 2 * m);
-        const float inv_rw = 1.0f / (float)rw;
+        const TbPhase pt = tb_phase(t - 1, LW, LH, fcol);
         T* dst = lds + (t & 1) * bufsz;
         const T* srcb = lds + ((t - 1) & 1) * bufsz;
-        for (int i = (int)threadIdx.x; i < count; i += TB) {
+        for (int i = (int)threadIdx.x; i < pt.count; i += TB) {
             TbCell c;
-            if (!tb_cell(g, i, m, rw, inv_rw, LW, x0, y0, false, c)) continue;
+            if (!tb_cell(g, i, pt, LW, x0, y0, false, c)) continue;
             T h[L::Q];
-            tb_pull_lds<T>(g, srcb, plane_sz, LW, c, h);
+            tb_pull_lds<T>(g, srcb, plane_sz, LW, rows, d0, c, h);
             Moments<L, T> mo;
             moments<L, T>(h, ph, mo);
             T out[L::Q];
             collide<L, T>(mo, sbuf[c.cell], out);
 #pragma unroll
             for (int a = 0; a < L::Q; ++a) dst[a * plane_sz + c.cell] = out[a];
+            tb_ghosts<T>(g, dst, dump, plane_sz, LW, LH, c, out);
+            if (ALLOUT && tb_owned(g, c, H, ox, oy, x0, y0)) {
+                S* o = allout + (size_t)(t - 1) * slot;
+#pragma unroll
+                for (int a = 0; a < L::Q; ++a) plane(o, a, g.N)[(unsigned)c.n] = (S)out[a];
+            }
         }
         __syncthreads();
     }
     // step nt: the output tile, from LDS to global memory (samples, checkpoint)
     double v[3] = {0.0, 0.0, 0.0};
     {
-        const int m = nt - 1;
-        const int rw = LW - 2 * m, count = rw * (LH - 2 * m);
-        const float inv_rw = 1.0f / (float)rw;
+        const TbPhase pn = tb_phase(nt - 1, LW, LH, fcol);
         const T* srcb = lds + ((nt - 1) & 1) * bufsz;
-        for (int i = (int)threadIdx.x; i < count; i += TB) {
+        for (int i = (int)threadIdx.x; i < pn.count; i += TB) {
             TbCell c;
-            if (!tb_cell(g, i, m, rw, inv_rw, LW, x0, y0, true, c)) continue;
+            if (!tb_cell(g, i, pn, LW, x0, y0, true, c)) continue;
             T h[L::Q];
-            tb_pull_lds<T>(g, srcb, plane_sz, LW, c, h);
+            tb_pull_lds<T>(g, srcb, plane_sz, LW, rows, d0, c, h);
             if (WPRE) {
 #pragma unroll
                 for (int a = 0; a < L::Q; ++a) plane(pre, a, g.N)[(unsigned)c.n] = (S)h[a];
@@ -332,7 +452,7 @@ __global__ __launch_bounds__(BLOCK) void k_export(const S* __restrict__ src, dou
         int x, y, z;
         node_coords(g, n, x, y, z);
         const int oc = open_code<L>(g, x, y, z);
-        pull<L, S, double>(src, g, n, x, y, z, oc, h);
+        pull<L, S, double>(src, g, n, x, y, z, h);
         if (oc) zou_he<L, double>(g, oc, y, h);
     }
     if (!FIELDS) {
@@ -388,7 +508,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(const A* __restrict__ nu_in, 
 #pragma unroll
         for (int a = 0; a < L::Q; ++a) h[a] = (T)plane(state, a, g.N)[(unsigned)n];
     } else {
-        pull<L, S, T>(state, g, n, x, y, z, oc, h);
+        pull<L, S, T>(state, g, n, x, y, z, h);
         if (oc) zou_he<L, T>(g, oc, y, h);
     }
     Moments<L, T> m;
@@ -519,20 +639,22 @@ __global__ __launch_bounds__(BLOCK) void k_copy_bytes(const unsigned int* __rest
 
 static inline dim3 grid_for(long n) { return dim3((unsigned)((n + BLOCK - 1) / BLOCK)); }
 
-template <class S, class T, bool SAMPLE, bool WPRE>
+template <class S, class T, bool SAMPLE, bool WPRE, bool ALLOUT>
 static void launch_tb(const StepLaunch& a) {
     const Geo& g = a.geo;
     const int tiles_x = (g.nx + a.tile_x - 1) / a.tile_x;
     const int tiles_y = (g.ny + a.tile_y - 1) / a.tile_y;
     const size_t lds = tb_lds_bytes(a.nsteps, a.tile_x, a.tile_y, sizeof(T));
     if (tb_threads(a.nsteps, a.tile_x, a.tile_y) == 512)
-        hipLaunchKernelGGL((k_step_tb<S, T, SAMPLE, WPRE, 512>), dim3(tiles_x * tiles_y), dim3(512), lds, a.stream,
-                           (const S*)a.gin, (S*)a.gout, (S*)a.pre, (const T*)a.s, g, a.ph, a.ob, a.partials,
-                           a.part_stride, a.nsteps, a.tile_x, a.tile_y, tiles_x);
+        hipLaunchKernelGGL((k_step_tb<S, T, SAMPLE, WPRE, 512, ALLOUT>), dim3(tiles_x * tiles_y), dim3(512), lds,
+                           a.stream, (const S*)a.gin, (S*)a.gout, (S*)a.pre, (const T*)a.s, g, a.ph, a.ob,
+                           a.partials, a.part_stride, a.nsteps, a.tile_x, a.tile_y, tiles_x, (S*)a.allout,
+                           a.allout_slot / sizeof(S));
     else
-        hipLaunchKernelGGL((k_step_tb<S, T, SAMPLE, WPRE, 1024>), dim3(tiles_x * tiles_y), dim3(1024), lds, a.stream,
-                           (const S*)a.gin, (S*)a.gout, (S*)a.pre, (const T*)a.s, g, a.ph, a.ob, a.partials,
-                           a.part_stride, a.nsteps, a.tile_x, a.tile_y, tiles_x);
+        hipLaunchKernelGGL((k_step_tb<S, T, SAMPLE, WPRE, 1024, ALLOUT>), dim3(tiles_x * tiles_y), dim3(1024), lds,
+                           a.stream, (const S*)a.gin, (S*)a.gout, (S*)a.pre, (const T*)a.s, g, a.ph, a.ob,
+                           a.partials, a.part_stride, a.nsteps, a.tile_x, a.tile_y, tiles_x, (S*)a.allout,
+                           a.allout_slot / sizeof(S));
 }
 
 template <class L, class S, class T>
@@ -544,12 +666,15 @@ static hipError_t step_t(const StepLaunch& a) {
     const T* sf = (const T*)a.s;
     if (a.nsteps > 1) {
         if (L::D != 2) return hipErrorInvalidValue;
-        if (a.sample) {
-            if (pre) launch_tb<S, T, true, true>(a);
-            else launch_tb<S, T, true, false>(a);
+        if (a.allout) {
+            if (a.sample || pre) return hipErrorInvalidValue;
+            launch_tb<S, T, false, false, true>(a);
+        } else if (a.sample) {
+            if (pre) launch_tb<S, T, true, true, false>(a);
+            else launch_tb<S, T, true, false, false>(a);
         } else {
-            if (pre) launch_tb<S, T, false, true>(a);
-            else launch_tb<S, T, false, false>(a);
+            if (pre) launch_tb<S, T, false, true, false>(a);
+            else launch_tb<S, T, false, false, false>(a);
         }
         return hipGetLastError();
     }
@@ -676,7 +801,8 @@ long blocks_for(long n) { return (n + BLOCK - 1) / BLOCK; }
 
 size_t tb_lds_bytes(int nsteps, int tile_x, int tile_y, size_t elem) {
     const size_t lw = tile_x + 2 * (nsteps - 1), lh = tile_y + 2 * (nsteps - 1);
-    return (2 * 9 + 1) * lw * lh * elem;
+    // state buffers, s plane, dump slots of up to 1024 threads, row cache
+    return (2 * 9 + 1) * lw * lh * elem + 1024 * elem + lh * (elem + 2);
 }
 
 long tb_blocks(int nx, int ny, int tile_x, int tile_y) {
@@ -690,10 +816,12 @@ int tb_threads(int nsteps, int tile_x, int tile_y) {
 
 template <class S, class T, int NT>
 static hipError_t tb_attr(int b) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_step_tb<S, T, false, false, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, true, false, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, false, true, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, true, true, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    const hipFuncAttribute at = hipFuncAttributeMaxDynamicSharedMemorySize;
+    hipError_t e = hipFuncSetAttribute((const void*)k_step_tb<S, T, false, false, NT, false>, at, b);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, true, false, NT, false>, at, b);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, false, true, NT, false>, at, b);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, true, true, NT, false>, at, b);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, false, false, NT, true>, at, b);
     return e;
 }
 

@@ -18,6 +18,8 @@ struct StepLaunch {
     int part_stride;       // partial slots per sample (unused slots are zeroed)
     int nsteps;            // 1: single step; > 1: temporally blocked launch (D2Q9)
     int tile_x, tile_y;    // output tile of a blocked launch
+    void* allout;          // blocked recompute: intermediate states go to allout + (t-1) * allout_slot bytes
+    size_t allout_slot;
     Geo geo;
     Phys ph;
     Obj ob;

@@ -393,6 +393,40 @@ def test_blocked_launches_match_single_steps(Solver, prec, case):
         assert rel_l2(g, g1) <= 100 * tol
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("case", [0, 1, 2, 3])
+def test_long_blocks_match_single_steps(Solver, prec, case):
+    """Long blocked launches (8 and 10 steps, halos of 7 and 9 nodes; FP64,
+    whose LDS holds fewer values, 4 and 7 steps), so the ghost cells of the
+    walls and the open-face column are reused over many LDS steps, and the
+    blocked recompute of the adjoint sweep (segments of 20 steps) against
+    single-step launches."""
+    name, w = _small_cases()[case]
+    w.window_len, w.sample_every, w.ckpt_every, w.max_windows = 40, 20, 20, 2
+    prob = oracle_problem(w)
+    f0 = random_start_state(prob, seed=5)
+    tol = {"f64": 1e-13, "f32": 1e-6, "f16s": 1e-3}[prec]
+    res = {}
+    blocks = ((4, (25, 25)), (7, (16, 16))) if prec == "f64" else ((8, (25, 25)), (10, (16, 16)))
+    for nt, tile in ((1, (32, 16)),) + blocks:
+        sv = Solver(w, prec)
+        sv.set_blocking(nt, *tile)
+        sv.set_state(f0, 0)
+        sv.forward(2 * w.window_len)
+        f, step = sv.get_state()
+        J, M, _ = sv.history()
+        g, _ = sv.adjoint()
+        assert step == 2 * w.window_len
+        res[nt] = (f, J, g.cpu().numpy())
+        sv.close()
+    f1, J1, g1 = res[1]
+    for nt, _ in blocks:
+        f, J, g = res[nt]
+        assert rel_l2(f, f1) <= tol, (nt, rel_l2(f, f1))
+        assert np.max(np.abs(J - J1)) <= tol * np.max(np.abs(J1)) + 1e-15
+        assert rel_l2(g, g1) <= 100 * tol
+
+
 # ------------------------------------------------- full-size configurations
 #
 # At full size the oracle cannot replay whole windows in a test, so the GPU
