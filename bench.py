@@ -235,7 +235,7 @@ def main():
     # forward time per step over all forward launches (blocked and single)
     fwd_steps = tm["tb_steps"] + tm["fwd_launches"]
     fwd_step_s = (tm["tb_ms"] + tm["fwd_ms"]) * 1e-3 / fwd_steps
-    adj_avg_s = tm["adj_ms"] / tm["adj_launches"] * 1e-3
+    adj_step_s = tm["adj_ms"] / tm["adj_steps"] * 1e-3
     # dominant kernel: the temporally blocked forward kernel when it is used
     if tm["tb_launches"] > 0 and tm["tb_ms"] >= tm["fwd_ms"]:
         kname = "k_step_tb (forward, temporally blocked)"
@@ -268,9 +268,11 @@ def main():
                      "steps_per_launch": round(steps_per_launch, 3),
                      "avg_launch_us": round(launch_s * 1e6, 3)},
         "fwd_mlups": round(N / fwd_step_s / 1e6, 1),
-        "adj_kernel_mlups": round(N / adj_avg_s / 1e6, 1),
-        "adj_kernel": {"avg_launch_us": round(adj_avg_s * 1e6, 3), "bytes_per_lup": ADJ_BYTES[args.prec],
-                       "achieved_GBs": round(ADJ_BYTES[args.prec] * N / adj_avg_s / 1e9, 1)},
+        "adj_kernel_mlups": round(N / adj_step_s / 1e6, 1),
+        "adj_kernel": {"avg_launch_us": round(tm["adj_ms"] / tm["adj_launches"] * 1e3, 3),
+                       "steps_per_launch": round(tm["adj_steps"] / tm["adj_launches"], 3),
+                       "us_per_step": round(adj_step_s * 1e6, 3), "bytes_per_lup": ADJ_BYTES[args.prec],
+                       "achieved_GBs": round(ADJ_BYTES[args.prec] * N / adj_step_s / 1e9, 1)},
         "recompute": {"avg_launch_us": round(tm["rec_ms"] / max(tm["rec_launches"], 1) * 1e3, 3),
                       "us_per_step": round(tm["rec_ms"] / max(tm["rec_steps"], 1) * 1e3, 3),
                       "steps_per_launch": round(tm["rec_steps"] / max(tm["rec_launches"], 1), 3)},

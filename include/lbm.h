@@ -197,7 +197,8 @@ lbm_status lbm_get_fields(lbm_ctx* ctx, double* rho_u_dev);
  * gaps between consecutive launches. A fourth pair counts the temporally
  * blocked forward launches; the ninth double is the steps they advanced and
  * the tenth the steps advanced by the recompute launches, which are also
- * blocked where the forward is (10 doubles in all). */
+ * blocked where the forward is, the eleventh the steps advanced by the
+ * adjoint launches (11 doubles in all). */
 lbm_status lbm_timing(lbm_ctx* ctx, int enable, double* out);
 
 /* Temporal blocking of forward launches (D2Q9 only): each launch advances
@@ -216,7 +217,10 @@ lbm_status lbm_timing(lbm_ctx* ctx, int enable, double* out);
  * (FP32, FP16S) or 4 steps (FP64); larger grids 6 steps on 64 x 16 tiles
  * (FP32), 6 steps on 32 x 32 (FP16S), 3 steps on 32 x 8 (FP64). The
  * recompute of the adjoint sweep uses the same blocking, storing every
- * intermediate state. */
+ * intermediate state; the adjoint steps that pull their pre-state from a
+ * recomputed segment run blocked on the same tiles, with as many steps per
+ * launch as their LDS (which adds an FP64 sensitivity plane of the tile)
+ * allows. */
 lbm_status lbm_set_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y);
 
 /* Thread-local message of the last failing call on this thread. */

@@ -169,6 +169,7 @@ struct lbm_ctx {
     std::vector<int> conv;
     bool unstable;
     int tb_steps, tile_x, tile_y;    // temporal blocking of forward launches (1 = off)
+    int adj_steps;                   // steps per blocked adjoint launch (1 = off)
     Timer tm;
 };
 
@@ -374,14 +375,18 @@ lbm_status set_blocking(lbm_ctx* c, int nsteps, int tile_x, int tile_y) {
         if (tile_x < 1 || tile_y < 1 || (long)tile_x * tile_y < 256)
             return fail(LBM_E_INVALID, "tile must hold at least 256 nodes");
         const size_t lds = tb_lds_bytes(nsteps, tile_x, tile_y, c->L.cs);
-        if (lds > 159 * 1024) return fail(LBM_E_INVALID, "tile and nsteps need more than 159 KB of LDS");
+        if (lds > TB_LDS_MAX) return fail(LBM_E_INVALID, "tile and nsteps need more than 159 KB of LDS");
         if (tb_blocks(c->cfg.nx, c->cfg.ny, tile_x, tile_y) > c->L.pstride)
             return fail(LBM_E_INVALID, "too many tiles");
-        HIPCHK(tb_prepare(c->cfg.prec, lds));
+        HIPCHK(tb_prepare(c->cfg.prec));
         c->tile_x = tile_x;
         c->tile_y = tile_y;
     }
     c->tb_steps = nsteps;
+    // the blocked adjoint uses the same tiles, as many steps as its LDS allows
+    int na = nsteps;
+    while (na > 1 && adj_tb_lds_bytes(na, tile_x, tile_y, c->L.cs) > TB_LDS_MAX) --na;
+    c->adj_steps = na;
     return LBM_OK;
 }
 
@@ -486,6 +491,7 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
     c->cur = 0;
     c->unstable = false;
     c->tb_steps = 1;
+    c->adj_steps = 1;
     c->tile_x = 32;
     c->tile_y = 16;
 
@@ -524,7 +530,7 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
             t = t < 16 ? 16 : (t > 25 ? 25 : t);
             tx = ty = t;
             nt = cfg->prec == LBM_F64 ? 4 : 10;
-            while (nt > 2 && tb_lds_bytes(nt, tx, ty, L.cs) > 159 * 1024) --nt;
+            while (nt > 2 && tb_lds_bytes(nt, tx, ty, L.cs) > TB_LDS_MAX) --nt;
         } else if (cfg->prec == LBM_F32) {
             nt = 6;
             tx = 64;
@@ -672,9 +678,18 @@ lbm_status lbm_adjoint(lbm_ctx* c, int window, double* dJdgamma_dev, double* J_o
     aa.ph = c->ph;
     aa.ob = c->ob;
     aa.stream = c->stream;
+    aa.nsteps = 1;
+    aa.tile_x = c->tile_x;
+    aa.tile_y = c->tile_y;
+    aa.gseg = c->seg[0];
+    aa.slot = L.SB;
+    aa.ns = ns;
+    aa.dW = dW;
+    aa.wgt = wgt;
     int cur = 0;
     for (int seg = L.R - 1; seg >= 0; --seg) {
         const long c0 = ns - 1 + (long)seg * K;       // checkpoint step
+        aa.kseg = c0;
         const bool last = seg == L.R - 1;
         const long nrec = last ? K - 1 : K - 2;       // step launches after the restart
         if (last || K >= 2) {
@@ -710,21 +725,31 @@ lbm_status lbm_adjoint(lbm_ctx* c, int window, double* dJdgamma_dev, double* J_o
             aa.src_w = wgt;
             HIPCHK(launch_adjoint(aa));
         }
-        for (long k = c0 + K; k >= c0 + 1; --k) {
+        for (long k = c0 + K; k >= c0 + 1;) {
             aa.nu_in = c->nu[cur];
             aa.nu_out = c->nu[cur ^ 1];
             aa.seed = 0;
+            aa.nsteps = 1;
+            long n = 1;
             if (k - 1 == c0) {
                 aa.direct = 1;
                 aa.state = c->ring[p][seg];
             } else {
+                // steps k .. c0 + 2 pull their pre-state from the segment
                 aa.direct = 0;
                 aa.state = c->seg[k - 2 - c0];
+                n = k - (c0 + 1);
+                if (n > c->adj_steps) n = c->adj_steps;
+                if (n > 1) {
+                    aa.nsteps = (int)n;
+                    aa.k_hi = k;
+                }
             }
             aa.src_w = (k > ns && (k - ns) % dW == 0) ? wgt : 0.0;
-            if ((st = t_launch(c, 1)) != LBM_OK) return st;
+            if ((st = t_launch(c, 1, n)) != LBM_OK) return st;
             HIPCHK(launch_adjoint(aa));
             cur ^= 1;
+            k -= n;
         }
         if ((st = t_close(c)) != LBM_OK) return st;
     }
@@ -822,6 +847,7 @@ lbm_status lbm_timing(lbm_ctx* c, int enable, double* out) {
         }
         out[8] = c->tm.st[3];
         out[9] = c->tm.st[2];
+        out[10] = c->tm.st[1];
     }
     if (enable) {
         if (c->tm.ev.empty()) {

@@ -212,10 +212,9 @@ __device__ __forceinline__ void zou_he(const Geo& g, int oc, int y, T h[L::Q]) {
 // A = 6 chi sum_{entering} w_a c_ax mu_a and B_p = 1/2 sum_{entering} c_ap mu_a.
 // For D2Q9 this is Eqs. adjoint_inlet_bc and adjoint_outlet_bc.
 template <class L, class T, int SGN>
-__device__ __forceinline__ void zou_he_adjoint_face(const Geo& g, int kind, int y, T mu[L::Q]) {
+__device__ __forceinline__ void zou_he_adjoint_face(int kind, T u0, T mu[L::Q]) {
     T chi;
     if (kind == ROW_VELOCITY) {
-        const T u0 = (T)g.u_in[y];
         chi = u0 / ((T)1 - u0);
     } else {
         chi = SGN == 1 ? (T)-1 : (T)1;
@@ -248,17 +247,24 @@ __device__ __forceinline__ void zou_he_adjoint_face(const Geo& g, int kind, int 
     for (int a = 0; a < L::Q; ++a) mu[a] = out[a];
 }
 
+// u0 is the row's inlet speed; both faces are evaluated and selected by
+// value (see zou_he_rows).
 template <class L, class T>
-__device__ __forceinline__ void zou_he_adjoint(const Geo& g, int oc, int y, T mu[L::Q]) {
+__device__ __forceinline__ void zou_he_adjoint_rows(int oc, T u0, T mu[L::Q]) {
     const int kind = (oc - 1) % 3;
     const bool west = oc <= 3;
     T mw[L::Q], me[L::Q];
 #pragma unroll
     for (int a = 0; a < L::Q; ++a) mw[a] = me[a] = mu[a];
-    zou_he_adjoint_face<L, T, 1>(g, kind, y, mw);
-    zou_he_adjoint_face<L, T, -1>(g, kind, y, me);
+    zou_he_adjoint_face<L, T, 1>(kind, u0, mw);
+    zou_he_adjoint_face<L, T, -1>(kind, u0, me);
 #pragma unroll
     for (int a = 0; a < L::Q; ++a) mu[a] = west ? mw[a] : me[a];
+}
+
+template <class L, class T>
+__device__ __forceinline__ void zou_he_adjoint(const Geo& g, int oc, int y, T mu[L::Q]) {
+    zou_he_adjoint_rows<L, T>(oc, (T)g.u_in[y], mu);
 }
 
 // Symmetric-tensor helpers over D x D, stored as the upper triangle in the

@@ -201,6 +201,20 @@ __device__ __forceinline__ bool tb_cell(const Geo& g, int i, const TbPhase& p, i
     return true;
 }
 
+// Tile of this workgroup. Workgroups are dealt to the 8 XCDs of the chip
+// round-robin (workgroup b runs on XCD b mod 8). The tiles are numbered down
+// the columns and each XCD takes a contiguous run of those numbers, so that
+// neighbouring tiles, whose halos overlap, mostly share an XCD and its L2.
+__device__ __forceinline__ void tb_tile(int tiles_x, int& tx, int& ty) {
+    const int T = (int)gridDim.x, tiles_y = T / tiles_x;
+    const int b = (int)blockIdx.x, xcd = b & 7, idx = b >> 3;
+    int start = 0;
+    for (int k = 0; k < xcd; ++k) start += (T - k + 7) >> 3;   // workgroups on XCDs before this one
+    const int t = start + idx;
+    tx = t / tiles_y;
+    ty = t - tx * tiles_y;
+}
+
 // True if cell c belongs to the tile's own output nodes (each node of the
 // domain is owned by exactly one tile).
 __device__ __forceinline__ bool tb_owned(const Geo& g, const TbCell& c, int H, int ox, int oy, int x0, int y0) {
@@ -307,7 +321,8 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
     T* dump = sbuf + plane_sz + threadIdx.x;          // this thread's dump slot
     const TbRows<T> rows = tb_rows<T>(sbuf + plane_sz + TB, LH);
     const T d0 = (T)g.drho_out;
-    const int tx = (int)blockIdx.x % tiles_x, ty = (int)blockIdx.x / tiles_x;
+    int tx, ty;
+    tb_tile(tiles_x, tx, ty);
     const int x0 = tx * ox - H, y0 = ty * oy - H;     // global coords of LDS cell (0, 0)
     // LDS column of an open x-face in the region (west first), or -1
     int fcol = -1;
@@ -482,6 +497,18 @@ __global__ __launch_bounds__(BLOCK) void k_import(const double* __restrict__ f, 
     for (int a = 0; a < L::Q; ++a) plane(pre, a, g.N)[(unsigned)n] = (S)(plane(f, a, g.N)[(unsigned)n] - L::w[a]);
 }
 
+// Sampled-objective source on the adjoint moments of node (x, y): the
+// pressure-drop sections and, for the dissipation objective, its gradient.
+template <class L, class T>
+__device__ __forceinline__ void adjoint_source(const Obj& ob, const Phys& ph, int x, int y, const Moments<L, T>& m,
+                                               double src_w, MomentGrad<L, T>& gr) {
+    T dp = 0;
+    if (x == ob.in_x && y >= ob.in_lo && y < ob.in_hi) dp += (T)((1.0 / 3.0) * ob.inv_nin * src_w);
+    if (x == ob.out_x && y >= ob.out_lo && y < ob.out_hi) dp -= (T)((1.0 / 3.0) * ob.inv_nout * src_w);
+    gr.gr += dp;
+    if (ob.obj == 1) dissipation_adjoint<L, T>(m, ph, (T)src_w, gr);
+}
+
 // Adjoint step for transition k (f^{k-1} -> f^k), reverse order.
 //   kappa_a(y) = nu_hat_a(y + c_a)  (adjoint streaming), with the adjoint
 //   wall rule kappa_a(y) = nu_hat_opp(a)(y) where y + c_a leaves through a
@@ -556,18 +583,154 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(const A* __restrict__ nu_in, 
         const T ds = collide_adjoint<L, T>(m, ph, s, kap, gr);
         sens[n] += (double)ds;
     }
-    if (src_w != 0.0) {
-        T dp = 0;
-        if (x == ob.in_x && y >= ob.in_lo && y < ob.in_hi) dp += (T)((1.0 / 3.0) * ob.inv_nin * src_w);
-        if (x == ob.out_x && y >= ob.out_lo && y < ob.out_hi) dp -= (T)((1.0 / 3.0) * ob.inv_nout * src_w);
-        gr.gr += dp;
-        if (ob.obj == 1) dissipation_adjoint<L, T>(m, ph, (T)src_w, gr);
-    }
+    if (src_w != 0.0) adjoint_source<L, T>(ob, ph, x, y, m, src_w, gr);
     T mu[L::Q];
     expand<L, T>(m, gr, mu);
     if (oc) zou_he_adjoint<L, T>(g, oc, y, mu);
 #pragma unroll
     for (int a = 0; a < L::Q; ++a) plane(nu_out, a, g.N)[(unsigned)n] = (A)mu[a];
+}
+
+// Temporally blocked adjoint steps (D2Q9) over a recomputed segment: one
+// launch takes nu_hat^{k_hi} to nu_hat^{k_hi - nt}. Step t (t = 1 .. nt) is
+// the transition k = k_hi - t + 1, whose pre-state f^{k-1} is pulled from
+// the post-collision state G^{k-2} = gseg + (k - 2 - kseg) * slot (global
+// memory; every step of a segment is stored by the blocked recompute). The
+// adjoint populations stay in LDS between steps, on tiles grown by nt - 1
+// nodes per side as in the forward blocked kernel. Adjoint streaming gathers
+// kappa_a(y) = nu_hat_a(y + c_a); for a direction leaving through a wall it
+// is nu_hat_opp(a)(y), for one leaving through an open face 0. In LDS both
+// come from ghost cells: after its step a face node stores, for every b
+// with y - c_b outside the domain, nu_hat_b(y) (0 on an open node) at
+// y - c_b in plane opp(b), the slot it gathers kappa_opp(b) from next. The
+// sensitivity of the tile's own nodes is summed over the launch's steps in
+// an FP64 LDS plane and added to global memory once.
+template <class S, class T, class A, int TB>
+__global__ __launch_bounds__(TB) void k_adjoint_tb(const A* __restrict__ nu_in, A* __restrict__ nu_out,
+                                                   const S* __restrict__ gseg, size_t slot, long kseg,
+                                                   const T* __restrict__ sfield, double* __restrict__ sens,
+                                                   Geo g, Phys ph, Obj ob, long k_hi, long ns, long dW, double wgt,
+                                                   int nt, int ox, int oy, int tiles_x) {
+    using L = D2Q9;
+    extern __shared__ unsigned char lds_raw[];
+    double* sacc = reinterpret_cast<double*>(lds_raw);   // ox * oy sensitivity sums
+    T* lds = reinterpret_cast<T*>(sacc + ox * oy);
+    const int H = nt - 1;
+    const int LW = ox + 2 * H, LH = oy + 2 * H;
+    const int plane_sz = LW * LH;
+    const int bufsz = L::Q * plane_sz;
+    T* sbuf = lds + 2 * bufsz;
+    T* dump = sbuf + plane_sz + threadIdx.x;
+    const TbRows<T> rows = tb_rows<T>(sbuf + plane_sz + TB, LH);
+    const T d0 = (T)g.drho_out;
+    int tx, ty;
+    tb_tile(tiles_x, tx, ty);
+    const int x0 = tx * ox - H, y0 = ty * oy - H;
+    int fcol = -1;
+    if (!g.per_x) {
+        if (x0 <= 0) fcol = -x0;
+        else if (x0 + LW - 1 >= g.nx - 1) fcol = g.nx - 1 - x0;
+    }
+    tb_fill_rows<T, TB>(g, rows, LH, y0);
+    __syncthreads();
+    for (int t = 1; t <= nt; ++t) {
+        const long k = k_hi - t + 1;
+        const S* Gk2 = gseg + (size_t)(k - 2 - kseg) * slot;
+        const double src_w = (k > ns && (k - ns) % dW == 0) ? wgt : 0.0;
+        const TbPhase pt = tb_phase(t - 1, LW, LH, fcol);
+        const T* srcb = lds + ((t - 1) & 1) * bufsz;
+        T* dst = lds + (t & 1) * bufsz;
+        const bool last = t == nt;
+        for (int i = (int)threadIdx.x; i < pt.count; i += TB) {
+            TbCell c;
+            if (!tb_cell(g, i, pt, LW, x0, y0, last, c)) continue;
+            const int oc = tb_open<T>(g, rows, c);
+            const T u0 = rows.u[c.ly];
+            // pre-state f^{k-1}
+            T h[L::Q];
+            pull<L, S, T>(Gk2, g, c.n, c.x, c.y, 0, h);
+            if (oc) zou_he_rows<L, T>(oc, u0, d0, h);
+            Moments<L, T> m;
+            moments<L, T>(h, ph, m);
+            // adjoint streaming
+            T kap[L::Q];
+            if (t == 1) {
+                const bool interior = c.x > 0 && c.x < g.nx - 1 && c.y > 0 && c.y < g.ny - 1;
+                if (interior) {
+#pragma unroll
+                    for (int a = 0; a < L::Q; ++a)
+                        kap[a] = (T)plane(nu_in, a, g.N)[(unsigned)(c.n + L::cx[a] + L::cy[a] * g.nx)];
+                } else {
+#pragma unroll
+                    for (int a = 0; a < L::Q; ++a) {
+                        int xt = c.x + L::cx[a], yt = c.y + L::cy[a];
+                        bool out = false;
+                        if (xt < 0 || xt >= g.nx) {
+                            if (g.per_x) xt = xt < 0 ? xt + g.nx : xt - g.nx;
+                            else out = true;
+                        }
+                        if (yt < 0 || yt >= g.ny) {
+                            if (g.per_y) yt = yt < 0 ? yt + g.ny : yt - g.ny;
+                            else out = true;
+                        }
+                        const unsigned src = out ? (unsigned)c.n : (unsigned)(yt * g.nx + xt);
+                        const int pa = out ? L::opp[a] : a;
+                        const T v = (T)plane(nu_in, pa, g.N)[src];
+                        kap[a] = (out && oc) ? (T)0 : v;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int a = 0; a < L::Q; ++a) kap[a] = srcb[a * plane_sz + c.cell + L::cy[a] * LW + L::cx[a]];
+            }
+            T s;
+            if (t == 1) {
+                s = sfield[c.n];
+                sbuf[c.cell] = s;
+            } else {
+                s = sbuf[c.cell];
+            }
+            MomentGrad<L, T> gr;
+            gr.gr = 0;
+#pragma unroll
+            for (int p = 0; p < L::D; ++p) gr.gj[p] = 0;
+#pragma unroll
+            for (int q = 0; q < Sym<L::D>::K; ++q) gr.GP[q] = 0;
+            const T ds = collide_adjoint<L, T>(m, ph, s, kap, gr);
+            if (tb_owned(g, c, H, ox, oy, x0, y0)) {
+                const int o = (c.ly - H) * ox + (c.lx - H);
+                if (t == 1) sacc[o] = (double)ds;
+                else if (!last) sacc[o] += (double)ds;
+                else sens[c.n] += sacc[o] + (double)ds;
+            }
+            if (src_w != 0.0) adjoint_source<L, T>(ob, ph, c.x, c.y, m, src_w, gr);
+            T mu[L::Q];
+            expand<L, T>(m, gr, mu);
+            if (oc) zou_he_adjoint_rows<L, T>(oc, u0, mu);
+            if (last) {
+#pragma unroll
+                for (int a = 0; a < L::Q; ++a) plane(nu_out, a, g.N)[(unsigned)c.n] = (A)mu[a];
+            } else {
+#pragma unroll
+                for (int a = 0; a < L::Q; ++a) dst[a * plane_sz + c.cell] = mu[a];
+                // ghost cells of the adjoint wall rule
+                const bool w = !g.per_x && c.x == 0, e = !g.per_x && c.x == g.nx - 1;
+                const bool so = !g.per_y && c.y == 0, no = !g.per_y && c.y == g.ny - 1;
+                const bool inner = c.lx >= 1 && c.ly >= 1 && c.lx <= LW - 2 && c.ly <= LH - 2;
+                if ((w || e || so || no) && inner) {
+#pragma unroll
+                    for (int b = 1; b < L::Q; ++b) {
+                        // y - c_b leaves the domain
+                        const bool leaves = (L::cx[b] > 0 && w) || (L::cx[b] < 0 && e) || (L::cy[b] > 0 && so) ||
+                                            (L::cy[b] < 0 && no);
+                        T* p = leaves ? dst + L::opp[b] * plane_sz + c.cell - L::cy[b] * LW - L::cx[b] : dump;
+                        *p = oc ? (T)0 : mu[b];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // Per-sample sums of the block partials in a fixed order (deterministic).
@@ -698,7 +861,23 @@ static hipError_t adj_t(const AdjLaunch& a) {
     A* nout = (A*)a.nu_out;
     const S* st = (const S*)a.state;
     const T* sf = (const T*)a.s;
-    if (a.seed) {
+    if (L::D == 2 && a.nsteps > 1) {
+        if (a.seed || a.direct) return hipErrorInvalidValue;
+        const int tiles_x = (g.nx + a.tile_x - 1) / a.tile_x;
+        const int tiles_y = (g.ny + a.tile_y - 1) / a.tile_y;
+        const size_t lds = adj_tb_lds_bytes(a.nsteps, a.tile_x, a.tile_y, sizeof(T));
+        const int tb = tb_threads(a.nsteps, a.tile_x, a.tile_y);
+        const S* gs = (const S*)a.gseg;
+        const size_t slot = a.slot / sizeof(S);
+        if (tb == 512)
+            hipLaunchKernelGGL((k_adjoint_tb<S, T, A, 512>), dim3(tiles_x * tiles_y), dim3(512), lds, a.stream, nin, nout,
+                               gs, slot, a.kseg, sf, a.sens, g, a.ph, a.ob, a.k_hi, a.ns, a.dW, a.wgt, a.nsteps,
+                               a.tile_x, a.tile_y, tiles_x);
+        else
+            hipLaunchKernelGGL((k_adjoint_tb<S, T, A, 1024>), dim3(tiles_x * tiles_y), dim3(1024), lds, a.stream, nin,
+                               nout, gs, slot, a.kseg, sf, a.sens, g, a.ph, a.ob, a.k_hi, a.ns, a.dW, a.wgt, a.nsteps,
+                               a.tile_x, a.tile_y, tiles_x);
+    } else if (a.seed) {
         hipLaunchKernelGGL((k_adjoint<L, S, T, A, false, true>), gr, dim3(BLOCK), 0, a.stream, nin, nout, st, sf, a.sens, g, a.ph, a.ob, a.src_w);
     } else if (a.direct) {
         hipLaunchKernelGGL((k_adjoint<L, S, T, A, true, false>), gr, dim3(BLOCK), 0, a.stream, nin, nout, st, sf, a.sens, g, a.ph, a.ob, a.src_w);
@@ -805,6 +984,11 @@ size_t tb_lds_bytes(int nsteps, int tile_x, int tile_y, size_t elem) {
     return (2 * 9 + 1) * lw * lh * elem + 1024 * elem + lh * (elem + 2);
 }
 
+size_t adj_tb_lds_bytes(int nsteps, int tile_x, int tile_y, size_t elem) {
+    // sensitivity sums of the tile (FP64), then the forward kernel's layout
+    return (size_t)tile_x * tile_y * 8 + tb_lds_bytes(nsteps, tile_x, tile_y, elem);
+}
+
 long tb_blocks(int nx, int ny, int tile_x, int tile_y) {
     return (long)((nx + tile_x - 1) / tile_x) * ((ny + tile_y - 1) / tile_y);
 }
@@ -814,7 +998,7 @@ int tb_threads(int nsteps, int tile_x, int tile_y) {
     return lw * lh <= 512 ? 512 : 1024;
 }
 
-template <class S, class T, int NT>
+template <class S, class T, class A, int NT>
 static hipError_t tb_attr(int b) {
     const hipFuncAttribute at = hipFuncAttributeMaxDynamicSharedMemorySize;
     hipError_t e = hipFuncSetAttribute((const void*)k_step_tb<S, T, false, false, NT, false>, at, b);
@@ -822,22 +1006,24 @@ static hipError_t tb_attr(int b) {
     if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, false, true, NT, false>, at, b);
     if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, true, true, NT, false>, at, b);
     if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, false, false, NT, true>, at, b);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_adjoint_tb<S, T, A, NT>, at, b);
     return e;
 }
 
-hipError_t tb_prepare(int prec, size_t lds_bytes) {
-    // opt in to more than 64 KB of dynamic LDS per workgroup
-    const int b = (int)lds_bytes;
+hipError_t tb_prepare(int prec) {
+    // opt in to the LDS of a compute unit (beyond the default 64 KB) for the
+    // blocked kernels; launches check their own size against TB_LDS_MAX
+    const int b = (int)TB_LDS_MAX;
     hipError_t e;
     if (prec == 0) {
-        e = tb_attr<double, double, 512>(b);
-        if (e == hipSuccess) e = tb_attr<double, double, 1024>(b);
+        e = tb_attr<double, double, double, 512>(b);
+        if (e == hipSuccess) e = tb_attr<double, double, double, 1024>(b);
     } else if (prec == 1) {
-        e = tb_attr<float, float, 512>(b);
-        if (e == hipSuccess) e = tb_attr<float, float, 1024>(b);
+        e = tb_attr<float, float, float, 512>(b);
+        if (e == hipSuccess) e = tb_attr<float, float, float, 1024>(b);
     } else {
-        e = tb_attr<_Float16, float, 512>(b);
-        if (e == hipSuccess) e = tb_attr<_Float16, float, 1024>(b);
+        e = tb_attr<_Float16, float, float, 512>(b);
+        if (e == hipSuccess) e = tb_attr<_Float16, float, float, 1024>(b);
     }
     return e;
 }

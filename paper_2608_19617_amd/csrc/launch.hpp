@@ -35,6 +35,13 @@ struct AdjLaunch {
     double* sens;
     int direct, seed;
     double src_w;          // weight of the objective source on f^{k-1} (0: none)
+    // blocked launch (nsteps > 1, D2Q9): steps k_hi .. k_hi - nsteps + 1, all
+    // pulling their pre-state from G^{k-2} = gseg + (k - 2 - kseg) * slot bytes
+    int nsteps, tile_x, tile_y;
+    const void* gseg;
+    size_t slot;
+    long kseg, k_hi, ns, dW;
+    double wgt;
     Geo geo;
     Phys ph;
     Obj ob;
@@ -67,6 +74,9 @@ struct AuxLaunch {
     hipStream_t stream;
 };
 
+// LDS a blocked launch may use (of the 160 KB of a compute unit)
+constexpr size_t TB_LDS_MAX = 159 * 1024;
+
 hipError_t launch_step(const StepLaunch& a);
 hipError_t launch_adjoint(const AdjLaunch& a);
 hipError_t launch_aux(const AuxLaunch& a);
@@ -78,8 +88,9 @@ hipError_t launch_fill(double* p, long n, double v, hipStream_t stream);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
 long blocks_for(long n);
 size_t tb_lds_bytes(int nsteps, int tile_x, int tile_y, size_t elem);
+size_t adj_tb_lds_bytes(int nsteps, int tile_x, int tile_y, size_t elem);
 long tb_blocks(int nx, int ny, int tile_x, int tile_y);
-hipError_t tb_prepare(int prec, size_t lds_bytes);
+hipError_t tb_prepare(int prec);
 int tb_threads(int nsteps, int tile_x, int tile_y);
 
 }  // namespace lbm

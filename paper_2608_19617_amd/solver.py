@@ -184,11 +184,11 @@ class Solver:
         return out.reshape(rev).permute(0, *range(len(rev) - 1, 0, -1))
 
     def timing(self, enable):
-        out = np.zeros(10)
+        out = np.zeros(11)
         B.check(B.lib.lbm_timing(self._ctx, int(bool(enable)), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return {"fwd_launches": out[0], "fwd_ms": out[1], "adj_launches": out[2], "adj_ms": out[3],
                 "rec_launches": out[4], "rec_ms": out[5], "tb_launches": out[6], "tb_ms": out[7],
-                "tb_steps": out[8], "rec_steps": out[9]}
+                "tb_steps": out[8], "rec_steps": out[9], "adj_steps": out[10]}
 
     def set_blocking(self, nsteps, tile_x=32, tile_y=16):
         """Temporal blocking of forward launches (D2Q9): nsteps per launch."""
