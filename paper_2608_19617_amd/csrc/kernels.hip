@@ -150,20 +150,34 @@ __global__ __launch_bounds__(BLOCK) void k_step(const S* __restrict__ gin, S* __
 // memory once), and the row cache. TB threads (512 or 1024, whichever
 // covers the first region in one round) update the nodes of a region.
 //
-// The region of a step is [m, LW - m) x [m, LH - m). Its cells are dealt
-// to threads row by row, except the column of an open x-face (at LDS x =
-// fc), which comes last: its nodes then share one or two wavefronts, so the
+// The region of a step is [m, LW - m) x [m, LH - m), cut to the domain on a
+// non-periodic axis and, for the output step, to the tile's own nodes
+// (unwrapped x < nx, y < ny, so that periodic wraps are not written twice).
+// Its cells are dealt to threads row by row, except the column of an open
+// x-face (LDS x = fc, always the first or last column of the cut region),
+// which comes last: its nodes then share one or two wavefronts, so the
 // Zou-He and ghost-cell work does not diverge every wavefront of the tile.
 struct TbPhase {
-    int m, rwp, fc, nrow, count;   // margin, row width without column fc, fc or -1, cells before fc's
-    float inv;                     // 1 / rwp
+    int ax, ay;         // first LDS column and row of the cut region
+    int rwp, sh;        // row width without the face column; 1 if fc == ax
+    int fc, nrow;       // face column or -1; cells before the face column's
+    int count;          // cells of the step
+    float inv;          // 1 / rwp
 };
 
-__device__ __forceinline__ TbPhase tb_phase(int m, int LW, int LH, int fcol) {
+__device__ __forceinline__ TbPhase tb_phase(const Geo& g, int m, int LW, int LH, int fcol, int x0, int y0,
+                                            bool output) {
+    int ax = m, bx = LW - m, ay = m, by = LH - m;
+    if (!g.per_x) ax = max(ax, -x0);
+    if (!g.per_y) ay = max(ay, -y0);
+    if (!g.per_x || output) bx = min(bx, g.nx - x0);
+    if (!g.per_y || output) by = min(by, g.ny - y0);
+    const int rw = max(bx - ax, 0), rh = max(by - ay, 0);
     TbPhase p;
-    p.m = m;
-    const int rw = LW - 2 * m, rh = LH - 2 * m;
-    p.fc = (fcol >= m && fcol < LW - m) ? fcol : -1;
+    p.ax = ax;
+    p.ay = ay;
+    p.fc = (fcol >= ax && fcol < bx) ? fcol : -1;
+    p.sh = (p.fc >= 0 && p.fc == ax) ? 1 : 0;
     p.rwp = p.fc >= 0 ? rw - 1 : rw;
     p.nrow = p.rwp * rh;
     p.count = rw * rh;
@@ -171,34 +185,28 @@ __device__ __forceinline__ TbPhase tb_phase(int m, int LW, int LH, int fcol) {
     return p;
 }
 
-// Cell i of a step's region: LDS coordinates and the (wrapped) global node;
-// false if the node lies outside the domain or, for the output step,
-// outside the tile's own part of the domain.
+// Cell i (< count) of a step: LDS coordinates and the (wrapped) global node.
 struct TbCell {
     int lx, ly, x, y, n, cell;
 };
 
-__device__ __forceinline__ bool tb_cell(const Geo& g, int i, const TbPhase& p, int LW, int x0, int y0,
-                                        bool output, TbCell& c) {
+__device__ __forceinline__ void tb_cell(const Geo& g, int i, const TbPhase& p, int LW, int x0, int y0,
+                                        TbCell& c) {
     if (i < p.nrow) {
         const int qy = (int)(((float)i + 0.5f) * p.inv);   // exact for i < 2^12
-        c.ly = p.m + qy;
-        c.lx = p.m + (i - qy * p.rwp);
-        if (p.fc >= 0 && c.lx >= p.fc) c.lx += 1;
+        c.ly = p.ay + qy;
+        c.lx = p.ax + p.sh + (i - qy * p.rwp);
     } else {
-        c.ly = p.m + (i - p.nrow);
+        c.ly = p.ay + (i - p.nrow);
         c.lx = p.fc;
     }
     int x = x0 + c.lx, y = y0 + c.ly;
-    if (output && (x >= g.nx || y >= g.ny)) return false;   // no wrapped duplicates in the output
     if (g.per_x) x = ((x % g.nx) + g.nx) % g.nx;
     if (g.per_y) y = ((y % g.ny) + g.ny) % g.ny;
-    if (x < 0 || x >= g.nx || y < 0 || y >= g.ny) return false;
     c.x = x;
     c.y = y;
     c.n = y * g.nx + x;
     c.cell = c.ly * LW + c.lx;
-    return true;
 }
 
 // Tile of this workgroup. Workgroups are dealt to the 8 XCDs of the chip
@@ -280,31 +288,43 @@ __device__ __forceinline__ void tb_pull_lds(const Geo& g, const T* __restrict__ 
     if (oc) zou_he_rows<L, T>(oc, rows.u[c.ly], d0, h);
 }
 
-// Ghost-cell stores of a node on a non-periodic face (see above). Every
-// direction is stored, the ones that stay in the domain to the thread's own
-// dump slot, so there is no branch per direction. Nodes on the region's
-// edge (only computed at step 1) pull nothing from LDS later and skip this.
-template <class T>
-__device__ __forceinline__ void tb_ghosts(const Geo& g, T* __restrict__ dst, T* __restrict__ dump, int plane_sz,
-                                          int LW, int LH, const TbCell& c, const T out[9]) {
+// Ghost-cell stores of a node on a non-periodic face. For every direction
+// b that leaves the domain across a face the node lies on (the directions
+// with c_b . n = +1 for the outward normal n), value(b) goes to the LDS cell
+// at c.cell + SGN * c_b in plane opp(b). Forward: SGN = +1, value = G_b (the
+// pull of opp(b) at the next step reads it). Adjoint: SGN = -1 with the
+// directions b whose -c_b leaves, value = nu_hat_b or 0 (the gather of
+// opp(b) reads it). A corner node stores its diagonal twice, with the same
+// value. Nodes on the region's edge (only computed at step 1) pull nothing
+// from LDS later and store no ghosts, which keeps every store in the region.
+template <class T, int SGN, int NX, int NY>
+__device__ __forceinline__ void tb_ghost_face(T* __restrict__ dst, int psz, int LW, int cell, const T v[9]) {
     using L = D2Q9;
-    const bool w = !g.per_x && c.x == 0, e = !g.per_x && c.x == g.nx - 1;
-    const bool s = !g.per_y && c.y == 0, n = !g.per_y && c.y == g.ny - 1;
-    const bool inner = c.lx >= 1 && c.ly >= 1 && c.lx <= LW - 2 && c.ly <= LH - 2;
-    if (!((w || e || s || n) && inner)) return;
 #pragma unroll
-    for (int a = 1; a < L::Q; ++a) {
-        const bool leaves = (L::cx[a] < 0 && w) || (L::cx[a] > 0 && e) || (L::cy[a] < 0 && s) ||
-                            (L::cy[a] > 0 && n);
-        T* p = leaves ? dst + L::opp[a] * plane_sz + c.cell + L::cy[a] * LW + L::cx[a] : dump;
-        *p = out[a];
+    for (int b = 1; b < L::Q; ++b) {
+        if ((NX != 0 && SGN * L::cx[b] == NX) || (NY != 0 && SGN * L::cy[b] == NY))
+            dst[L::opp[b] * psz + cell + SGN * (L::cy[b] * LW + L::cx[b])] = v[b];
     }
+}
+
+template <class T, int SGN>
+__device__ __forceinline__ void tb_ghosts(const Geo& g, T* __restrict__ dst, int psz, int LW, int LH,
+                                          const TbCell& c, const T v[9]) {
+    const bool inner = c.lx >= 1 && c.ly >= 1 && c.lx <= LW - 2 && c.ly <= LH - 2;
+    if (!inner) return;
+    if (!g.per_x && c.x == 0) tb_ghost_face<T, SGN, -1, 0>(dst, psz, LW, c.cell, v);
+    if (!g.per_x && c.x == g.nx - 1) tb_ghost_face<T, SGN, 1, 0>(dst, psz, LW, c.cell, v);
+    if (!g.per_y && c.y == 0) tb_ghost_face<T, SGN, 0, -1>(dst, psz, LW, c.cell, v);
+    if (!g.per_y && c.y == g.ny - 1) tb_ghost_face<T, SGN, 0, 1>(dst, psz, LW, c.cell, v);
 }
 
 // ALLOUT (recompute of an adjoint segment): every step t < nt also stores
 // the tile's post-collision state to allout + (t - 1) * slot (the step nt
 // state goes to gout as usual), so that each intermediate state is kept.
-template <class S, class T, bool SAMPLE, bool WPRE, int TB, bool ALLOUT>
+// PS > 0: the planes of the LDS buffers are PS values apart (a compile-time
+// stride, so a node reaches its nine planes with immediate offsets); PS = 0:
+// they are LW * LH apart.
+template <class S, class T, bool SAMPLE, bool WPRE, int TB, bool ALLOUT, int PS>
 __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __restrict__ gout,
                                                 S* __restrict__ pre, const T* __restrict__ sfield,
                                                 Geo g, Phys ph, Obj ob, double* __restrict__ partials,
@@ -315,11 +335,10 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
     T* lds = reinterpret_cast<T*>(lds_raw);
     const int H = nt - 1;
     const int LW = ox + 2 * H, LH = oy + 2 * H;
-    const int plane_sz = LW * LH;
+    const int plane_sz = PS > 0 ? PS : LW * LH;
     const int bufsz = L::Q * plane_sz;                // buffer b starts at lds + b * bufsz
     T* sbuf = lds + 2 * bufsz;                        // s of the region, loaded at step 1
-    T* dump = sbuf + plane_sz + threadIdx.x;          // this thread's dump slot
-    const TbRows<T> rows = tb_rows<T>(sbuf + plane_sz + TB, LH);
+    const TbRows<T> rows = tb_rows<T>(sbuf + plane_sz, LH);
     const T d0 = (T)g.drho_out;
     int tx, ty;
     tb_tile(tiles_x, tx, ty);
@@ -331,42 +350,58 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
         else if (x0 + LW - 1 >= g.nx - 1) fcol = g.nx - 1 - x0;
     }
 
-    // step 1: pull from global memory over the whole LDS region
+    // step 1: pull from global memory over the whole LDS region. A thread
+    // takes cells i and i + TB together and issues the loads of both before
+    // computing either, so a region of up to 2 TB cells waits on global
+    // memory once.
     tb_fill_rows<T, TB>(g, rows, LH, y0);
     {
-        const TbPhase ph1 = tb_phase(0, LW, LH, fcol);
+        const TbPhase ph1 = tb_phase(g, 0, LW, LH, fcol, x0, y0, false);
         T* dst = lds + bufsz;
-        for (int i = (int)threadIdx.x; i < ph1.count; i += TB) {
-            TbCell c;
-            if (!tb_cell(g, i, ph1, LW, x0, y0, false, c)) continue;
-            const int oc = open_code<L>(g, c.x, c.y, 0);
-            T h[L::Q];
-            pull<L, S, T>(gin, g, c.n, c.x, c.y, 0, h);
-            if (oc) zou_he<L, T>(g, oc, c.y, h);
-            Moments<L, T> mo;
-            moments<L, T>(h, ph, mo);
-            const T sv = sfield[c.n];
-            sbuf[c.cell] = sv;
-            T out[L::Q];
-            collide<L, T>(mo, sv, out);
+        for (int i = (int)threadIdx.x; i < ph1.count; i += 2 * TB) {
+            TbCell c[2];
+            bool v[2];
+            T h[2][L::Q];
+            T sv[2];
+            int oc[2];
 #pragma unroll
-            for (int a = 0; a < L::Q; ++a) dst[a * plane_sz + c.cell] = out[a];
-            tb_ghosts<T>(g, dst, dump, plane_sz, LW, LH, c, out);
-            if (ALLOUT && tb_owned(g, c, H, ox, oy, x0, y0)) {
+            for (int u = 0; u < 2; ++u) {
+                v[u] = i + u * TB < ph1.count;
+                if (v[u]) {
+                    tb_cell(g, i + u * TB, ph1, LW, x0, y0, c[u]);
+                    oc[u] = open_code<L>(g, c[u].x, c[u].y, 0);
+                    pull<L, S, T>(gin, g, c[u].n, c[u].x, c[u].y, 0, h[u]);
+                    sv[u] = sfield[c[u].n];
+                }
+            }
 #pragma unroll
-                for (int a = 0; a < L::Q; ++a) plane(allout, a, g.N)[(unsigned)c.n] = (S)out[a];
+            for (int u = 0; u < 2; ++u) {
+                if (!v[u]) continue;
+                if (oc[u]) zou_he<L, T>(g, oc[u], c[u].y, h[u]);
+                Moments<L, T> mo;
+                moments<L, T>(h[u], ph, mo);
+                sbuf[c[u].cell] = sv[u];
+                T out[L::Q];
+                collide<L, T>(mo, sv[u], out);
+#pragma unroll
+                for (int a = 0; a < L::Q; ++a) dst[a * plane_sz + c[u].cell] = out[a];
+                tb_ghosts<T, 1>(g, dst, plane_sz, LW, LH, c[u], out);
+                if (ALLOUT && tb_owned(g, c[u], H, ox, oy, x0, y0)) {
+#pragma unroll
+                    for (int a = 0; a < L::Q; ++a) plane(allout, a, g.N)[(unsigned)c[u].n] = (S)out[a];
+                }
             }
         }
         __syncthreads();
     }
     // steps 2 .. nt-1: LDS to LDS over shrinking regions
     for (int t = 2; t < nt; ++t) {
-        const TbPhase pt = tb_phase(t - 1, LW, LH, fcol);
+        const TbPhase pt = tb_phase(g, t - 1, LW, LH, fcol, x0, y0, false);
         T* dst = lds + (t & 1) * bufsz;
         const T* srcb = lds + ((t - 1) & 1) * bufsz;
         for (int i = (int)threadIdx.x; i < pt.count; i += TB) {
             TbCell c;
-            if (!tb_cell(g, i, pt, LW, x0, y0, false, c)) continue;
+            tb_cell(g, i, pt, LW, x0, y0, c);
             T h[L::Q];
             tb_pull_lds<T>(g, srcb, plane_sz, LW, rows, d0, c, h);
             Moments<L, T> mo;
@@ -375,7 +410,7 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
             collide<L, T>(mo, sbuf[c.cell], out);
 #pragma unroll
             for (int a = 0; a < L::Q; ++a) dst[a * plane_sz + c.cell] = out[a];
-            tb_ghosts<T>(g, dst, dump, plane_sz, LW, LH, c, out);
+            tb_ghosts<T, 1>(g, dst, plane_sz, LW, LH, c, out);
             if (ALLOUT && tb_owned(g, c, H, ox, oy, x0, y0)) {
                 S* o = allout + (size_t)(t - 1) * slot;
 #pragma unroll
@@ -387,11 +422,11 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
     // step nt: the output tile, from LDS to global memory (samples, checkpoint)
     double v[3] = {0.0, 0.0, 0.0};
     {
-        const TbPhase pn = tb_phase(nt - 1, LW, LH, fcol);
+        const TbPhase pn = tb_phase(g, nt - 1, LW, LH, fcol, x0, y0, true);
         const T* srcb = lds + ((nt - 1) & 1) * bufsz;
         for (int i = (int)threadIdx.x; i < pn.count; i += TB) {
             TbCell c;
-            if (!tb_cell(g, i, pn, LW, x0, y0, true, c)) continue;
+            tb_cell(g, i, pn, LW, x0, y0, c);
             T h[L::Q];
             tb_pull_lds<T>(g, srcb, plane_sz, LW, rows, d0, c, h);
             if (WPRE) {
@@ -605,7 +640,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(const A* __restrict__ nu_in, 
 // y - c_b in plane opp(b), the slot it gathers kappa_opp(b) from next. The
 // sensitivity of the tile's own nodes is summed over the launch's steps in
 // an FP64 LDS plane and added to global memory once.
-template <class S, class T, class A, int TB>
+template <class S, class T, class A, int TB, int PS>
 __global__ __launch_bounds__(TB) void k_adjoint_tb(const A* __restrict__ nu_in, A* __restrict__ nu_out,
                                                    const S* __restrict__ gseg, size_t slot, long kseg,
                                                    const T* __restrict__ sfield, double* __restrict__ sens,
@@ -617,11 +652,10 @@ __global__ __launch_bounds__(TB) void k_adjoint_tb(const A* __restrict__ nu_in, 
     T* lds = reinterpret_cast<T*>(sacc + ox * oy);
     const int H = nt - 1;
     const int LW = ox + 2 * H, LH = oy + 2 * H;
-    const int plane_sz = LW * LH;
+    const int plane_sz = PS > 0 ? PS : LW * LH;
     const int bufsz = L::Q * plane_sz;
     T* sbuf = lds + 2 * bufsz;
-    T* dump = sbuf + plane_sz + threadIdx.x;
-    const TbRows<T> rows = tb_rows<T>(sbuf + plane_sz + TB, LH);
+    const TbRows<T> rows = tb_rows<T>(sbuf + plane_sz, LH);
     const T d0 = (T)g.drho_out;
     int tx, ty;
     tb_tile(tiles_x, tx, ty);
@@ -637,13 +671,13 @@ __global__ __launch_bounds__(TB) void k_adjoint_tb(const A* __restrict__ nu_in, 
         const long k = k_hi - t + 1;
         const S* Gk2 = gseg + (size_t)(k - 2 - kseg) * slot;
         const double src_w = (k > ns && (k - ns) % dW == 0) ? wgt : 0.0;
-        const TbPhase pt = tb_phase(t - 1, LW, LH, fcol);
+        const bool last = t == nt;
+        const TbPhase pt = tb_phase(g, t - 1, LW, LH, fcol, x0, y0, last);
         const T* srcb = lds + ((t - 1) & 1) * bufsz;
         T* dst = lds + (t & 1) * bufsz;
-        const bool last = t == nt;
         for (int i = (int)threadIdx.x; i < pt.count; i += TB) {
             TbCell c;
-            if (!tb_cell(g, i, pt, LW, x0, y0, last, c)) continue;
+            tb_cell(g, i, pt, LW, x0, y0, c);
             const int oc = tb_open<T>(g, rows, c);
             const T u0 = rows.u[c.ly];
             // pre-state f^{k-1}
@@ -713,20 +747,12 @@ __global__ __launch_bounds__(TB) void k_adjoint_tb(const A* __restrict__ nu_in, 
             } else {
 #pragma unroll
                 for (int a = 0; a < L::Q; ++a) dst[a * plane_sz + c.cell] = mu[a];
-                // ghost cells of the adjoint wall rule
-                const bool w = !g.per_x && c.x == 0, e = !g.per_x && c.x == g.nx - 1;
-                const bool so = !g.per_y && c.y == 0, no = !g.per_y && c.y == g.ny - 1;
-                const bool inner = c.lx >= 1 && c.ly >= 1 && c.lx <= LW - 2 && c.ly <= LH - 2;
-                if ((w || e || so || no) && inner) {
+                // ghost cells of the adjoint wall rule (0 on an open node)
+                if (oc) {
 #pragma unroll
-                    for (int b = 1; b < L::Q; ++b) {
-                        // y - c_b leaves the domain
-                        const bool leaves = (L::cx[b] > 0 && w) || (L::cx[b] < 0 && e) || (L::cy[b] > 0 && so) ||
-                                            (L::cy[b] < 0 && no);
-                        T* p = leaves ? dst + L::opp[b] * plane_sz + c.cell - L::cy[b] * LW - L::cx[b] : dump;
-                        *p = oc ? (T)0 : mu[b];
-                    }
+                    for (int a = 0; a < L::Q; ++a) mu[a] = (T)0;
                 }
+                tb_ghosts<T, -1>(g, dst, plane_sz, LW, LH, c, mu);
             }
         }
         __syncthreads();
@@ -802,22 +828,39 @@ __global__ __launch_bounds__(BLOCK) void k_copy_bytes(const unsigned int* __rest
 
 static inline dim3 grid_for(long n) { return dim3((unsigned)((n + BLOCK - 1) / BLOCK)); }
 
+// Compile-time plane strides of the blocked kernels' LDS buffers (values of
+// the compute type); each keeps the largest immediate LDS offset of a node,
+// 8 planes, below 64 KB. Regions of more than 512 nodes use the smallest
+// that holds them when the LDS allows; other launches use their region size.
+static constexpr int TB_PS32[2] = {1856, 2040};
+static constexpr int TB_PS64 = 1020;
+
+template <class S, class T, bool SAMPLE, bool WPRE, int TB, bool ALLOUT, int PS>
+static void launch_tb_ps(const StepLaunch& a, int tiles_x, int tiles_y, size_t lds) {
+    hipLaunchKernelGGL((k_step_tb<S, T, SAMPLE, WPRE, TB, ALLOUT, PS>), dim3(tiles_x * tiles_y), dim3(TB), lds,
+                       a.stream, (const S*)a.gin, (S*)a.gout, (S*)a.pre, (const T*)a.s, a.geo, a.ph, a.ob,
+                       a.partials, a.part_stride, a.nsteps, a.tile_x, a.tile_y, tiles_x, (S*)a.allout,
+                       a.allout_slot / sizeof(S));
+}
+
 template <class S, class T, bool SAMPLE, bool WPRE, bool ALLOUT>
 static void launch_tb(const StepLaunch& a) {
     const Geo& g = a.geo;
     const int tiles_x = (g.nx + a.tile_x - 1) / a.tile_x;
     const int tiles_y = (g.ny + a.tile_y - 1) / a.tile_y;
     const size_t lds = tb_lds_bytes(a.nsteps, a.tile_x, a.tile_y, sizeof(T));
-    if (tb_threads(a.nsteps, a.tile_x, a.tile_y) == 512)
-        hipLaunchKernelGGL((k_step_tb<S, T, SAMPLE, WPRE, 512, ALLOUT>), dim3(tiles_x * tiles_y), dim3(512), lds,
-                           a.stream, (const S*)a.gin, (S*)a.gout, (S*)a.pre, (const T*)a.s, g, a.ph, a.ob,
-                           a.partials, a.part_stride, a.nsteps, a.tile_x, a.tile_y, tiles_x, (S*)a.allout,
-                           a.allout_slot / sizeof(S));
-    else
-        hipLaunchKernelGGL((k_step_tb<S, T, SAMPLE, WPRE, 1024, ALLOUT>), dim3(tiles_x * tiles_y), dim3(1024), lds,
-                           a.stream, (const S*)a.gin, (S*)a.gout, (S*)a.pre, (const T*)a.s, g, a.ph, a.ob,
-                           a.partials, a.part_stride, a.nsteps, a.tile_x, a.tile_y, tiles_x, (S*)a.allout,
-                           a.allout_slot / sizeof(S));
+    const int ps = tb_plane(a.nsteps, a.tile_x, a.tile_y, sizeof(T), 0);
+    if (tb_threads(a.nsteps, a.tile_x, a.tile_y) == 512) {
+        launch_tb_ps<S, T, SAMPLE, WPRE, 512, ALLOUT, 0>(a, tiles_x, tiles_y, lds);
+        return;
+    }
+    if constexpr (sizeof(T) == 4) {
+        if (ps == TB_PS32[0]) return launch_tb_ps<S, T, SAMPLE, WPRE, 1024, ALLOUT, TB_PS32[0]>(a, tiles_x, tiles_y, lds);
+        if (ps == TB_PS32[1]) return launch_tb_ps<S, T, SAMPLE, WPRE, 1024, ALLOUT, TB_PS32[1]>(a, tiles_x, tiles_y, lds);
+    } else {
+        if (ps == TB_PS64) return launch_tb_ps<S, T, SAMPLE, WPRE, 1024, ALLOUT, TB_PS64>(a, tiles_x, tiles_y, lds);
+    }
+    launch_tb_ps<S, T, SAMPLE, WPRE, 1024, ALLOUT, 0>(a, tiles_x, tiles_y, lds);
 }
 
 template <class L, class S, class T>
@@ -866,17 +909,35 @@ static hipError_t adj_t(const AdjLaunch& a) {
         const int tiles_x = (g.nx + a.tile_x - 1) / a.tile_x;
         const int tiles_y = (g.ny + a.tile_y - 1) / a.tile_y;
         const size_t lds = adj_tb_lds_bytes(a.nsteps, a.tile_x, a.tile_y, sizeof(T));
+        const int ps = tb_plane(a.nsteps, a.tile_x, a.tile_y, sizeof(T), (size_t)a.tile_x * a.tile_y * 8);
         const int tb = tb_threads(a.nsteps, a.tile_x, a.tile_y);
+        const dim3 grid(tiles_x * tiles_y);
         const S* gs = (const S*)a.gseg;
         const size_t slot = a.slot / sizeof(S);
-        if (tb == 512)
-            hipLaunchKernelGGL((k_adjoint_tb<S, T, A, 512>), dim3(tiles_x * tiles_y), dim3(512), lds, a.stream, nin, nout,
-                               gs, slot, a.kseg, sf, a.sens, g, a.ph, a.ob, a.k_hi, a.ns, a.dW, a.wgt, a.nsteps,
-                               a.tile_x, a.tile_y, tiles_x);
-        else
-            hipLaunchKernelGGL((k_adjoint_tb<S, T, A, 1024>), dim3(tiles_x * tiles_y), dim3(1024), lds, a.stream, nin,
-                               nout, gs, slot, a.kseg, sf, a.sens, g, a.ph, a.ob, a.k_hi, a.ns, a.dW, a.wgt, a.nsteps,
-                               a.tile_x, a.tile_y, tiles_x);
+#define LBM_ADJ_TB(TBV, PSV)                                                                                \
+    hipLaunchKernelGGL((k_adjoint_tb<S, T, A, TBV, PSV>), grid, dim3(TBV), lds, a.stream, nin, nout, gs, slot, \
+                       a.kseg, sf, a.sens, g, a.ph, a.ob, a.k_hi, a.ns, a.dW, a.wgt, a.nsteps, a.tile_x,       \
+                       a.tile_y, tiles_x)
+        bool done = false;
+        if (tb == 512) {
+            LBM_ADJ_TB(512, 0);
+            done = true;
+        } else if constexpr (sizeof(T) == 4) {
+            if (ps == TB_PS32[0]) {
+                LBM_ADJ_TB(1024, TB_PS32[0]);
+                done = true;
+            } else if (ps == TB_PS32[1]) {
+                LBM_ADJ_TB(1024, TB_PS32[1]);
+                done = true;
+            }
+        } else {
+            if (ps == TB_PS64) {
+                LBM_ADJ_TB(1024, TB_PS64);
+                done = true;
+            }
+        }
+        if (!done) LBM_ADJ_TB(1024, 0);
+#undef LBM_ADJ_TB
     } else if (a.seed) {
         hipLaunchKernelGGL((k_adjoint<L, S, T, A, false, true>), gr, dim3(BLOCK), 0, a.stream, nin, nout, st, sf, a.sens, g, a.ph, a.ob, a.src_w);
     } else if (a.direct) {
@@ -978,15 +1039,34 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t str
 
 long blocks_for(long n) { return (n + BLOCK - 1) / BLOCK; }
 
+// Plane stride (values) of a blocked launch whose LDS also holds `extra`
+// bytes beyond the forward kernel's layout.
+int tb_plane(int nsteps, int tile_x, int tile_y, size_t elem, size_t extra) {
+    const long lw = tile_x + 2 * (nsteps - 1), lh = tile_y + 2 * (nsteps - 1);
+    const long region = lw * lh;
+    extra += lh * (elem + 2);   // row cache
+    if (region > 512) {
+        if (elem == 4) {
+            for (int ps : TB_PS32)
+                if (ps >= region && (2 * 9 + 1) * (size_t)ps * elem + extra <= TB_LDS_MAX) return ps;
+        } else if (elem == 8) {
+            if (TB_PS64 >= region && (2 * 9 + 1) * (size_t)TB_PS64 * elem + extra <= TB_LDS_MAX) return TB_PS64;
+        }
+    }
+    return (int)region;
+}
+
 size_t tb_lds_bytes(int nsteps, int tile_x, int tile_y, size_t elem) {
-    const size_t lw = tile_x + 2 * (nsteps - 1), lh = tile_y + 2 * (nsteps - 1);
-    // state buffers, s plane, dump slots of up to 1024 threads, row cache
-    return (2 * 9 + 1) * lw * lh * elem + 1024 * elem + lh * (elem + 2);
+    const size_t lh = tile_y + 2 * (nsteps - 1);
+    // two state buffers and the s plane, then the row cache
+    return (2 * 9 + 1) * (size_t)tb_plane(nsteps, tile_x, tile_y, elem, 0) * elem + lh * (elem + 2);
 }
 
 size_t adj_tb_lds_bytes(int nsteps, int tile_x, int tile_y, size_t elem) {
     // sensitivity sums of the tile (FP64), then the forward kernel's layout
-    return (size_t)tile_x * tile_y * 8 + tb_lds_bytes(nsteps, tile_x, tile_y, elem);
+    const size_t sens = (size_t)tile_x * tile_y * 8;
+    const size_t lh = tile_y + 2 * (nsteps - 1);
+    return sens + (2 * 9 + 1) * (size_t)tb_plane(nsteps, tile_x, tile_y, elem, sens) * elem + lh * (elem + 2);
 }
 
 long tb_blocks(int nx, int ny, int tile_x, int tile_y) {
@@ -998,15 +1078,28 @@ int tb_threads(int nsteps, int tile_x, int tile_y) {
     return lw * lh <= 512 ? 512 : 1024;
 }
 
-template <class S, class T, class A, int NT>
+template <class S, class T, class A, int NT, int PS>
 static hipError_t tb_attr(int b) {
     const hipFuncAttribute at = hipFuncAttributeMaxDynamicSharedMemorySize;
-    hipError_t e = hipFuncSetAttribute((const void*)k_step_tb<S, T, false, false, NT, false>, at, b);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, true, false, NT, false>, at, b);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, false, true, NT, false>, at, b);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, true, true, NT, false>, at, b);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, false, false, NT, true>, at, b);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_adjoint_tb<S, T, A, NT>, at, b);
+    hipError_t e = hipFuncSetAttribute((const void*)k_step_tb<S, T, false, false, NT, false, PS>, at, b);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, true, false, NT, false, PS>, at, b);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, false, true, NT, false, PS>, at, b);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, true, true, NT, false, PS>, at, b);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, false, false, NT, true, PS>, at, b);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_adjoint_tb<S, T, A, NT, PS>, at, b);
+    return e;
+}
+
+template <class S, class T, class A>
+static hipError_t tb_attr_all(int b) {
+    hipError_t e = tb_attr<S, T, A, 512, 0>(b);
+    if (e == hipSuccess) e = tb_attr<S, T, A, 1024, 0>(b);
+    if constexpr (sizeof(T) == 4) {
+        if (e == hipSuccess) e = tb_attr<S, T, A, 1024, TB_PS32[0]>(b);
+        if (e == hipSuccess) e = tb_attr<S, T, A, 1024, TB_PS32[1]>(b);
+    } else {
+        if (e == hipSuccess) e = tb_attr<S, T, A, 1024, TB_PS64>(b);
+    }
     return e;
 }
 
@@ -1014,18 +1107,9 @@ hipError_t tb_prepare(int prec) {
     // opt in to the LDS of a compute unit (beyond the default 64 KB) for the
     // blocked kernels; launches check their own size against TB_LDS_MAX
     const int b = (int)TB_LDS_MAX;
-    hipError_t e;
-    if (prec == 0) {
-        e = tb_attr<double, double, double, 512>(b);
-        if (e == hipSuccess) e = tb_attr<double, double, double, 1024>(b);
-    } else if (prec == 1) {
-        e = tb_attr<float, float, float, 512>(b);
-        if (e == hipSuccess) e = tb_attr<float, float, float, 1024>(b);
-    } else {
-        e = tb_attr<_Float16, float, float, 512>(b);
-        if (e == hipSuccess) e = tb_attr<_Float16, float, float, 1024>(b);
-    }
-    return e;
+    if (prec == 0) return tb_attr_all<double, double, double>(b);
+    if (prec == 1) return tb_attr_all<float, float, float>(b);
+    return tb_attr_all<_Float16, float, float>(b);
 }
 
 }  // namespace lbm
