@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--counters", action="store_true",
                     help="run one window and its adjoint of the workload plus a 256 MiB device copy "
                          "(for rocprofv3 --pmc byte counters) and exit")
+    ap.add_argument("--suite", choices=["hbm"], default=None,
+                    help="hbm: rooflines of the forward, recompute and adjoint kernels on grids far "
+                         "larger than the caches (one JSON line per configuration) instead of the "
+                         "benchmark step")
     return ap.parse_args()
 
 
@@ -217,6 +221,68 @@ def precision_compare(w, ref_prec, res_ref, args, torch, Solver):
     return out
 
 
+# Algorithmic bytes per update on D3Q19 (FP32 storage): forward 19 * 4 * 2 + 4;
+# adjoint 19 * 4 * 2 + 19 * 4 + 4 + 16.
+FWD_BYTES_3D = {"f32": 19 * 4 * 2 + 4, "f64": 19 * 8 * 2 + 8, "f16s": 19 * 2 * 2 + 4}
+ADJ_BYTES_3D = {"f32": 19 * 4 * 3 + 4 + 16, "f64": 19 * 8 * 3 + 8 + 16, "f16s": 19 * 4 * 2 + 19 * 2 + 4 + 16}
+
+
+def hbm_suite(args, torch):
+    """Kernel rooflines where the state does not fit in any cache: the
+    cylinder wake scaled 4x per axis (8192 x 2048, 16.8M nodes, disk R = 128,
+    same Re and inlet speed) in every precision, and the 3D cylinder channel
+    384 x 128 x 128 (6.3M nodes, D3Q19, FP32). Each configuration runs a
+    spin-up window, a timed window of forward steps, then the adjoint of that
+    window (recompute + adjoint steps), all timed per kernel class with HIP
+    events; one JSON line per configuration."""
+    from paper_2608_19617_amd import workloads as W
+    from paper_2608_19617_amd.solver import Solver
+    cases = []
+    for prec in ("f64", "f32", "f16s"):
+        w = W.cylinder_wake(nx=8192, ny=2048, radius=128, window_len=500, sample_every=20, ckpt_every=50,
+                            max_windows=2)
+        cases.append(("cylinder wake 8192x2048 (C3 x4 per axis)", w, prec, FWD_BYTES[prec], ADJ_BYTES[prec]))
+    w3 = W.cylinder_3d(window_len=100, sample_every=20, ckpt_every=20, n_windows=2)
+    cases.append(("cylinder 3D 384x128x128 D3Q19", w3, "f32", FWD_BYTES_3D["f32"], ADJ_BYTES_3D["f32"]))
+    for name, w, prec, fb, ab in cases:
+        sv = Solver(w, prec)
+        sv.set_gamma(w.gamma)
+        sv.forward(w.window_len)                  # spin-up window
+        torch.cuda.synchronize()
+        sv.timing(True)
+        sv.forward(w.window_len)
+        torch.cuda.synchronize()
+        tf = sv.timing(True)
+        t0 = time.perf_counter()
+        sv.adjoint()
+        torch.cuda.synchronize()
+        t_sweep = time.perf_counter() - t0
+        ta = sv.timing(False)
+        N = w.nodes
+        fwd_ms = tf["fwd_ms"] + tf["tb_ms"]
+        fwd_steps = tf["fwd_launches"] + tf["tb_steps"]
+        fwd_s = fwd_ms * 1e-3 / fwd_steps
+        adj_s = ta["adj_ms"] * 1e-3 / ta["adj_steps"]
+        rec_s = ta["rec_ms"] * 1e-3 / max(ta["rec_steps"], 1)
+        line = {"suite": "hbm", "workload": name, "grid": list(w.shape), "nodes": N, "dtype": prec,
+                "forward": {"steps": int(fwd_steps), "us_per_step": round(fwd_s * 1e6, 3),
+                            "steps_per_launch": round(fwd_steps / max(tf["fwd_launches"] + tf["tb_launches"], 1), 2),
+                            "mlups": round(N / fwd_s / 1e6, 1), "bytes_per_lup": fb,
+                            "achieved_GBs": round(fb * N / fwd_s / 1e9, 1),
+                            "frac_of_hbm_peak": round(fb * N / fwd_s / 1e9 / HBM_PEAK_GBS, 4)},
+                "adjoint": {"steps": int(ta["adj_steps"]), "us_per_step": round(adj_s * 1e6, 3),
+                            "steps_per_launch": round(ta["adj_steps"] / max(ta["adj_launches"], 1), 2),
+                            "mlups": round(N / adj_s / 1e6, 1), "bytes_per_lup": ab,
+                            "achieved_GBs": round(ab * N / adj_s / 1e9, 1),
+                            "frac_of_hbm_peak": round(ab * N / adj_s / 1e9 / HBM_PEAK_GBS, 4)},
+                "recompute": {"steps": int(ta["rec_steps"]), "us_per_step": round(rec_s * 1e6, 3),
+                              "frac_of_hbm_peak": round(fb * N / rec_s / 1e9 / HBM_PEAK_GBS, 4)},
+                "reverse_sweep": {"s": round(t_sweep, 4),
+                                  "mlups_per_window_lup": round(N * w.window_len / t_sweep / 1e6, 1)}}
+        sv.close()
+        print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -229,6 +295,9 @@ def main():
         sys.exit(1)
     if args.counters:
         counters_run(args, torch)
+        return
+    if args.suite == "hbm":
+        hbm_suite(args, torch)
         return
     from paper_2608_19617_amd import workloads as W
     from paper_2608_19617_amd.solver import Solver

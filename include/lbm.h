@@ -206,22 +206,39 @@ lbm_status lbm_timing(lbm_ctx* ctx, int enable, double* out);
  * intermediate populations of each tile and its halo in LDS. nsteps = 1
  * turns it off. Samples, checkpoints and window ends always fall on the last
  * step of a launch, so results are those of single steps up to the
- * contraction of multiply-adds. Requires tile_x * tile_y >= 256 and
- * 19 * (tile_x + 2(nsteps-1)) * (tile_y + 2(nsteps-1)) values of compute
- * precision, 1024 more (per-thread dump slots) and a row cache of
- * (tile_y + 2(nsteps-1)) * (value + 2 bytes)
- * within 159 KB. A launch never runs past the next sample,
+ * contraction of multiply-adds. With R = (tile_x + 2(nsteps-1)) *
+ * (tile_y + 2(nsteps-1)) region nodes, requires tile_x * tile_y >= 256 and
+ * 18 R state values (FP16 for FP16S, else the compute type), R compute-type
+ * values of s and a row cache of (tile_y + 2(nsteps-1)) * (value + 2 bytes)
+ * within 159 KB (R may be rounded up to a fixed plane stride). FP16S
+ * intermediate states are rounded to FP16 as a single step stores them.
+ * A launch never runs past the next sample,
  * checkpoint or window end, so shorter blocked launches occur. Defaults
  * after lbm_init (measured on MI355X): grids of at most 400k nodes use
  * square tiles of about N / 256 nodes (16 to 25 per side) and 10 steps
  * (FP32, FP16S) or 4 steps (FP64); larger grids 6 steps on 64 x 16 tiles
- * (FP32), 6 steps on 32 x 32 (FP16S), 3 steps on 32 x 8 (FP64). The
+ * (FP32), 2 steps on 32 x 8 (FP64), and for FP16S (whose LDS holds FP16
+ * states) 6 steps on 48 x 48 below 4M nodes, 5 steps on 64 x 40 above. The
  * recompute of the adjoint sweep uses the same blocking, storing every
- * intermediate state; the adjoint steps that pull their pre-state from a
- * recomputed segment run blocked on the same tiles, with as many steps per
- * launch as their LDS (which adds an FP64 sensitivity plane of the tile)
- * allows. */
+ * intermediate state. The adjoint steps that pull their pre-state from a
+ * recomputed segment run blocked too (see lbm_set_adjoint_blocking); this
+ * call sets their default: on grids of more than 400k nodes 4 steps on
+ * 25 x 25 tiles (FP64) or 5 steps on 48 x 24 (FP32, FP16S), else the
+ * forward's steps and tiles, falling back to the first of 48 x 24, 64 x 16,
+ * 32 x 32, 32 x 16, 16 x 16 whose LDS allows two or more steps; nsteps = 1
+ * turns both off. */
 lbm_status lbm_set_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y);
+
+/* Blocking of the adjoint launches that pull their pre-states from a
+ * recomputed segment (D2Q9 only): up to nsteps reverse steps per launch on
+ * tile_x x tile_y output tiles, the adjoint populations (FP32, or FP64 for
+ * LBM_F64) of the tile and its halo and an FP64 sensitivity plane of the
+ * tile in LDS. nsteps = 1 turns it off. Requires tile_x * tile_y >= 256 and
+ * tile_x * tile_y * 8 bytes plus 19 R values of the adjoint type plus the
+ * row cache within 159 KB (R as for lbm_set_blocking). lbm_set_blocking
+ * resets it to its default (described there). Errors: LBM_E_INVALID for
+ * out-of-range arguments, LBM_E_HIP if the LDS opt-in fails. */
+lbm_status lbm_set_adjoint_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y);
 
 /* Thread-local message of the last failing call on this thread. */
 const char* lbm_last_error(void);

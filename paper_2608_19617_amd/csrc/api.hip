@@ -169,7 +169,7 @@ struct lbm_ctx {
     std::vector<int> conv;
     bool unstable;
     int tb_steps, tile_x, tile_y;    // temporal blocking of forward launches (1 = off)
-    int adj_steps;                   // steps per blocked adjoint launch (1 = off)
+    int adj_steps, adj_tile_x, adj_tile_y;   // blocked adjoint launches (adj_steps 1 = off)
     Timer tm;
 };
 
@@ -368,13 +368,45 @@ long last_window(lbm_ctx* c) {
     return g > c->base / W ? g : 0;
 }
 
+// The blocked adjoint keeps FP32/FP64 populations and an FP64 sensitivity
+// plane in LDS. Measured on MI355X: on grids of more than 400k nodes 4 steps
+// on 25 x 25 tiles (FP64) or 5 steps on 48 x 24 (FP32 populations) are the
+// fastest; on smaller grids the forward's tiles. If the first choice does
+// not fit, the first of a few tiles that allows two or more steps, with as
+// many steps (up to the first choice's) as the LDS allows.
+lbm_status default_adj_blocking(lbm_ctx* c, int nsteps, int tile_x, int tile_y) {
+    c->adj_steps = 1;
+    c->adj_tile_x = tile_x;
+    c->adj_tile_y = tile_y;
+    if (nsteps > 1) {
+        int nfirst = nsteps;
+        if (c->L.N > 400000) {
+            nfirst = c->cfg.prec == LBM_F64 ? 4 : 5;
+            tile_x = c->cfg.prec == LBM_F64 ? 25 : 48;
+            tile_y = c->cfg.prec == LBM_F64 ? 25 : 24;
+        }
+        const int cand[6][2] = {{tile_x, tile_y}, {48, 24}, {64, 16}, {32, 32}, {32, 16}, {16, 16}};
+        for (const auto& t : cand) {
+            int na = nfirst;
+            while (na > 1 && adj_tb_lds_bytes(na, t[0], t[1], c->L.cs) > TB_LDS_MAX) --na;
+            if (na >= 2 && tb_blocks(c->cfg.nx, c->cfg.ny, t[0], t[1]) <= c->L.pstride) {
+                c->adj_steps = na;
+                c->adj_tile_x = t[0];
+                c->adj_tile_y = t[1];
+                break;
+            }
+        }
+    }
+    return LBM_OK;
+}
+
 lbm_status set_blocking(lbm_ctx* c, int nsteps, int tile_x, int tile_y) {
     if (nsteps < 1 || nsteps > 16) return fail(LBM_E_INVALID, "nsteps must be in [1, 16]");
     if (nsteps > 1 && c->cfg.lattice != LBM_D2Q9) return fail(LBM_E_INVALID, "temporal blocking is D2Q9 only");
     if (nsteps > 1) {
         if (tile_x < 1 || tile_y < 1 || (long)tile_x * tile_y < 256)
             return fail(LBM_E_INVALID, "tile must hold at least 256 nodes");
-        const size_t lds = tb_lds_bytes(nsteps, tile_x, tile_y, c->L.cs);
+        const size_t lds = tb_lds_bytes_prec(nsteps, tile_x, tile_y, c->cfg.prec);
         if (lds > TB_LDS_MAX) return fail(LBM_E_INVALID, "tile and nsteps need more than 159 KB of LDS");
         if (tb_blocks(c->cfg.nx, c->cfg.ny, tile_x, tile_y) > c->L.pstride)
             return fail(LBM_E_INVALID, "too many tiles");
@@ -383,10 +415,24 @@ lbm_status set_blocking(lbm_ctx* c, int nsteps, int tile_x, int tile_y) {
         c->tile_y = tile_y;
     }
     c->tb_steps = nsteps;
-    // the blocked adjoint uses the same tiles, as many steps as its LDS allows
-    int na = nsteps;
-    while (na > 1 && adj_tb_lds_bytes(na, tile_x, tile_y, c->L.cs) > TB_LDS_MAX) --na;
-    c->adj_steps = na;
+    return default_adj_blocking(c, nsteps, tile_x, tile_y);
+}
+
+lbm_status set_adj_blocking(lbm_ctx* c, int nsteps, int tile_x, int tile_y) {
+    if (nsteps < 1 || nsteps > 16) return fail(LBM_E_INVALID, "nsteps must be in [1, 16]");
+    if (nsteps > 1) {
+        if (c->cfg.lattice != LBM_D2Q9) return fail(LBM_E_INVALID, "temporal blocking is D2Q9 only");
+        if (tile_x < 1 || tile_y < 1 || (long)tile_x * tile_y < 256)
+            return fail(LBM_E_INVALID, "tile must hold at least 256 nodes");
+        if (adj_tb_lds_bytes(nsteps, tile_x, tile_y, c->L.cs) > TB_LDS_MAX)
+            return fail(LBM_E_INVALID, "tile and nsteps need more than 159 KB of LDS");
+        if (tb_blocks(c->cfg.nx, c->cfg.ny, tile_x, tile_y) > c->L.pstride)
+            return fail(LBM_E_INVALID, "too many tiles");
+        HIPCHK(tb_prepare(c->cfg.prec));
+        c->adj_tile_x = tile_x;
+        c->adj_tile_y = tile_y;
+    }
+    c->adj_steps = nsteps;
     return LBM_OK;
 }
 
@@ -397,6 +443,11 @@ extern "C" {
 lbm_status lbm_set_blocking(lbm_ctx* c, int nsteps, int tile_x, int tile_y) {
     if (!c) return fail(LBM_E_INVALID, "NULL context");
     return set_blocking(c, nsteps, tile_x, tile_y);
+}
+
+lbm_status lbm_set_adjoint_blocking(lbm_ctx* c, int nsteps, int tile_x, int tile_y) {
+    if (!c) return fail(LBM_E_INVALID, "NULL context");
+    return set_adj_blocking(c, nsteps, tile_x, tile_y);
 }
 
 
@@ -492,6 +543,8 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
     c->unstable = false;
     c->tb_steps = 1;
     c->adj_steps = 1;
+    c->adj_tile_x = 32;
+    c->adj_tile_y = 16;
     c->tile_x = 32;
     c->tile_y = 16;
 
@@ -530,18 +583,23 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
             t = t < 16 ? 16 : (t > 25 ? 25 : t);
             tx = ty = t;
             nt = cfg->prec == LBM_F64 ? 4 : 10;
-            while (nt > 2 && tb_lds_bytes(nt, tx, ty, L.cs) > TB_LDS_MAX) --nt;
+            while (nt > 2 && tb_lds_bytes_prec(nt, tx, ty, cfg->prec) > TB_LDS_MAX) --nt;
         } else if (cfg->prec == LBM_F32) {
             nt = 6;
             tx = 64;
             ty = 16;
         } else if (cfg->prec == LBM_F64) {
-            nt = 3;
+            nt = 2;
             tx = 32;
             ty = 8;
-        } else {
+        } else if (L.N < 4000000) {
+            // FP16 LDS state: larger tiles
             nt = 6;
-            tx = ty = 32;
+            tx = ty = 48;
+        } else {
+            nt = 5;
+            tx = 64;
+            ty = 40;
         }
         if ((st = set_blocking(c, nt, tx, ty)) != LBM_OK) return bail(st);
     }
@@ -679,8 +737,8 @@ lbm_status lbm_adjoint(lbm_ctx* c, int window, double* dJdgamma_dev, double* J_o
     aa.ob = c->ob;
     aa.stream = c->stream;
     aa.nsteps = 1;
-    aa.tile_x = c->tile_x;
-    aa.tile_y = c->tile_y;
+    aa.tile_x = c->adj_tile_x;
+    aa.tile_y = c->adj_tile_y;
     aa.gseg = c->seg[0];
     aa.slot = L.SB;
     aa.ns = ns;

@@ -278,12 +278,12 @@ __device__ __forceinline__ int tb_open(const Geo& g, const TbRows<T>& r, const T
 
 // Pull of node c from the previous step's LDS buffer (walls come from the
 // ghost cells), then the Zou-He rule on open nodes.
-template <class T>
-__device__ __forceinline__ void tb_pull_lds(const Geo& g, const T* __restrict__ srcb, int plane_sz, int LW,
+template <class T, class LT>
+__device__ __forceinline__ void tb_pull_lds(const Geo& g, const LT* __restrict__ srcb, int plane_sz, int LW,
                                             const TbRows<T>& rows, T d0, const TbCell& c, T h[9]) {
     using L = D2Q9;
 #pragma unroll
-    for (int a = 0; a < L::Q; ++a) h[a] = srcb[a * plane_sz + c.cell - L::cy[a] * LW - L::cx[a]];
+    for (int a = 0; a < L::Q; ++a) h[a] = (T)srcb[a * plane_sz + c.cell - L::cy[a] * LW - L::cx[a]];
     const int oc = tb_open<T>(g, rows, c);
     if (oc) zou_he_rows<L, T>(oc, rows.u[c.ly], d0, h);
 }
@@ -297,26 +297,38 @@ __device__ __forceinline__ void tb_pull_lds(const Geo& g, const T* __restrict__ 
 // opp(b) reads it). A corner node stores its diagonal twice, with the same
 // value. Nodes on the region's edge (only computed at step 1) pull nothing
 // from LDS later and store no ghosts, which keeps every store in the region.
-template <class T, int SGN, int NX, int NY>
-__device__ __forceinline__ void tb_ghost_face(T* __restrict__ dst, int psz, int LW, int cell, const T v[9]) {
+template <class LT, class T, int SGN, int NX, int NY>
+__device__ __forceinline__ void tb_ghost_face(LT* __restrict__ dst, int psz, int LW, int cell, const T v[9]) {
     using L = D2Q9;
 #pragma unroll
     for (int b = 1; b < L::Q; ++b) {
         if ((NX != 0 && SGN * L::cx[b] == NX) || (NY != 0 && SGN * L::cy[b] == NY))
-            dst[L::opp[b] * psz + cell + SGN * (L::cy[b] * LW + L::cx[b])] = v[b];
+            dst[L::opp[b] * psz + cell + SGN * (L::cy[b] * LW + L::cx[b])] = (LT)v[b];
     }
 }
 
-template <class T, int SGN>
-__device__ __forceinline__ void tb_ghosts(const Geo& g, T* __restrict__ dst, int psz, int LW, int LH,
+template <class LT, class T, int SGN>
+__device__ __forceinline__ void tb_ghosts(const Geo& g, LT* __restrict__ dst, int psz, int LW, int LH,
                                           const TbCell& c, const T v[9]) {
     const bool inner = c.lx >= 1 && c.ly >= 1 && c.lx <= LW - 2 && c.ly <= LH - 2;
     if (!inner) return;
-    if (!g.per_x && c.x == 0) tb_ghost_face<T, SGN, -1, 0>(dst, psz, LW, c.cell, v);
-    if (!g.per_x && c.x == g.nx - 1) tb_ghost_face<T, SGN, 1, 0>(dst, psz, LW, c.cell, v);
-    if (!g.per_y && c.y == 0) tb_ghost_face<T, SGN, 0, -1>(dst, psz, LW, c.cell, v);
-    if (!g.per_y && c.y == g.ny - 1) tb_ghost_face<T, SGN, 0, 1>(dst, psz, LW, c.cell, v);
+    if (!g.per_x && c.x == 0) tb_ghost_face<LT, T, SGN, -1, 0>(dst, psz, LW, c.cell, v);
+    if (!g.per_x && c.x == g.nx - 1) tb_ghost_face<LT, T, SGN, 1, 0>(dst, psz, LW, c.cell, v);
+    if (!g.per_y && c.y == 0) tb_ghost_face<LT, T, SGN, 0, -1>(dst, psz, LW, c.cell, v);
+    if (!g.per_y && c.y == g.ny - 1) tb_ghost_face<LT, T, SGN, 0, 1>(dst, psz, LW, c.cell, v);
 }
+
+// Element type of the forward kernel's LDS state buffers: the compute type,
+// except FP16 for FP16-shifted storage, so that every intermediate state of
+// a blocked launch is rounded exactly as a single-step launch stores it.
+template <class S, class T>
+struct TbLds {
+    using type = T;
+};
+template <>
+struct TbLds<_Float16, float> {
+    using type = _Float16;
+};
 
 // ALLOUT (recompute of an adjoint segment): every step t < nt also stores
 // the tile's post-collision state to allout + (t - 1) * slot (the step nt
@@ -331,13 +343,14 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
                                                 int part_stride, int nt, int ox, int oy, int tiles_x,
                                                 S* __restrict__ allout, size_t slot) {
     using L = D2Q9;
+    using LT = typename TbLds<S, T>::type;
     extern __shared__ unsigned char lds_raw[];
-    T* lds = reinterpret_cast<T*>(lds_raw);
+    LT* lds = reinterpret_cast<LT*>(lds_raw);
     const int H = nt - 1;
     const int LW = ox + 2 * H, LH = oy + 2 * H;
     const int plane_sz = PS > 0 ? PS : LW * LH;
     const int bufsz = L::Q * plane_sz;                // buffer b starts at lds + b * bufsz
-    T* sbuf = lds + 2 * bufsz;                        // s of the region, loaded at step 1
+    T* sbuf = reinterpret_cast<T*>(lds + 2 * bufsz);  // s of the region, loaded at step 1
     const TbRows<T> rows = tb_rows<T>(sbuf + plane_sz, LH);
     const T d0 = (T)g.drho_out;
     int tx, ty;
@@ -357,7 +370,7 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
     tb_fill_rows<T, TB>(g, rows, LH, y0);
     {
         const TbPhase ph1 = tb_phase(g, 0, LW, LH, fcol, x0, y0, false);
-        T* dst = lds + bufsz;
+        LT* dst = lds + bufsz;
         for (int i = (int)threadIdx.x; i < ph1.count; i += 2 * TB) {
             TbCell c[2];
             bool v[2];
@@ -384,8 +397,8 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
                 T out[L::Q];
                 collide<L, T>(mo, sv[u], out);
 #pragma unroll
-                for (int a = 0; a < L::Q; ++a) dst[a * plane_sz + c[u].cell] = out[a];
-                tb_ghosts<T, 1>(g, dst, plane_sz, LW, LH, c[u], out);
+                for (int a = 0; a < L::Q; ++a) dst[a * plane_sz + c[u].cell] = (LT)out[a];
+                tb_ghosts<LT, T, 1>(g, dst, plane_sz, LW, LH, c[u], out);
                 if (ALLOUT && tb_owned(g, c[u], H, ox, oy, x0, y0)) {
 #pragma unroll
                     for (int a = 0; a < L::Q; ++a) plane(allout, a, g.N)[(unsigned)c[u].n] = (S)out[a];
@@ -397,20 +410,20 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
     // steps 2 .. nt-1: LDS to LDS over shrinking regions
     for (int t = 2; t < nt; ++t) {
         const TbPhase pt = tb_phase(g, t - 1, LW, LH, fcol, x0, y0, false);
-        T* dst = lds + (t & 1) * bufsz;
-        const T* srcb = lds + ((t - 1) & 1) * bufsz;
+        LT* dst = lds + (t & 1) * bufsz;
+        const LT* srcb = lds + ((t - 1) & 1) * bufsz;
         for (int i = (int)threadIdx.x; i < pt.count; i += TB) {
             TbCell c;
             tb_cell(g, i, pt, LW, x0, y0, c);
             T h[L::Q];
-            tb_pull_lds<T>(g, srcb, plane_sz, LW, rows, d0, c, h);
+            tb_pull_lds<T, LT>(g, srcb, plane_sz, LW, rows, d0, c, h);
             Moments<L, T> mo;
             moments<L, T>(h, ph, mo);
             T out[L::Q];
             collide<L, T>(mo, sbuf[c.cell], out);
 #pragma unroll
-            for (int a = 0; a < L::Q; ++a) dst[a * plane_sz + c.cell] = out[a];
-            tb_ghosts<T, 1>(g, dst, plane_sz, LW, LH, c, out);
+            for (int a = 0; a < L::Q; ++a) dst[a * plane_sz + c.cell] = (LT)out[a];
+            tb_ghosts<LT, T, 1>(g, dst, plane_sz, LW, LH, c, out);
             if (ALLOUT && tb_owned(g, c, H, ox, oy, x0, y0)) {
                 S* o = allout + (size_t)(t - 1) * slot;
 #pragma unroll
@@ -423,12 +436,12 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
     double v[3] = {0.0, 0.0, 0.0};
     {
         const TbPhase pn = tb_phase(g, nt - 1, LW, LH, fcol, x0, y0, true);
-        const T* srcb = lds + ((nt - 1) & 1) * bufsz;
+        const LT* srcb = lds + ((nt - 1) & 1) * bufsz;
         for (int i = (int)threadIdx.x; i < pn.count; i += TB) {
             TbCell c;
             tb_cell(g, i, pn, LW, x0, y0, c);
             T h[L::Q];
-            tb_pull_lds<T>(g, srcb, plane_sz, LW, rows, d0, c, h);
+            tb_pull_lds<T, LT>(g, srcb, plane_sz, LW, rows, d0, c, h);
             if (WPRE) {
 #pragma unroll
                 for (int a = 0; a < L::Q; ++a) plane(pre, a, g.N)[(unsigned)c.n] = (S)h[a];
@@ -752,7 +765,7 @@ __global__ __launch_bounds__(TB) void k_adjoint_tb(const A* __restrict__ nu_in, 
 #pragma unroll
                     for (int a = 0; a < L::Q; ++a) mu[a] = (T)0;
                 }
-                tb_ghosts<T, -1>(g, dst, plane_sz, LW, LH, c, mu);
+                tb_ghosts<T, T, -1>(g, dst, plane_sz, LW, LH, c, mu);
             }
         }
         __syncthreads();
@@ -834,6 +847,7 @@ static inline dim3 grid_for(long n) { return dim3((unsigned)((n + BLOCK - 1) / B
 // that holds them when the LDS allows; other launches use their region size.
 static constexpr int TB_PS32[2] = {1856, 2040};
 static constexpr int TB_PS64 = 1020;
+static constexpr int TB_PS16[3] = {1856, 3584, 3712};   // FP16 LDS state (FP16S forward)
 
 template <class S, class T, bool SAMPLE, bool WPRE, int TB, bool ALLOUT, int PS>
 static void launch_tb_ps(const StepLaunch& a, int tiles_x, int tiles_y, size_t lds) {
@@ -848,13 +862,18 @@ static void launch_tb(const StepLaunch& a) {
     const Geo& g = a.geo;
     const int tiles_x = (g.nx + a.tile_x - 1) / a.tile_x;
     const int tiles_y = (g.ny + a.tile_y - 1) / a.tile_y;
-    const size_t lds = tb_lds_bytes(a.nsteps, a.tile_x, a.tile_y, sizeof(T));
-    const int ps = tb_plane(a.nsteps, a.tile_x, a.tile_y, sizeof(T), 0);
+    using LT = typename TbLds<S, T>::type;
+    const size_t lds = tb_lds_bytes(a.nsteps, a.tile_x, a.tile_y, sizeof(LT), sizeof(T));
+    const int ps = tb_plane(a.nsteps, a.tile_x, a.tile_y, sizeof(LT), sizeof(T), 0);
     if (tb_threads(a.nsteps, a.tile_x, a.tile_y) == 512) {
         launch_tb_ps<S, T, SAMPLE, WPRE, 512, ALLOUT, 0>(a, tiles_x, tiles_y, lds);
         return;
     }
-    if constexpr (sizeof(T) == 4) {
+    if constexpr (sizeof(LT) == 2) {
+        if (ps == TB_PS16[0]) return launch_tb_ps<S, T, SAMPLE, WPRE, 1024, ALLOUT, TB_PS16[0]>(a, tiles_x, tiles_y, lds);
+        if (ps == TB_PS16[1]) return launch_tb_ps<S, T, SAMPLE, WPRE, 1024, ALLOUT, TB_PS16[1]>(a, tiles_x, tiles_y, lds);
+        if (ps == TB_PS16[2]) return launch_tb_ps<S, T, SAMPLE, WPRE, 1024, ALLOUT, TB_PS16[2]>(a, tiles_x, tiles_y, lds);
+    } else if constexpr (sizeof(T) == 4) {
         if (ps == TB_PS32[0]) return launch_tb_ps<S, T, SAMPLE, WPRE, 1024, ALLOUT, TB_PS32[0]>(a, tiles_x, tiles_y, lds);
         if (ps == TB_PS32[1]) return launch_tb_ps<S, T, SAMPLE, WPRE, 1024, ALLOUT, TB_PS32[1]>(a, tiles_x, tiles_y, lds);
     } else {
@@ -909,7 +928,7 @@ static hipError_t adj_t(const AdjLaunch& a) {
         const int tiles_x = (g.nx + a.tile_x - 1) / a.tile_x;
         const int tiles_y = (g.ny + a.tile_y - 1) / a.tile_y;
         const size_t lds = adj_tb_lds_bytes(a.nsteps, a.tile_x, a.tile_y, sizeof(T));
-        const int ps = tb_plane(a.nsteps, a.tile_x, a.tile_y, sizeof(T), (size_t)a.tile_x * a.tile_y * 8);
+        const int ps = tb_plane(a.nsteps, a.tile_x, a.tile_y, sizeof(T), sizeof(T), (size_t)a.tile_x * a.tile_y * 8);
         const int tb = tb_threads(a.nsteps, a.tile_x, a.tile_y);
         const dim3 grid(tiles_x * tiles_y);
         const S* gs = (const S*)a.gseg;
@@ -1039,34 +1058,45 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t str
 
 long blocks_for(long n) { return (n + BLOCK - 1) / BLOCK; }
 
-// Plane stride (values) of a blocked launch whose LDS also holds `extra`
-// bytes beyond the forward kernel's layout.
-int tb_plane(int nsteps, int tile_x, int tile_y, size_t elem, size_t extra) {
+// Plane stride (elements) of a blocked launch: LDS state elements of lsize
+// bytes, s plane and row cache of vsize-byte values, and `extra` bytes more.
+int tb_plane(int nsteps, int tile_x, int tile_y, size_t lsize, size_t vsize, size_t extra) {
     const long lw = tile_x + 2 * (nsteps - 1), lh = tile_y + 2 * (nsteps - 1);
     const long region = lw * lh;
-    extra += lh * (elem + 2);   // row cache
+    extra += lh * (vsize + 2);   // row cache
+    auto fits = [&](long ps) { return (size_t)ps * (2 * 9 * lsize + vsize) + extra <= TB_LDS_MAX; };
     if (region > 512) {
-        if (elem == 4) {
+        if (lsize == 2) {
+            for (int ps : TB_PS16)
+                if (ps >= region && fits(ps)) return ps;
+        } else if (lsize == 4) {
             for (int ps : TB_PS32)
-                if (ps >= region && (2 * 9 + 1) * (size_t)ps * elem + extra <= TB_LDS_MAX) return ps;
-        } else if (elem == 8) {
-            if (TB_PS64 >= region && (2 * 9 + 1) * (size_t)TB_PS64 * elem + extra <= TB_LDS_MAX) return TB_PS64;
+                if (ps >= region && fits(ps)) return ps;
+        } else if (lsize == 8) {
+            if (TB_PS64 >= region && fits(TB_PS64)) return TB_PS64;
         }
     }
     return (int)region;
 }
 
-size_t tb_lds_bytes(int nsteps, int tile_x, int tile_y, size_t elem) {
+size_t tb_lds_bytes(int nsteps, int tile_x, int tile_y, size_t lsize, size_t vsize) {
     const size_t lh = tile_y + 2 * (nsteps - 1);
     // two state buffers and the s plane, then the row cache
-    return (2 * 9 + 1) * (size_t)tb_plane(nsteps, tile_x, tile_y, elem, 0) * elem + lh * (elem + 2);
+    const size_t ps = tb_plane(nsteps, tile_x, tile_y, lsize, vsize, 0);
+    return ps * (2 * 9 * lsize + vsize) + lh * (vsize + 2);
 }
 
-size_t adj_tb_lds_bytes(int nsteps, int tile_x, int tile_y, size_t elem) {
+size_t adj_tb_lds_bytes(int nsteps, int tile_x, int tile_y, size_t vsize) {
     // sensitivity sums of the tile (FP64), then the forward kernel's layout
     const size_t sens = (size_t)tile_x * tile_y * 8;
     const size_t lh = tile_y + 2 * (nsteps - 1);
-    return sens + (2 * 9 + 1) * (size_t)tb_plane(nsteps, tile_x, tile_y, elem, sens) * elem + lh * (elem + 2);
+    const size_t ps = tb_plane(nsteps, tile_x, tile_y, vsize, vsize, sens);
+    return sens + ps * (2 * 9 * vsize + vsize) + lh * (vsize + 2);
+}
+
+size_t tb_lds_bytes_prec(int nsteps, int tile_x, int tile_y, int prec) {
+    return prec == 0 ? tb_lds_bytes(nsteps, tile_x, tile_y, 8, 8)
+                     : tb_lds_bytes(nsteps, tile_x, tile_y, prec == 1 ? 4 : 2, 4);
 }
 
 long tb_blocks(int nx, int ny, int tile_x, int tile_y) {
@@ -1078,15 +1108,27 @@ int tb_threads(int nsteps, int tile_x, int tile_y) {
     return lw * lh <= 512 ? 512 : 1024;
 }
 
-template <class S, class T, class A, int NT, int PS>
-static hipError_t tb_attr(int b) {
+template <class S, class T, int NT, int PS>
+static hipError_t tb_attr_fwd(int b) {
     const hipFuncAttribute at = hipFuncAttributeMaxDynamicSharedMemorySize;
     hipError_t e = hipFuncSetAttribute((const void*)k_step_tb<S, T, false, false, NT, false, PS>, at, b);
     if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, true, false, NT, false, PS>, at, b);
     if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, false, true, NT, false, PS>, at, b);
     if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, true, true, NT, false, PS>, at, b);
     if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tb<S, T, false, false, NT, true, PS>, at, b);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_adjoint_tb<S, T, A, NT, PS>, at, b);
+    return e;
+}
+
+template <class S, class T, class A, int NT, int PS>
+static hipError_t tb_attr_adj(int b) {
+    return hipFuncSetAttribute((const void*)k_adjoint_tb<S, T, A, NT, PS>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, b);
+}
+
+template <class S, class T, class A, int NT, int PS>
+static hipError_t tb_attr(int b) {
+    hipError_t e = tb_attr_fwd<S, T, NT, PS>(b);
+    if (e == hipSuccess) e = tb_attr_adj<S, T, A, NT, PS>(b);
     return e;
 }
 
@@ -1094,7 +1136,14 @@ template <class S, class T, class A>
 static hipError_t tb_attr_all(int b) {
     hipError_t e = tb_attr<S, T, A, 512, 0>(b);
     if (e == hipSuccess) e = tb_attr<S, T, A, 1024, 0>(b);
-    if constexpr (sizeof(T) == 4) {
+    if constexpr (sizeof(S) == 2) {
+        // forward kernels take the FP16 strides, the adjoint the FP32 ones
+        if (e == hipSuccess) e = tb_attr_fwd<S, T, 1024, TB_PS16[0]>(b);
+        if (e == hipSuccess) e = tb_attr_fwd<S, T, 1024, TB_PS16[1]>(b);
+        if (e == hipSuccess) e = tb_attr_fwd<S, T, 1024, TB_PS16[2]>(b);
+        if (e == hipSuccess) e = tb_attr_adj<S, T, A, 1024, TB_PS32[0]>(b);
+        if (e == hipSuccess) e = tb_attr_adj<S, T, A, 1024, TB_PS32[1]>(b);
+    } else if constexpr (sizeof(T) == 4) {
         if (e == hipSuccess) e = tb_attr<S, T, A, 1024, TB_PS32[0]>(b);
         if (e == hipSuccess) e = tb_attr<S, T, A, 1024, TB_PS32[1]>(b);
     } else {

@@ -87,9 +87,10 @@ hipError_t launch_finalize(const double* gamma, const double* sens, double* out,
 hipError_t launch_fill(double* p, long n, double v, hipStream_t stream);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
 long blocks_for(long n);
-int tb_plane(int nsteps, int tile_x, int tile_y, size_t elem, size_t extra);
-size_t tb_lds_bytes(int nsteps, int tile_x, int tile_y, size_t elem);
-size_t adj_tb_lds_bytes(int nsteps, int tile_x, int tile_y, size_t elem);
+int tb_plane(int nsteps, int tile_x, int tile_y, size_t lsize, size_t vsize, size_t extra);
+size_t tb_lds_bytes(int nsteps, int tile_x, int tile_y, size_t lsize, size_t vsize);
+size_t tb_lds_bytes_prec(int nsteps, int tile_x, int tile_y, int prec);   // forward kernel of a precision
+size_t adj_tb_lds_bytes(int nsteps, int tile_x, int tile_y, size_t vsize);
 long tb_blocks(int nx, int ny, int tile_x, int tile_y);
 hipError_t tb_prepare(int prec);
 int tb_threads(int nsteps, int tile_x, int tile_y);

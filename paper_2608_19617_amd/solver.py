@@ -195,6 +195,10 @@ class Solver:
         B.check(B.lib.lbm_set_blocking(self._ctx, int(nsteps), int(tile_x), int(tile_y)))
         self.blocking = (int(nsteps), int(tile_x), int(tile_y))
 
+    def set_adjoint_blocking(self, nsteps, tile_x=32, tile_y=16):
+        """Blocking of the adjoint launches over recomputed segments (D2Q9)."""
+        B.check(B.lib.lbm_set_adjoint_blocking(self._ctx, int(nsteps), int(tile_x), int(tile_y)))
+
     def close(self):
         if getattr(self, "_ctx", None):
             B.lib.lbm_destroy(self._ctx)

@@ -427,6 +427,40 @@ def test_long_blocks_match_single_steps(Solver, prec, case):
         assert rel_l2(g, g1) <= 100 * tol
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("case", [0, 1, 2, 3])
+def test_adjoint_blocking_matches_single_steps(Solver, prec, case):
+    """lbm_set_adjoint_blocking: blocked adjoint launches on tiles other than
+    the forward's, with several depths, give the single-step adjoint's
+    dJ/dgamma; bad arguments are rejected."""
+    from paper_2608_19617_amd.binding import LbmError
+    name, w = _small_cases()[case]
+    w.window_len, w.sample_every, w.ckpt_every, w.max_windows = 40, 20, 20, 2
+    prob = oracle_problem(w)
+    f0 = random_start_state(prob, seed=7)
+    tol = {"f64": 1e-12, "f32": 1e-5}[prec]
+    sv = Solver(w, prec)
+    sv.set_state(f0, 0)
+    sv.forward(2 * w.window_len)
+    sv.set_adjoint_blocking(1)
+    g1, J1 = sv.adjoint()
+    g1 = g1.cpu().numpy()
+    configs = {"f64": ((2, (16, 16)), (4, (25, 25)), (3, (32, 16)), (7, (16, 16))),
+               "f32": ((2, (16, 16)), (5, (25, 25)), (3, (48, 24)), (10, (16, 16)))}[prec]
+    with pytest.raises(LbmError, match="LBM_E_INVALID"):
+        sv.set_adjoint_blocking(17, 16, 16)       # more than 16 steps
+    for na, tile in configs:
+        sv.set_adjoint_blocking(na, *tile)
+        g, J = sv.adjoint()
+        assert J == J1
+        assert rel_l2(g.cpu().numpy(), g1) <= tol, (na, tile, rel_l2(g.cpu().numpy(), g1))
+    with pytest.raises(LbmError, match="LBM_E_INVALID"):
+        sv.set_adjoint_blocking(4, 8, 8)          # fewer than 256 nodes per tile
+    with pytest.raises(LbmError, match="LBM_E_INVALID"):
+        sv.set_adjoint_blocking(16, 64, 64)       # more LDS than a compute unit has
+    sv.close()
+
+
 # ------------------------------------------------- full-size configurations
 #
 # At full size the oracle cannot replay whole windows in a test, so the GPU
