@@ -237,6 +237,19 @@ def hbm_suite(args, torch):
     events; one JSON line per configuration."""
     from paper_2608_19617_amd import workloads as W
     from paper_2608_19617_amd.solver import Solver
+    # reference ceiling: a plain device-to-device copy of 2 GiB
+    a = torch.ones(2 ** 29, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * a.numel() * 4 * 10 / (time.perf_counter() - t0) / 1e9
+    print(json.dumps({"suite": "hbm", "device_copy_2GiB_GBs": round(copy_gbs, 1),
+                      "frac_of_hbm_peak": round(copy_gbs / HBM_PEAK_GBS, 4)}), flush=True)
+    del a, b
     cases = []
     for prec in ("f64", "f32", "f16s"):
         w = W.cylinder_wake(nx=8192, ny=2048, radius=128, window_len=500, sample_every=20, ckpt_every=50,

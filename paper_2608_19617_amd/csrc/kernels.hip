@@ -847,7 +847,7 @@ static inline dim3 grid_for(long n) { return dim3((unsigned)((n + BLOCK - 1) / B
 // that holds them when the LDS allows; other launches use their region size.
 static constexpr int TB_PS32[2] = {1856, 2040};
 static constexpr int TB_PS64 = 1020;
-static constexpr int TB_PS16[3] = {1856, 3584, 3712};   // FP16 LDS state (FP16S forward)
+static constexpr int TB_PS16[2] = {1856, 3584};   // FP16 LDS state (FP16S forward)
 
 template <class S, class T, bool SAMPLE, bool WPRE, int TB, bool ALLOUT, int PS>
 static void launch_tb_ps(const StepLaunch& a, int tiles_x, int tiles_y, size_t lds) {
@@ -872,7 +872,6 @@ static void launch_tb(const StepLaunch& a) {
     if constexpr (sizeof(LT) == 2) {
         if (ps == TB_PS16[0]) return launch_tb_ps<S, T, SAMPLE, WPRE, 1024, ALLOUT, TB_PS16[0]>(a, tiles_x, tiles_y, lds);
         if (ps == TB_PS16[1]) return launch_tb_ps<S, T, SAMPLE, WPRE, 1024, ALLOUT, TB_PS16[1]>(a, tiles_x, tiles_y, lds);
-        if (ps == TB_PS16[2]) return launch_tb_ps<S, T, SAMPLE, WPRE, 1024, ALLOUT, TB_PS16[2]>(a, tiles_x, tiles_y, lds);
     } else if constexpr (sizeof(T) == 4) {
         if (ps == TB_PS32[0]) return launch_tb_ps<S, T, SAMPLE, WPRE, 1024, ALLOUT, TB_PS32[0]>(a, tiles_x, tiles_y, lds);
         if (ps == TB_PS32[1]) return launch_tb_ps<S, T, SAMPLE, WPRE, 1024, ALLOUT, TB_PS32[1]>(a, tiles_x, tiles_y, lds);
@@ -1140,7 +1139,6 @@ static hipError_t tb_attr_all(int b) {
         // forward kernels take the FP16 strides, the adjoint the FP32 ones
         if (e == hipSuccess) e = tb_attr_fwd<S, T, 1024, TB_PS16[0]>(b);
         if (e == hipSuccess) e = tb_attr_fwd<S, T, 1024, TB_PS16[1]>(b);
-        if (e == hipSuccess) e = tb_attr_fwd<S, T, 1024, TB_PS16[2]>(b);
         if (e == hipSuccess) e = tb_attr_adj<S, T, A, 1024, TB_PS32[0]>(b);
         if (e == hipSuccess) e = tb_attr_adj<S, T, A, 1024, TB_PS32[1]>(b);
     } else if constexpr (sizeof(T) == 4) {
