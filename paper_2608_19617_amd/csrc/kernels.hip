@@ -153,52 +153,82 @@ __global__ __launch_bounds__(BLOCK) void k_step(const S* __restrict__ gin, S* __
 // The region of a step is [m, LW - m) x [m, LH - m), cut to the domain on a
 // non-periodic axis and, for the output step, to the tile's own nodes
 // (unwrapped x < nx, y < ny, so that periodic wraps are not written twice).
-// Its cells are dealt to threads row by row, except the column of an open
-// x-face (LDS x = fc, always the first or last column of the cut region),
-// which comes last: its nodes then share one or two wavefronts, so the
-// Zou-He and ghost-cell work does not diverge every wavefront of the tile.
+// Its cells are dealt to threads in two parts: first the interior rectangle
+// (nodes off every non-periodic face, which need neither the Zou-He rule nor
+// ghost-cell stores), row by row; then the face frame (the node rows and
+// columns on non-periodic faces, at most one wide on each side), which take
+// the boundary work. The face cells thus share a few wavefronts instead of
+// diverging every wavefront of a boundary tile.
 struct TbPhase {
-    int ax, ay;         // first LDS column and row of the cut region
-    int rwp, sh;        // row width without the face column; 1 if fc == ax
-    int fc, nrow;       // face column or -1; cells before the face column's
-    int count;          // cells of the step
-    float inv;          // 1 / rwp
+    int ax, ay, rw;           // cut region: first LDS column and row, width
+    int ix0, iy0, iw, ih;     // interior rectangle: first column and row, width, height
+    int ni;                   // interior cells (iw * ih)
+    int nb, nt, nl;           // face frame: bottom row, top row, left column present (0/1)
+    int count;                // all cells of the step
+    float inv;                // 1 / iw
 };
 
-__device__ __forceinline__ TbPhase tb_phase(const Geo& g, int m, int LW, int LH, int fcol, int x0, int y0,
-                                            bool output) {
+__device__ __forceinline__ TbPhase tb_phase(const Geo& g, int m, int LW, int LH, int x0, int y0, bool output) {
     int ax = m, bx = LW - m, ay = m, by = LH - m;
     if (!g.per_x) ax = max(ax, -x0);
     if (!g.per_y) ay = max(ay, -y0);
     if (!g.per_x || output) bx = min(bx, g.nx - x0);
     if (!g.per_y || output) by = min(by, g.ny - y0);
-    const int rw = max(bx - ax, 0), rh = max(by - ay, 0);
+    bx = max(bx, ax);
+    by = max(by, ay);
+    int ix0 = ax, ix1 = bx, iy0 = ay, iy1 = by;
+    if (!g.per_x) {
+        ix0 = min(max(ax, 1 - x0), bx);
+        ix1 = max(min(bx, g.nx - 1 - x0), ix0);
+    }
+    if (!g.per_y) {
+        iy0 = min(max(ay, 1 - y0), by);
+        iy1 = max(min(by, g.ny - 1 - y0), iy0);
+    }
     TbPhase p;
     p.ax = ax;
     p.ay = ay;
-    p.fc = (fcol >= ax && fcol < bx) ? fcol : -1;
-    p.sh = (p.fc >= 0 && p.fc == ax) ? 1 : 0;
-    p.rwp = p.fc >= 0 ? rw - 1 : rw;
-    p.nrow = p.rwp * rh;
-    p.count = rw * rh;
-    p.inv = 1.0f / (float)p.rwp;
+    p.rw = bx - ax;
+    p.ix0 = ix0;
+    p.iy0 = iy0;
+    p.iw = ix1 - ix0;
+    p.ih = iy1 - iy0;
+    p.ni = p.iw * p.ih;
+    p.nb = iy0 - ay;        // 0 or 1
+    p.nt = by - iy1;        // 0 or 1
+    p.nl = ix0 - ax;        // 0 or 1; the right column has bx - ix1 cells per row
+    p.count = p.rw * (by - ay);
+    p.inv = 1.0f / (float)p.iw;
     return p;
 }
 
 // Cell i (< count) of a step: LDS coordinates and the (wrapped) global node.
+// Returns true for a face cell.
 struct TbCell {
     int lx, ly, x, y, n, cell;
 };
 
-__device__ __forceinline__ void tb_cell(const Geo& g, int i, const TbPhase& p, int LW, int x0, int y0,
+__device__ __forceinline__ bool tb_cell(const Geo& g, int i, const TbPhase& p, int LW, int x0, int y0,
                                         TbCell& c) {
-    if (i < p.nrow) {
+    bool face = false;
+    if (i < p.ni) {
         const int qy = (int)(((float)i + 0.5f) * p.inv);   // exact for i < 2^12
-        c.ly = p.ay + qy;
-        c.lx = p.ax + p.sh + (i - qy * p.rwp);
+        c.ly = p.iy0 + qy;
+        c.lx = p.ix0 + (i - qy * p.iw);
     } else {
-        c.ly = p.ay + (i - p.nrow);
-        c.lx = p.fc;
+        face = true;
+        int j = i - p.ni;
+        const int nrow = p.rw * (p.nb + p.nt);
+        if (j < nrow) {                                     // bottom row, then top row
+            const bool top = j >= p.rw * p.nb;
+            c.ly = top ? p.iy0 + p.ih : p.ay;
+            c.lx = p.ax + (top ? j - p.rw * p.nb : j);
+        } else {                                            // left column, then right column
+            j -= nrow;
+            const bool right = j >= p.ih * p.nl;
+            c.ly = p.iy0 + (right ? j - p.ih * p.nl : j);
+            c.lx = right ? p.ix0 + p.iw : p.ax;
+        }
     }
     int x = x0 + c.lx, y = y0 + c.ly;
     if (g.per_x) x = ((x % g.nx) + g.nx) % g.nx;
@@ -207,6 +237,7 @@ __device__ __forceinline__ void tb_cell(const Geo& g, int i, const TbPhase& p, i
     c.y = y;
     c.n = y * g.nx + x;
     c.cell = c.ly * LW + c.lx;
+    return face;
 }
 
 // Tile of this workgroup. Workgroups are dealt to the 8 XCDs of the chip
@@ -277,15 +308,17 @@ __device__ __forceinline__ int tb_open(const Geo& g, const TbRows<T>& r, const T
 }
 
 // Pull of node c from the previous step's LDS buffer (walls come from the
-// ghost cells), then the Zou-He rule on open nodes.
+// ghost cells); on a face cell also the Zou-He rule of an open node.
 template <class T, class LT>
 __device__ __forceinline__ void tb_pull_lds(const Geo& g, const LT* __restrict__ srcb, int plane_sz, int LW,
-                                            const TbRows<T>& rows, T d0, const TbCell& c, T h[9]) {
+                                            const TbRows<T>& rows, T d0, const TbCell& c, bool face, T h[9]) {
     using L = D2Q9;
 #pragma unroll
     for (int a = 0; a < L::Q; ++a) h[a] = (T)srcb[a * plane_sz + c.cell - L::cy[a] * LW - L::cx[a]];
-    const int oc = tb_open<T>(g, rows, c);
-    if (oc) zou_he_rows<L, T>(oc, rows.u[c.ly], d0, h);
+    if (face) {
+        const int oc = tb_open<T>(g, rows, c);
+        if (oc) zou_he_rows<L, T>(oc, rows.u[c.ly], d0, h);
+    }
 }
 
 // Ghost-cell stores of a node on a non-periodic face. For every direction
@@ -356,12 +389,6 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
     int tx, ty;
     tb_tile(tiles_x, tx, ty);
     const int x0 = tx * ox - H, y0 = ty * oy - H;     // global coords of LDS cell (0, 0)
-    // LDS column of an open x-face in the region (west first), or -1
-    int fcol = -1;
-    if (!g.per_x) {
-        if (x0 <= 0) fcol = -x0;
-        else if (x0 + LW - 1 >= g.nx - 1) fcol = g.nx - 1 - x0;
-    }
 
     // step 1: pull from global memory over the whole LDS region. A thread
     // takes cells i and i + TB together and issues the loads of both before
@@ -369,11 +396,11 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
     // memory once.
     tb_fill_rows<T, TB>(g, rows, LH, y0);
     {
-        const TbPhase ph1 = tb_phase(g, 0, LW, LH, fcol, x0, y0, false);
+        const TbPhase ph1 = tb_phase(g, 0, LW, LH, x0, y0, false);
         LT* dst = lds + bufsz;
         for (int i = (int)threadIdx.x; i < ph1.count; i += 2 * TB) {
             TbCell c[2];
-            bool v[2];
+            bool v[2], face[2];
             T h[2][L::Q];
             T sv[2];
             int oc[2];
@@ -381,8 +408,8 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
             for (int u = 0; u < 2; ++u) {
                 v[u] = i + u * TB < ph1.count;
                 if (v[u]) {
-                    tb_cell(g, i + u * TB, ph1, LW, x0, y0, c[u]);
-                    oc[u] = open_code<L>(g, c[u].x, c[u].y, 0);
+                    face[u] = tb_cell(g, i + u * TB, ph1, LW, x0, y0, c[u]);
+                    oc[u] = face[u] ? open_code<L>(g, c[u].x, c[u].y, 0) : 0;
                     pull<L, S, T>(gin, g, c[u].n, c[u].x, c[u].y, 0, h[u]);
                     sv[u] = sfield[c[u].n];
                 }
@@ -398,7 +425,7 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
                 collide<L, T>(mo, sv[u], out);
 #pragma unroll
                 for (int a = 0; a < L::Q; ++a) dst[a * plane_sz + c[u].cell] = (LT)out[a];
-                tb_ghosts<LT, T, 1>(g, dst, plane_sz, LW, LH, c[u], out);
+                if (face[u]) tb_ghosts<LT, T, 1>(g, dst, plane_sz, LW, LH, c[u], out);
                 if (ALLOUT && tb_owned(g, c[u], H, ox, oy, x0, y0)) {
 #pragma unroll
                     for (int a = 0; a < L::Q; ++a) plane(allout, a, g.N)[(unsigned)c[u].n] = (S)out[a];
@@ -409,21 +436,21 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
     }
     // steps 2 .. nt-1: LDS to LDS over shrinking regions
     for (int t = 2; t < nt; ++t) {
-        const TbPhase pt = tb_phase(g, t - 1, LW, LH, fcol, x0, y0, false);
+        const TbPhase pt = tb_phase(g, t - 1, LW, LH, x0, y0, false);
         LT* dst = lds + (t & 1) * bufsz;
         const LT* srcb = lds + ((t - 1) & 1) * bufsz;
         for (int i = (int)threadIdx.x; i < pt.count; i += TB) {
             TbCell c;
-            tb_cell(g, i, pt, LW, x0, y0, c);
+            const bool face = tb_cell(g, i, pt, LW, x0, y0, c);
             T h[L::Q];
-            tb_pull_lds<T, LT>(g, srcb, plane_sz, LW, rows, d0, c, h);
+            tb_pull_lds<T, LT>(g, srcb, plane_sz, LW, rows, d0, c, face, h);
             Moments<L, T> mo;
             moments<L, T>(h, ph, mo);
             T out[L::Q];
             collide<L, T>(mo, sbuf[c.cell], out);
 #pragma unroll
             for (int a = 0; a < L::Q; ++a) dst[a * plane_sz + c.cell] = (LT)out[a];
-            tb_ghosts<LT, T, 1>(g, dst, plane_sz, LW, LH, c, out);
+            if (face) tb_ghosts<LT, T, 1>(g, dst, plane_sz, LW, LH, c, out);
             if (ALLOUT && tb_owned(g, c, H, ox, oy, x0, y0)) {
                 S* o = allout + (size_t)(t - 1) * slot;
 #pragma unroll
@@ -435,13 +462,13 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
     // step nt: the output tile, from LDS to global memory (samples, checkpoint)
     double v[3] = {0.0, 0.0, 0.0};
     {
-        const TbPhase pn = tb_phase(g, nt - 1, LW, LH, fcol, x0, y0, true);
+        const TbPhase pn = tb_phase(g, nt - 1, LW, LH, x0, y0, true);
         const LT* srcb = lds + ((nt - 1) & 1) * bufsz;
         for (int i = (int)threadIdx.x; i < pn.count; i += TB) {
             TbCell c;
-            tb_cell(g, i, pn, LW, x0, y0, c);
+            const bool face = tb_cell(g, i, pn, LW, x0, y0, c);
             T h[L::Q];
-            tb_pull_lds<T, LT>(g, srcb, plane_sz, LW, rows, d0, c, h);
+            tb_pull_lds<T, LT>(g, srcb, plane_sz, LW, rows, d0, c, face, h);
             if (WPRE) {
 #pragma unroll
                 for (int a = 0; a < L::Q; ++a) plane(pre, a, g.N)[(unsigned)c.n] = (S)h[a];
@@ -673,11 +700,6 @@ __global__ __launch_bounds__(TB) void k_adjoint_tb(const A* __restrict__ nu_in, 
     int tx, ty;
     tb_tile(tiles_x, tx, ty);
     const int x0 = tx * ox - H, y0 = ty * oy - H;
-    int fcol = -1;
-    if (!g.per_x) {
-        if (x0 <= 0) fcol = -x0;
-        else if (x0 + LW - 1 >= g.nx - 1) fcol = g.nx - 1 - x0;
-    }
     tb_fill_rows<T, TB>(g, rows, LH, y0);
     __syncthreads();
     for (int t = 1; t <= nt; ++t) {
@@ -685,13 +707,13 @@ __global__ __launch_bounds__(TB) void k_adjoint_tb(const A* __restrict__ nu_in, 
         const S* Gk2 = gseg + (size_t)(k - 2 - kseg) * slot;
         const double src_w = (k > ns && (k - ns) % dW == 0) ? wgt : 0.0;
         const bool last = t == nt;
-        const TbPhase pt = tb_phase(g, t - 1, LW, LH, fcol, x0, y0, last);
+        const TbPhase pt = tb_phase(g, t - 1, LW, LH, x0, y0, last);
         const T* srcb = lds + ((t - 1) & 1) * bufsz;
         T* dst = lds + (t & 1) * bufsz;
         for (int i = (int)threadIdx.x; i < pt.count; i += TB) {
             TbCell c;
-            tb_cell(g, i, pt, LW, x0, y0, c);
-            const int oc = tb_open<T>(g, rows, c);
+            const bool face = tb_cell(g, i, pt, LW, x0, y0, c);
+            const int oc = face ? tb_open<T>(g, rows, c) : 0;
             const T u0 = rows.u[c.ly];
             // pre-state f^{k-1}
             T h[L::Q];
@@ -761,11 +783,13 @@ __global__ __launch_bounds__(TB) void k_adjoint_tb(const A* __restrict__ nu_in, 
 #pragma unroll
                 for (int a = 0; a < L::Q; ++a) dst[a * plane_sz + c.cell] = mu[a];
                 // ghost cells of the adjoint wall rule (0 on an open node)
-                if (oc) {
+                if (face) {
+                    if (oc) {
 #pragma unroll
-                    for (int a = 0; a < L::Q; ++a) mu[a] = (T)0;
+                        for (int a = 0; a < L::Q; ++a) mu[a] = (T)0;
+                    }
+                    tb_ghosts<T, T, -1>(g, dst, plane_sz, LW, LH, c, mu);
                 }
-                tb_ghosts<T, T, -1>(g, dst, plane_sz, LW, LH, c, mu);
             }
         }
         __syncthreads();
