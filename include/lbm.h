@@ -229,6 +229,22 @@ lbm_status lbm_timing(lbm_ctx* ctx, int enable, double* out);
  * turns both off. */
 lbm_status lbm_set_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y);
 
+/* Temporal blocking of D3Q19 forward (and recompute) launches: nsteps = 2
+ * advances two steps per launch. A workgroup owns tile_x x tile_y nodes in
+ * x and y and tile_z consecutive z planes; it takes the first step plane by
+ * plane over the tile grown by one node in x and y, keeping three planes of
+ * that state in LDS (walls on x and y faces as ghost cells, as for D2Q9),
+ * and the second step of each plane as soon as the plane above is ready.
+ * nsteps = 1 turns it off. Requires at least 256 nodes per block,
+ * (tile_x + 2) * (tile_y + 2) <= 1024 and 3 (tile_x + 2)(tile_y + 2) x
+ * (19 state values in the storage-rounded LDS type + one compute-type
+ * value) within 159 KB, and a state (19 x nodes x storage bytes) below
+ * 4 GB. Samples, checkpoints and window ends fall on a launch's last step as
+ * in 2D. Adjoint launches stay single-step. Errors:
+ * LBM_E_INVALID for a D2Q9 context or out-of-range arguments, LBM_E_HIP if
+ * the LDS opt-in fails. */
+lbm_status lbm_set_blocking_3d(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y, int tile_z);
+
 /* Blocking of the adjoint launches that pull their pre-states from a
  * recomputed segment (D2Q9 only): up to nsteps reverse steps per launch on
  * tile_x x tile_y output tiles, the adjoint populations (FP32, or FP64 for

@@ -169,6 +169,7 @@ struct lbm_ctx {
     std::vector<int> conv;
     bool unstable;
     int tb_steps, tile_x, tile_y;    // temporal blocking of forward launches (1 = off)
+    int tile_z;                      // D3Q19 tiles are tile_x x tile_y x tile_z
     int adj_steps, adj_tile_x, adj_tile_y;   // blocked adjoint launches (adj_steps 1 = off)
     Timer tm;
 };
@@ -239,6 +240,7 @@ StepLaunch step_args(lbm_ctx* c) {
     a.nsteps = 1;
     a.tile_x = c->tile_x;
     a.tile_y = c->tile_y;
+    a.tile_z = c->tile_z;
     a.allout = nullptr;
     a.allout_slot = 0;
     return a;
@@ -378,7 +380,7 @@ lbm_status default_adj_blocking(lbm_ctx* c, int nsteps, int tile_x, int tile_y) 
     c->adj_steps = 1;
     c->adj_tile_x = tile_x;
     c->adj_tile_y = tile_y;
-    if (nsteps > 1) {
+    if (nsteps > 1 && c->cfg.lattice == LBM_D2Q9) {
         int nfirst = nsteps;
         if (c->L.N > 400000) {
             nfirst = c->cfg.prec == LBM_F64 ? 4 : 5;
@@ -418,6 +420,32 @@ lbm_status set_blocking(lbm_ctx* c, int nsteps, int tile_x, int tile_y) {
     return default_adj_blocking(c, nsteps, tile_x, tile_y);
 }
 
+lbm_status set_blocking_3d(lbm_ctx* c, int nsteps, int tile_x, int tile_y, int tile_z) {
+    if (c->cfg.lattice != LBM_D3Q19) return fail(LBM_E_INVALID, "3D blocking needs the D3Q19 lattice");
+    if (nsteps != 1 && nsteps != 2) return fail(LBM_E_INVALID, "D3Q19 blocking takes 1 or 2 steps");
+    if (nsteps == 2) {
+        if (tile_x < 1 || tile_y < 1 || tile_z < 1 || (long)tile_x * tile_y * tile_z < 256)
+            return fail(LBM_E_INVALID, "tile must hold at least 256 nodes");
+        if ((long)(tile_x + 2) * (tile_y + 2) > 1024)
+            return fail(LBM_E_INVALID, "(tile_x + 2) * (tile_y + 2) must be at most 1024");
+        if (tbz_lds_bytes_prec(tile_x, tile_y, c->cfg.prec) > TB_LDS_MAX)
+            return fail(LBM_E_INVALID, "tile needs more than 159 KB of LDS");
+        // the blocked kernel addresses a state with 32-bit byte offsets
+        if ((size_t)c->L.Q * c->L.N * c->L.ss > TBZ_STATE_MAX)
+            return fail(LBM_E_INVALID, "state too large for D3Q19 blocking (limit 4 GB)");
+        const long tiles = (long)((c->cfg.nx + tile_x - 1) / tile_x) * ((c->cfg.ny + tile_y - 1) / tile_y) *
+                           ((c->cfg.nz + tile_z - 1) / tile_z);
+        if (tiles > c->L.pstride) return fail(LBM_E_INVALID, "too many tiles");
+        HIPCHK(tb_prepare(c->cfg.prec));
+        c->tile_x = tile_x;
+        c->tile_y = tile_y;
+        c->tile_z = tile_z;
+    }
+    c->tb_steps = nsteps;
+    c->adj_steps = 1;
+    return LBM_OK;
+}
+
 lbm_status set_adj_blocking(lbm_ctx* c, int nsteps, int tile_x, int tile_y) {
     if (nsteps < 1 || nsteps > 16) return fail(LBM_E_INVALID, "nsteps must be in [1, 16]");
     if (nsteps > 1) {
@@ -443,6 +471,11 @@ extern "C" {
 lbm_status lbm_set_blocking(lbm_ctx* c, int nsteps, int tile_x, int tile_y) {
     if (!c) return fail(LBM_E_INVALID, "NULL context");
     return set_blocking(c, nsteps, tile_x, tile_y);
+}
+
+lbm_status lbm_set_blocking_3d(lbm_ctx* c, int nsteps, int tile_x, int tile_y, int tile_z) {
+    if (!c) return fail(LBM_E_INVALID, "NULL context");
+    return set_blocking_3d(c, nsteps, tile_x, tile_y, tile_z);
 }
 
 lbm_status lbm_set_adjoint_blocking(lbm_ctx* c, int nsteps, int tile_x, int tile_y) {
@@ -547,6 +580,7 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
     c->adj_tile_y = 16;
     c->tile_x = 32;
     c->tile_y = 16;
+    c->tile_z = 8;
 
     auto bail = [&](lbm_status s2) {
         std::string keep = g_err;

@@ -143,6 +143,44 @@ __device__ __forceinline__ void pull(const S* __restrict__ G, const Geo& g, int 
     }
 }
 
+// Source of every population of the pull into node (x, y, z), as element
+// indices into the state that include the plane (a * N + node); the same
+// sources as pull. The branch between interior and boundary nodes only
+// computes indices, so the loads that follow are one straight run with no
+// join between them (no wait on loads already in flight at a join).
+template <class L>
+__device__ __forceinline__ void pull_index(const Geo& g, int n, int x, int y, int z, unsigned e[L::Q]) {
+    const int N = g.N;
+    const bool interior = x > 0 && x < g.nx - 1 && y > 0 && y < g.ny - 1 &&
+                          (L::D == 2 || (z > 0 && z < g.nz - 1));
+    if (interior) {
+#pragma unroll
+        for (int a = 0; a < L::Q; ++a) {
+            const int off = L::cx[a] + L::cy[a] * g.nx + L::cz[a] * g.nx * g.ny;
+            e[a] = (unsigned)(a * N - off) + (unsigned)n;
+        }
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) {
+        int xs = x - L::cx[a], ys = y - L::cy[a], zs = z - L::cz[a];
+        bool out = false;
+        if (xs < 0 || xs >= g.nx) {
+            if (g.per_x) xs = xs < 0 ? xs + g.nx : xs - g.nx;
+            else out = true;
+        }
+        if (ys < 0 || ys >= g.ny) {
+            if (g.per_y) ys = ys < 0 ? ys + g.ny : ys - g.ny;
+            else out = true;
+        }
+        if (L::D == 3 && (zs < 0 || zs >= g.nz)) {
+            if (g.per_z) zs = zs < 0 ? zs + g.nz : zs - g.nz;
+            else out = true;
+        }
+        e[a] = out ? (unsigned)(L::opp[a] * N + n) : (unsigned)(a * N + (zs * g.ny + ys) * g.nx + xs);
+    }
+}
+
 // Zou-He rule on an open x-face node (Eqs. inlet, outlet; the west
 // pressure outlet is their x-mirror; in 3D the same rule with the
 // tangential momentum correction of every transverse axis). In shifted

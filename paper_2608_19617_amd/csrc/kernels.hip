@@ -494,6 +494,351 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
     }
 }
 
+// Two forward steps per launch for D3Q19, marching along z. A workgroup owns
+// an output block of ox x oy x oz nodes: an xy tile and a run of oz planes.
+// Step 1 is taken plane by plane, from the plane below the run to the plane
+// above it, over the tile grown by one node in x and y (cut to the domain on
+// non-periodic axes), and its post-collision state is kept in LDS in a ring
+// of three plane slots; step 2 of plane k follows once step 1 of plane k + 1
+// is in the ring, pulls from the three slots and writes to global memory.
+// The global loads of the next step-1 plane are issued before step 2 of the
+// current plane, so they are in flight while it computes. Halo work is only
+// in x and y (plus two planes per run), unlike a tile grown in all three
+// axes.
+//
+// Walls on x and y faces are ghost cells as in the D2Q9 kernel: a face node
+// stores each population leaving across the face at cell + c_b in plane
+// opp(b) of the slot of plane k + c_bz. A wall on a z face is the halfway
+// reflection taken in the step-2 pull itself; a whole plane lies on such a
+// face, so that choice is uniform across the workgroup. Slot reuse is safe:
+// step 1 of plane k + 1 writes ghosts into the slot of plane k + 2, which
+// still holds plane k - 1 for step 2 of plane k, but only into planes with
+// c_z = -1, and step 2 reads plane k - 1 only in planes with c_z = +1.
+//
+// LDS: the s values of the three slots (compute type), then the three slots
+// of Q planes of (ox + 2) x (oy + 2) values in the storage-rounded LDS type.
+// TB threads (256 for planes of up to 256 region cells, else 512) take U
+// cells each of a plane (U = 2 for regions of more than 512 cells).
+
+// Open-face code of a node's (x, y) position (open_code without the z test).
+__device__ __forceinline__ int open_code_xy(const Geo& g, int x, int y) {
+    if (g.per_x) return 0;
+    if (x == 0) {
+        const int k = g.west[y];
+        return k ? 1 + k : 0;
+    }
+    if (x == g.nx - 1) {
+        const int k = g.east[y];
+        return k ? 4 + k : 0;
+    }
+    return 0;
+}
+
+// Ghost-cell stores of a D3Q19 node on non-periodic x or y faces: each
+// direction b leaving across such a face stores v[b] at cell + c_b (in x, y)
+// in plane opp(b) of the slot of the plane the direction reaches (slot[0]
+// for c_bz = -1, slot[1] for 0, slot[2] for +1; slots are Q * psz apart).
+template <class LT, class T>
+__device__ __forceinline__ void tbz_ghosts(const Geo& g, LT* __restrict__ ring, int psz, int LW, int LH,
+                                           const int slot[3], const TbCell& c, const T v[19]) {
+    using L = D3Q19;
+    const bool inner = c.lx >= 1 && c.ly >= 1 && c.lx <= LW - 2 && c.ly <= LH - 2;
+    if (!inner) return;
+    const bool fx0 = !g.per_x && c.x == 0, fx1 = !g.per_x && c.x == g.nx - 1;
+    const bool fy0 = !g.per_y && c.y == 0, fy1 = !g.per_y && c.y == g.ny - 1;
+#pragma unroll
+    for (int b = 1; b < L::Q; ++b) {
+        const int sx = L::cx[b], sy = L::cy[b];
+        const bool leaves = (sx < 0 && fx0) || (sx > 0 && fx1) || (sy < 0 && fy0) || (sy > 0 && fy1);
+        if (leaves) ring[(slot[L::cz[b] + 1] * L::Q + L::opp[b]) * psz + c.cell + sy * LW + sx] = (LT)v[b];
+    }
+}
+
+// Workgroup barrier that orders LDS accesses only, so global loads issued
+// before it stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Raw buffer access (the range check of a buffer resource): a byte offset
+// of BUF_OOB lies beyond every array, so a store there is dropped and a load
+// returns 0. The z-marching kernel issues all of its global loads and stores
+// this way and unconditionally, so that every plane issues the same sequence
+// of vector memory operations whatever the lane, plane or face; the
+// compiler's count of the loads still in flight is then exact across its
+// branches, and the loads of two planes stay in flight behind the current
+// one. The arrays must be smaller than BUF_OOB bytes (checked by the host).
+constexpr unsigned BUF_OOB = 0xFFFFFFF0u;
+using BufRsrc = __amdgpu_buffer_rsrc_t;
+using BufU2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(BufRsrc(), 0, 0, 0));
+
+// The offset passes through an empty asm statement, so that the compiler
+// cannot see its out-of-range value and split one access into branches.
+__device__ __forceinline__ unsigned buf_off(unsigned off) {
+    asm("" : "+v"(off));
+    return off;
+}
+
+__device__ __forceinline__ BufRsrc buf_rsrc(const void* p, size_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)(unsigned)bytes, 0x00020000);
+}
+__device__ __forceinline__ void buf_ld(BufRsrc r, unsigned off, float& v) {
+    v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)buf_off(off), 0, 0));
+}
+__device__ __forceinline__ void buf_ld(BufRsrc r, unsigned off, double& v) {
+    v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)buf_off(off), 0, 0));
+}
+__device__ __forceinline__ void buf_ld(BufRsrc r, unsigned off, _Float16& v) {
+    v = __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)buf_off(off), 0, 0));
+}
+// FP16 storage is loaded into a full 32-bit register (zero-extended), so
+// that two values in flight never share one register.
+__device__ __forceinline__ void buf_ld(BufRsrc r, unsigned off, unsigned& v) {
+    v = (unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, (int)buf_off(off), 0, 0);
+}
+template <class S>
+struct BufReg {
+    using type = S;
+};
+template <>
+struct BufReg<_Float16> {
+    using type = unsigned;
+};
+template <class T, class R>
+__device__ __forceinline__ T from_reg(R v) {
+    if constexpr (sizeof(R) == 4 && !std::is_floating_point<R>::value)
+        return (T)__builtin_bit_cast(_Float16, (unsigned short)v);
+    else
+        return (T)v;
+}
+
+__device__ __forceinline__ void buf_st(BufRsrc r, unsigned off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)buf_off(off), 0, 0);
+}
+__device__ __forceinline__ void buf_st(BufRsrc r, unsigned off, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(BufU2, v), r, (int)buf_off(off), 0, 0);
+}
+__device__ __forceinline__ void buf_st(BufRsrc r, unsigned off, _Float16 v) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)buf_off(off), 0, 0);
+}
+
+template <class S, class T, bool SAMPLE, bool WPRE, int TB, int U, bool ALLOUT>
+__global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* __restrict__ gout,
+                                                 S* __restrict__ pre, const T* __restrict__ sfield, Geo g, Phys ph,
+                                                 Obj ob, double* __restrict__ partials, int part_stride, int ox,
+                                                 int oy, int oz, int tiles_x, int tiles_y, S* __restrict__ allout) {
+    using L = D3Q19;
+    using LT = typename TbLds<S, T>::type;
+    extern __shared__ unsigned char lds_raw[];
+    const int LW = ox + 2, LH = oy + 2, psz = LW * LH;
+    T* sring = reinterpret_cast<T*>(lds_raw);
+    LT* ring = reinterpret_cast<LT*>(sring + 3 * psz);
+    const int b = (int)blockIdx.x;
+    const int tx = b % tiles_x, ty = (b / tiles_x) % tiles_y, tz = b / (tiles_x * tiles_y);
+    const int x0 = tx * ox - 1, y0 = ty * oy - 1;       // global x, y of LDS cell (0, 0)
+    const int zs = tz * oz, nzc = min(oz, g.nz - zs);   // output planes zs .. zs + nzc - 1
+    const int N = g.N, nxy = g.nx * g.ny;
+    const T d0 = (T)g.drho_out;
+    const size_t state_bytes = (size_t)L::Q * N * sizeof(S);
+    const BufRsrc rin = buf_rsrc(gin, state_bytes);
+    const BufRsrc rs = buf_rsrc(sfield, (size_t)N * sizeof(T));
+    const BufRsrc rout = buf_rsrc(gout, state_bytes);
+    const BufRsrc rpre = buf_rsrc(WPRE ? pre : gout, state_bytes);
+    const BufRsrc rall = buf_rsrc(ALLOUT ? allout : gout, state_bytes);
+
+    // this thread's cells of a plane, the same on every plane: up to U of
+    // the step-1 region and U of the output tile; a lane without a cell
+    // takes LDS cell (1, 1) and node 0 and stores nothing
+    const TbPhase p1 = tb_phase(g, 0, LW, LH, x0, y0, false);
+    const TbPhase p2 = tb_phase(g, 1, LW, LH, x0, y0, true);
+    TbCell c1[U], c2[U];
+    bool v1[U], v2[U], f1[U], f2[U], own[U];
+    int o1[U], o2[U];
+    T u1[U], u2[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int i = (int)threadIdx.x + u * TB;
+        const TbCell none = {1, 1, 0, 0, 0, LW + 1};
+        c1[u] = none;
+        c2[u] = none;
+        v1[u] = i < p1.count;
+        f1[u] = v1[u] && tb_cell(g, i, p1, LW, x0, y0, c1[u]);
+        o1[u] = f1[u] ? open_code_xy(g, c1[u].x, c1[u].y) : 0;
+        u1[u] = o1[u] ? (T)g.u_in[c1[u].y] : (T)0;
+        own[u] = ALLOUT && v1[u] && tb_owned(g, c1[u], 1, ox, oy, x0, y0);
+        v2[u] = i < p2.count;
+        f2[u] = v2[u] && tb_cell(g, i, p2, LW, x0, y0, c2[u]);
+        o2[u] = f2[u] ? open_code_xy(g, c2[u].x, c2[u].y) : 0;
+        u2[u] = o2[u] ? (T)g.u_in[c2[u].y] : (T)0;
+    }
+
+    // plane of ring level j (zs - 1 + j); false beyond the run or a z wall
+    auto level_z = [&](int j, int& z) {
+        z = zs - 1 + j;
+        if (j < 0 || j > nzc + 1) return false;
+        if (g.per_z) {
+            z = z < 0 ? z + g.nz : (z >= g.nz ? z - g.nz : z);
+            return true;
+        }
+        return z >= 0 && z < g.nz;
+    };
+    // loads of the step-1 inputs of level j into a register set, in the
+    // storage type (converted at their use, so nothing waits for them here)
+    using R = typename BufReg<S>::type;
+    auto load1 = [&](int j, R (&h)[U][L::Q], T (&s)[U]) {
+        int z;
+        const bool ok = level_z(j, z);
+        const int zc = ok ? z : 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool live = ok && v1[u];
+            const int n = zc * nxy + c1[u].n;
+            unsigned e[L::Q];
+            pull_index<L>(g, n, c1[u].x, c1[u].y, zc, e);
+#pragma unroll
+            for (int a = 0; a < L::Q; ++a) buf_ld(rin, live ? e[a] * (unsigned)sizeof(S) : BUF_OOB, h[u][a]);
+            buf_ld(rs, live ? (unsigned)n * (unsigned)sizeof(T) : BUF_OOB, s[u]);
+        }
+    };
+    // step 1 of level j into its ring slot (a uniform branch around LDS and
+    // arithmetic only), then the intermediate state of the recompute
+    auto step1 = [&](int j, const R (&h)[U][L::Q], const T (&s)[U]) {
+        int z;
+        const bool ok = level_z(j, z);
+        T out[U][L::Q];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int a = 0; a < L::Q; ++a) out[u][a] = (T)0;
+        if (ok) {
+            const bool zf = !g.per_z && (z == 0 || z == g.nz - 1);
+            const int slot[3] = {(j + 2) % 3, j % 3, (j + 1) % 3};
+            LT* dst = ring + slot[1] * L::Q * psz;
+            T* sdst = sring + slot[1] * psz;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (!v1[u]) continue;
+                T hh[L::Q];
+#pragma unroll
+                for (int a = 0; a < L::Q; ++a) hh[a] = from_reg<T>(h[u][a]);
+                if (o1[u] && !zf) zou_he_rows<L, T>(o1[u], u1[u], d0, hh);
+                Moments<L, T> mo;
+                moments<L, T>(hh, ph, mo);
+                sdst[c1[u].cell] = s[u];
+                collide<L, T>(mo, s[u], out[u]);
+#pragma unroll
+                for (int a = 0; a < L::Q; ++a) dst[a * psz + c1[u].cell] = (LT)out[u][a];
+                if (f1[u]) tbz_ghosts<LT, T>(g, ring, psz, LW, LH, slot, c1[u], out[u]);
+            }
+        }
+        if constexpr (ALLOUT) {
+            const bool keep = ok && j >= 1 && j <= nzc;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const unsigned n = (unsigned)((ok ? z : 0) * nxy + c1[u].n);
+#pragma unroll
+                for (int a = 0; a < L::Q; ++a)
+                    buf_st(rall, keep && own[u] ? ((unsigned)a * N + n) * (unsigned)sizeof(S) : BUF_OOB,
+                           (S)out[u][a]);
+            }
+        }
+    };
+    // step 2 of level j - 1 (plane zs + j - 2) from the slots of levels
+    // j - 2, j - 1, j, then its stores
+    double v[3] = {0.0, 0.0, 0.0};
+    auto step2 = [&](int j) {
+        const int k = j - 1;
+        const bool ok = k >= 1 && k <= nzc;
+        const int z = ok ? zs + k - 1 : 0;
+        T out[U][L::Q], hp[U][L::Q];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int a = 0; a < L::Q; ++a) out[u][a] = hp[u][a] = (T)0;
+        if (ok) {
+            const bool zlo = !g.per_z && z == 0, zhi = !g.per_z && z == g.nz - 1;
+            const bool zf = zlo || zhi;
+            const int sm = (k + 2) % 3, s0 = k % 3, sp = (k + 1) % 3;
+            int off[L::Q];   // uniform source offset of each direction, relative to the cell
+#pragma unroll
+            for (int a = 0; a < L::Q; ++a) {
+                const int shift = -(L::cy[a] * LW + L::cx[a]);
+                if (L::cz[a] == 0) {
+                    off[a] = (s0 * L::Q + a) * psz + shift;
+                } else {
+                    const bool refl = L::cz[a] > 0 ? zlo : zhi;   // source beyond a z wall
+                    const int sl = L::cz[a] > 0 ? sm : sp;
+                    off[a] = refl ? (s0 * L::Q + L::opp[a]) * psz : (sl * L::Q + a) * psz + shift;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const TbCell& c = c2[u];
+                T h[L::Q];
+#pragma unroll
+                for (int a = 0; a < L::Q; ++a) h[a] = (T)ring[off[a] + c.cell];
+                if (o2[u] && !zf) zou_he_rows<L, T>(o2[u], u2[u], d0, h);
+                if (WPRE) {
+#pragma unroll
+                    for (int a = 0; a < L::Q; ++a) hp[u][a] = h[a];
+                }
+                Moments<L, T> mo;
+                moments<L, T>(h, ph, mo);
+                if (SAMPLE && v2[u]) {
+                    double vv[3];
+                    node_samples<L, T>(ob, c.x, c.y, mo, vv);
+                    v[0] += vv[0];
+                    v[1] += vv[1];
+                    v[2] += vv[2];
+                }
+                collide<L, T>(mo, sring[s0 * psz + c.cell], out[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool live = ok && v2[u];
+            const unsigned n = (unsigned)(z * nxy + c2[u].n);
+#pragma unroll
+            for (int a = 0; a < L::Q; ++a) {
+                const unsigned o = live ? ((unsigned)a * N + n) * (unsigned)sizeof(S) : BUF_OOB;
+                buf_st(rout, o, (S)out[u][a]);
+                if (WPRE) buf_st(rpre, o, (S)hp[u][a]);
+            }
+        }
+    };
+    // ring level j: step 1 of level j from its register set, the loads of
+    // level j + 2 into that set, then step 2 of level j - 1, whose levels
+    // j - 2 .. j are in the ring. Two register sets keep the loads of two
+    // levels in flight; the loop is unrolled by two so that each set has
+    // fixed registers, and starts at level -2 (no work, only the loads of
+    // levels 0 and 1) so that every pass issues the same memory operations.
+    R hA[U][L::Q], hB[U][L::Q];
+    T sA[U], sB[U];
+    auto level = [&](int j, R (&h)[U][L::Q], T (&s)[U]) {
+        step1(j, h, s);
+        load1(j + 2, h, s);
+        lds_barrier();
+        step2(j);
+        lds_barrier();
+    };
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int a = 0; a < L::Q; ++a) hA[u][a] = hB[u][a] = (R)0;
+        sA[u] = sB[u] = (T)0;
+    }
+    for (int j = -2; j <= nzc + 1; j += 2) {
+        level(j, hA, sA);
+        level(j + 1, hB, sB);
+    }
+    if (SAMPLE) {
+        block_sum_n<3, TB>(v, partials + 3 * (size_t)blockIdx.x);
+        zero_unused_partials_n<TB>(partials, part_stride);
+    }
+}
+
 // G = C(f) for a stored pre-collision state f (checkpoint restart).
 template <class L, class S, class T>
 __global__ __launch_bounds__(BLOCK) void k_collide(const S* __restrict__ pre, S* __restrict__ gout,
@@ -905,6 +1250,30 @@ static void launch_tb(const StepLaunch& a) {
     launch_tb_ps<S, T, SAMPLE, WPRE, 1024, ALLOUT, 0>(a, tiles_x, tiles_y, lds);
 }
 
+template <class S, class T, bool SAMPLE, bool WPRE, bool ALLOUT>
+static void launch_tbz(const StepLaunch& a) {
+    using LT = typename TbLds<S, T>::type;
+    const Geo& g = a.geo;
+    const int tiles_x = (g.nx + a.tile_x - 1) / a.tile_x;
+    const int tiles_y = (g.ny + a.tile_y - 1) / a.tile_y;
+    const int tiles_z = (g.nz + a.tile_z - 1) / a.tile_z;
+    const size_t lds = tbz_lds_bytes(a.tile_x, a.tile_y, sizeof(LT), sizeof(T));
+    const dim3 grid(tiles_x * tiles_y * tiles_z);
+    const int nt = tbz_threads(a.tile_x, a.tile_y), u = tbz_cells(a.tile_x, a.tile_y);
+#define LBM_TBZ(TB, U)                                                                                          \
+    hipLaunchKernelGGL((k_step_tbz<S, T, SAMPLE, WPRE, TB, U, ALLOUT>), grid, dim3(TB), lds, a.stream,          \
+                       (const S*)a.gin, (S*)a.gout, (S*)a.pre, (const T*)a.s, g, a.ph, a.ob, a.partials,        \
+                       a.part_stride, a.tile_x, a.tile_y, a.tile_z, tiles_x, tiles_y, (S*)a.allout)
+    if (nt == 256) {
+        LBM_TBZ(256, 1);
+    } else if (u == 1) {
+        LBM_TBZ(512, 1);
+    } else if constexpr (sizeof(T) == 4) {   // FP64 regions never exceed 512 cells (LDS)
+        LBM_TBZ(512, 2);
+    }
+#undef LBM_TBZ
+}
+
 template <class L, class S, class T>
 static hipError_t step_t(const StepLaunch& a) {
     const Geo& g = a.geo;
@@ -912,6 +1281,20 @@ static hipError_t step_t(const StepLaunch& a) {
     S* gout = (S*)a.gout;
     S* pre = (S*)a.pre;
     const T* sf = (const T*)a.s;
+    if (L::D == 3 && a.nsteps > 1) {
+        if (a.nsteps != 2) return hipErrorInvalidValue;
+        if (a.allout) {
+            if (a.sample || pre) return hipErrorInvalidValue;
+            launch_tbz<S, T, false, false, true>(a);
+        } else if (a.sample) {
+            if (pre) launch_tbz<S, T, true, true, false>(a);
+            else launch_tbz<S, T, true, false, false>(a);
+        } else {
+            if (pre) launch_tbz<S, T, false, true, false>(a);
+            else launch_tbz<S, T, false, false, false>(a);
+        }
+        return hipGetLastError();
+    }
     if (a.nsteps > 1) {
         if (L::D != 2) return hipErrorInvalidValue;
         if (a.allout) {
@@ -1122,6 +1505,21 @@ size_t tb_lds_bytes_prec(int nsteps, int tile_x, int tile_y, int prec) {
                      : tb_lds_bytes(nsteps, tile_x, tile_y, prec == 1 ? 4 : 2, 4);
 }
 
+size_t tbz_lds_bytes(int tile_x, int tile_y, size_t lsize, size_t vsize) {
+    // three plane slots: s values, then the Q state planes
+    const size_t psz = (size_t)(tile_x + 2) * (tile_y + 2);
+    return 3 * psz * (vsize + 19 * lsize);
+}
+
+size_t tbz_lds_bytes_prec(int tile_x, int tile_y, int prec) {
+    return prec == 0 ? tbz_lds_bytes(tile_x, tile_y, 8, 8)
+                     : tbz_lds_bytes(tile_x, tile_y, prec == 1 ? 4 : 2, 4);
+}
+
+int tbz_threads(int tile_x, int tile_y) { return (long)(tile_x + 2) * (tile_y + 2) <= 256 ? 256 : 512; }
+
+int tbz_cells(int tile_x, int tile_y) { return (long)(tile_x + 2) * (tile_y + 2) <= 512 ? 1 : 2; }
+
 long tb_blocks(int nx, int ny, int tile_x, int tile_y) {
     return (long)((nx + tile_x - 1) / tile_x) * ((ny + tile_y - 1) / tile_y);
 }
@@ -1155,9 +1553,25 @@ static hipError_t tb_attr(int b) {
     return e;
 }
 
+template <class S, class T, int NT, int U>
+static hipError_t tbz_attr(int b) {
+    const hipFuncAttribute at = hipFuncAttributeMaxDynamicSharedMemorySize;
+    hipError_t e = hipFuncSetAttribute((const void*)k_step_tbz<S, T, false, false, NT, U, false>, at, b);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tbz<S, T, true, false, NT, U, false>, at, b);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tbz<S, T, false, true, NT, U, false>, at, b);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tbz<S, T, true, true, NT, U, false>, at, b);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tbz<S, T, false, false, NT, U, true>, at, b);
+    return e;
+}
+
 template <class S, class T, class A>
 static hipError_t tb_attr_all(int b) {
-    hipError_t e = tb_attr<S, T, A, 512, 0>(b);
+    hipError_t e = tbz_attr<S, T, 256, 1>(b);
+    if (e == hipSuccess) e = tbz_attr<S, T, 512, 1>(b);
+    if constexpr (sizeof(T) == 4) {
+        if (e == hipSuccess) e = tbz_attr<S, T, 512, 2>(b);
+    }
+    if (e == hipSuccess) e = tb_attr<S, T, A, 512, 0>(b);
     if (e == hipSuccess) e = tb_attr<S, T, A, 1024, 0>(b);
     if constexpr (sizeof(S) == 2) {
         // forward kernels take the FP16 strides, the adjoint the FP32 ones

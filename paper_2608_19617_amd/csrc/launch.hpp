@@ -16,8 +16,9 @@ struct StepLaunch {
     int sample;            // write block partials of the samples of f^k (last step)
     double* partials;      // [part_stride][3]
     int part_stride;       // partial slots per sample (unused slots are zeroed)
-    int nsteps;            // 1: single step; > 1: temporally blocked launch (D2Q9)
+    int nsteps;            // 1: single step; > 1: temporally blocked launch (D2Q9; 2 for D3Q19)
     int tile_x, tile_y;    // output tile of a blocked launch
+    int tile_z;            // D3Q19: two steps on tile_x x tile_y tiles, tile_z planes per workgroup
     void* allout;          // blocked recompute: intermediate states go to allout + (t-1) * allout_slot bytes
     size_t allout_slot;
     Geo geo;
@@ -76,6 +77,9 @@ struct AuxLaunch {
 
 // LDS a blocked launch may use (of the 160 KB of a compute unit)
 constexpr size_t TB_LDS_MAX = 159 * 1024;
+// Largest state (bytes) of a blocked D3Q19 launch, which addresses it with
+// 32-bit byte offsets and keeps the offsets above this for no-op accesses.
+constexpr size_t TBZ_STATE_MAX = 0xFFFFFF00u;
 
 hipError_t launch_step(const StepLaunch& a);
 hipError_t launch_adjoint(const AdjLaunch& a);
@@ -92,6 +96,10 @@ size_t tb_lds_bytes(int nsteps, int tile_x, int tile_y, size_t lsize, size_t vsi
 size_t tb_lds_bytes_prec(int nsteps, int tile_x, int tile_y, int prec);   // forward kernel of a precision
 size_t adj_tb_lds_bytes(int nsteps, int tile_x, int tile_y, size_t vsize);
 long tb_blocks(int nx, int ny, int tile_x, int tile_y);
+size_t tbz_lds_bytes(int tile_x, int tile_y, size_t lsize, size_t vsize);
+size_t tbz_lds_bytes_prec(int tile_x, int tile_y, int prec);
+int tbz_threads(int tile_x, int tile_y);
+int tbz_cells(int tile_x, int tile_y);
 hipError_t tb_prepare(int prec);
 int tb_threads(int nsteps, int tile_x, int tile_y);
 

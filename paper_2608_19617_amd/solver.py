@@ -195,6 +195,11 @@ class Solver:
         B.check(B.lib.lbm_set_blocking(self._ctx, int(nsteps), int(tile_x), int(tile_y)))
         self.blocking = (int(nsteps), int(tile_x), int(tile_y))
 
+    def set_blocking_3d(self, nsteps, tile_x=16, tile_y=8, tile_z=8):
+        """Two-step blocking of D3Q19 forward launches (nsteps 1 or 2)."""
+        B.check(B.lib.lbm_set_blocking_3d(self._ctx, int(nsteps), int(tile_x), int(tile_y), int(tile_z)))
+        self.blocking = (int(nsteps), int(tile_x), int(tile_y), int(tile_z))
+
     def set_adjoint_blocking(self, nsteps, tile_x=32, tile_y=16):
         """Blocking of the adjoint launches over recomputed segments (D2Q9)."""
         B.check(B.lib.lbm_set_adjoint_blocking(self._ctx, int(nsteps), int(tile_x), int(tile_y)))

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared_functions():
     text = open(os.path.join(ROOT, "include", "lbm.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)
+    names = re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)
     return sorted(set(names))
 
 

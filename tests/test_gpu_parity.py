@@ -270,6 +270,78 @@ def test_small_window_d3q19_fp32(Solver):
     sv.close()
 
 
+def _small_3d_cases():
+    cases = [("periodic_z", _small_3d())]
+    w = _small_3d()
+    w.periodic = (False, False, False)        # walls on the z faces too
+    cases.append(("walls_z", w))
+    w = _small_3d()
+    w.periodic = (True, False, True)          # no open faces
+    w.west = np.zeros_like(w.west)
+    w.east = np.zeros_like(w.east)
+    cases.append(("periodic_xz", w))
+    return cases
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("case", [0, 1, 2])
+def test_blocked_d3q19_matches_single_steps(Solver, prec, case):
+    """Two-step D3Q19 launches (z-marching blocks, xy tiles grown by one node
+    in LDS, walls as ghost cells or z reflections, Zou-He faces, periodic
+    wraps; one and, below FP64, two cells per thread) give the states, window objectives
+    and adjoint of single-step launches; FP64 also against the oracle."""
+    name, w = _small_3d_cases()[case]
+    w.window_len, w.sample_every, w.ckpt_every, w.max_windows = 8, 2, 4, 2
+    prob = oracle_problem(w)
+    f0 = random_start_state(prob, seed=23 + case)
+    tol = {"f64": 1e-13, "f32": 1e-6, "f16s": 1e-3}[prec]
+    res = {}
+    blocks = (("single", (1,)), ("a", (2, 8, 8, 4)), ("b", (2, 16, 4, 4)), ("c", (2, 7, 5, 8)),
+              ("d", (2, 16, 14, 2) if prec == "f64" else (2, 24, 24, 2)), ("e", (2, 16, 16, 1)))
+    for key, blk in blocks:
+        sv = Solver(w, prec)
+        sv.set_blocking_3d(*blk) if len(blk) > 1 else sv.set_blocking_3d(1)
+        sv.set_state(f0, 0)
+        sv.forward(2 * w.window_len)
+        f, step = sv.get_state()
+        J, M, _ = sv.history()
+        g, _ = sv.adjoint()
+        assert step == 2 * w.window_len
+        res[key] = (f, J, g.cpu().numpy())
+        sv.close()
+    f1, J1, g1 = res["single"]
+    for key in ("a", "b", "c", "d", "e"):
+        f, J, g = res[key]
+        assert rel_l2(f, f1) <= tol, (key, rel_l2(f, f1))
+        assert np.max(np.abs(J - J1)) <= tol * np.max(np.abs(J1)) + 1e-15
+        assert rel_l2(g, g1) <= 100 * tol
+    if prec == "f64":
+        s_ = fw.design_map(prob, w.gamma)
+        f_o = f0
+        for _ in range(2 * w.window_len):
+            f_o = fw.step(prob, f_o, s_)
+        assert rel_l2(res["a"][0], f_o) <= 1e-12
+
+
+def test_blocking_3d_rejects_bad_blocks(Solver):
+    """Blocks below 256 nodes, xy regions above 1024 cells and blocks whose
+    ring exceeds the LDS are refused; a D2Q9 context refuses 3D blocking."""
+    from paper_2608_19617_amd.binding import LbmError
+    name, w = _small_3d_cases()[0]
+    sv = Solver(w, "f64")
+    for blk in ((2, 4, 4, 4), (2, 40, 30, 1), (2, 30, 30, 1), (3, 8, 8, 8)):
+        with pytest.raises(LbmError):
+            sv.set_blocking_3d(*blk)
+    sv.set_blocking_3d(2, 8, 8, 4)
+    sv.close()
+    w2 = W.cylinder_channel(nx=64, ny=24, radius=4, center=(16, 12), window_len=8, sample_every=2,
+                            ckpt_every=4, n_windows=1)
+    sv = Solver(w2, "f32")
+    with pytest.raises(LbmError):
+        sv.set_blocking_3d(2, 8, 8, 4)
+    sv.close()
+
+
 # ------------------------------------------------- replay, FD and autograd
 
 def test_replay_matches_forward_and_fd(Solver):
