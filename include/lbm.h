@@ -229,9 +229,10 @@ lbm_status lbm_timing(lbm_ctx* ctx, int enable, double* out);
  * turns both off. */
 lbm_status lbm_set_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y);
 
-/* Temporal blocking of D3Q19 forward (and recompute) launches: nsteps = 2
- * advances two steps per launch. A workgroup owns tile_x x tile_y nodes in
- * x and y and tile_z consecutive z planes; it takes the first step plane by
+/* Temporal blocking of D3Q19 forward launches: nsteps = 2 advances two
+ * steps per launch (the recompute of the adjoint sweep takes single
+ * steps). A workgroup owns tile_x x tile_y nodes in x and y and tile_z
+ * consecutive z planes; it takes the first step plane by
  * plane over the tile grown by one node in x and y, keeping three planes of
  * that state in LDS (walls on x and y faces as ghost cells, as for D2Q9),
  * and the second step of each plane as soon as the plane above is ready.
@@ -240,7 +241,10 @@ lbm_status lbm_set_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y);
  * (19 state values in the storage-rounded LDS type + one compute-type
  * value) within 159 KB, and a state (19 x nodes x storage bytes) below
  * 4 GB. Samples, checkpoints and window ends fall on a launch's last step as
- * in 2D. Adjoint launches stay single-step. Errors:
+ * in 2D. Adjoint launches stay single-step. Default (set by lbm_init): FP32
+ * grids of more than 2M nodes take 2 steps on 32 x 13 tiles, with the z run
+ * that lets the blocks fill the compute units in nearly whole rounds with
+ * the fewest halo planes; other D3Q19 contexts take single steps. Errors:
  * LBM_E_INVALID for a D2Q9 context or out-of-range arguments, LBM_E_HIP if
  * the LDS opt-in fails. */
 lbm_status lbm_set_blocking_3d(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y, int tile_z);

@@ -254,6 +254,16 @@ __device__ __forceinline__ void tb_tile(int tiles_x, int& tx, int& ty) {
     ty = t - tx * tiles_y;
 }
 
+// Block number of this workgroup in an order where each of the 8 XCDs
+// (workgroup b runs on XCD b mod 8) takes a contiguous range of numbers.
+__device__ __forceinline__ int xcd_block() {
+    const int T = (int)gridDim.x;
+    const int b = (int)blockIdx.x, xcd = b & 7, idx = b >> 3;
+    int start = 0;
+    for (int k = 0; k < xcd; ++k) start += (T - k + 7) >> 3;   // workgroups on XCDs before this one
+    return start + idx;
+}
+
 // True if cell c belongs to the tile's own output nodes (each node of the
 // domain is owned by exactly one tile).
 __device__ __forceinline__ bool tb_owned(const Geo& g, const TbCell& c, int H, int ox, int oy, int x0, int y0) {
@@ -624,18 +634,21 @@ __device__ __forceinline__ void buf_st(BufRsrc r, unsigned off, _Float16 v) {
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)buf_off(off), 0, 0);
 }
 
-template <class S, class T, bool SAMPLE, bool WPRE, int TB, int U, bool ALLOUT>
+template <class S, class T, bool SAMPLE, bool WPRE, int TB, int U>
 __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* __restrict__ gout,
                                                  S* __restrict__ pre, const T* __restrict__ sfield, Geo g, Phys ph,
                                                  Obj ob, double* __restrict__ partials, int part_stride, int ox,
-                                                 int oy, int oz, int tiles_x, int tiles_y, S* __restrict__ allout) {
+                                                 int oy, int oz, int tiles_x, int tiles_y) {
     using L = D3Q19;
     using LT = typename TbLds<S, T>::type;
     extern __shared__ unsigned char lds_raw[];
     const int LW = ox + 2, LH = oy + 2, psz = LW * LH;
     T* sring = reinterpret_cast<T*>(lds_raw);
     LT* ring = reinterpret_cast<LT*>(sring + 3 * psz);
-    const int b = (int)blockIdx.x;
+    // blocks are numbered x fastest, then y, then z run; each XCD takes a
+    // contiguous range of those numbers (workgroup b runs on XCD b mod 8), so
+    // the tiles that share halo rows and cache lines mostly share an L2
+    const int b = xcd_block();
     const int tx = b % tiles_x, ty = (b / tiles_x) % tiles_y, tz = b / (tiles_x * tiles_y);
     const int x0 = tx * ox - 1, y0 = ty * oy - 1;       // global x, y of LDS cell (0, 0)
     const int zs = tz * oz, nzc = min(oz, g.nz - zs);   // output planes zs .. zs + nzc - 1
@@ -646,7 +659,6 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
     const BufRsrc rs = buf_rsrc(sfield, (size_t)N * sizeof(T));
     const BufRsrc rout = buf_rsrc(gout, state_bytes);
     const BufRsrc rpre = buf_rsrc(WPRE ? pre : gout, state_bytes);
-    const BufRsrc rall = buf_rsrc(ALLOUT ? allout : gout, state_bytes);
 
     // this thread's cells of a plane, the same on every plane: up to U of
     // the step-1 region and U of the output tile; a lane without a cell
@@ -654,7 +666,7 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
     const TbPhase p1 = tb_phase(g, 0, LW, LH, x0, y0, false);
     const TbPhase p2 = tb_phase(g, 1, LW, LH, x0, y0, true);
     TbCell c1[U], c2[U];
-    bool v1[U], v2[U], f1[U], f2[U], own[U];
+    bool v1[U], v2[U], f1[U], f2[U];
     int o1[U], o2[U];
     T u1[U], u2[U];
 #pragma unroll
@@ -667,7 +679,6 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
         f1[u] = v1[u] && tb_cell(g, i, p1, LW, x0, y0, c1[u]);
         o1[u] = f1[u] ? open_code_xy(g, c1[u].x, c1[u].y) : 0;
         u1[u] = o1[u] ? (T)g.u_in[c1[u].y] : (T)0;
-        own[u] = ALLOUT && v1[u] && tb_owned(g, c1[u], 1, ox, oy, x0, y0);
         v2[u] = i < p2.count;
         f2[u] = v2[u] && tb_cell(g, i, p2, LW, x0, y0, c2[u]);
         o2[u] = f2[u] ? open_code_xy(g, c2[u].x, c2[u].y) : 0;
@@ -703,15 +714,10 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
         }
     };
     // step 1 of level j into its ring slot (a uniform branch around LDS and
-    // arithmetic only), then the intermediate state of the recompute
+    // arithmetic only)
     auto step1 = [&](int j, const R (&h)[U][L::Q], const T (&s)[U]) {
         int z;
         const bool ok = level_z(j, z);
-        T out[U][L::Q];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int a = 0; a < L::Q; ++a) out[u][a] = (T)0;
         if (ok) {
             const bool zf = !g.per_z && (z == 0 || z == g.nz - 1);
             const int slot[3] = {(j + 2) % 3, j % 3, (j + 1) % 3};
@@ -727,21 +733,11 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
                 Moments<L, T> mo;
                 moments<L, T>(hh, ph, mo);
                 sdst[c1[u].cell] = s[u];
-                collide<L, T>(mo, s[u], out[u]);
+                T out[L::Q];
+                collide<L, T>(mo, s[u], out);
 #pragma unroll
-                for (int a = 0; a < L::Q; ++a) dst[a * psz + c1[u].cell] = (LT)out[u][a];
-                if (f1[u]) tbz_ghosts<LT, T>(g, ring, psz, LW, LH, slot, c1[u], out[u]);
-            }
-        }
-        if constexpr (ALLOUT) {
-            const bool keep = ok && j >= 1 && j <= nzc;
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const unsigned n = (unsigned)((ok ? z : 0) * nxy + c1[u].n);
-#pragma unroll
-                for (int a = 0; a < L::Q; ++a)
-                    buf_st(rall, keep && own[u] ? ((unsigned)a * N + n) * (unsigned)sizeof(S) : BUF_OOB,
-                           (S)out[u][a]);
+                for (int a = 0; a < L::Q; ++a) dst[a * psz + c1[u].cell] = (LT)out[a];
+                if (f1[u]) tbz_ghosts<LT, T>(g, ring, psz, LW, LH, slot, c1[u], out);
             }
         }
     };
@@ -1250,7 +1246,7 @@ static void launch_tb(const StepLaunch& a) {
     launch_tb_ps<S, T, SAMPLE, WPRE, 1024, ALLOUT, 0>(a, tiles_x, tiles_y, lds);
 }
 
-template <class S, class T, bool SAMPLE, bool WPRE, bool ALLOUT>
+template <class S, class T, bool SAMPLE, bool WPRE>
 static void launch_tbz(const StepLaunch& a) {
     using LT = typename TbLds<S, T>::type;
     const Geo& g = a.geo;
@@ -1261,9 +1257,9 @@ static void launch_tbz(const StepLaunch& a) {
     const dim3 grid(tiles_x * tiles_y * tiles_z);
     const int nt = tbz_threads(a.tile_x, a.tile_y), u = tbz_cells(a.tile_x, a.tile_y);
 #define LBM_TBZ(TB, U)                                                                                          \
-    hipLaunchKernelGGL((k_step_tbz<S, T, SAMPLE, WPRE, TB, U, ALLOUT>), grid, dim3(TB), lds, a.stream,          \
+    hipLaunchKernelGGL((k_step_tbz<S, T, SAMPLE, WPRE, TB, U>), grid, dim3(TB), lds, a.stream,                  \
                        (const S*)a.gin, (S*)a.gout, (S*)a.pre, (const T*)a.s, g, a.ph, a.ob, a.partials,        \
-                       a.part_stride, a.tile_x, a.tile_y, a.tile_z, tiles_x, tiles_y, (S*)a.allout)
+                       a.part_stride, a.tile_x, a.tile_y, a.tile_z, tiles_x, tiles_y)
     if (nt == 256) {
         LBM_TBZ(256, 1);
     } else if (u == 1) {
@@ -1282,16 +1278,13 @@ static hipError_t step_t(const StepLaunch& a) {
     S* pre = (S*)a.pre;
     const T* sf = (const T*)a.s;
     if (L::D == 3 && a.nsteps > 1) {
-        if (a.nsteps != 2) return hipErrorInvalidValue;
-        if (a.allout) {
-            if (a.sample || pre) return hipErrorInvalidValue;
-            launch_tbz<S, T, false, false, true>(a);
-        } else if (a.sample) {
-            if (pre) launch_tbz<S, T, true, true, false>(a);
-            else launch_tbz<S, T, true, false, false>(a);
+        if (a.nsteps != 2 || a.allout) return hipErrorInvalidValue;
+        if (a.sample) {
+            if (pre) launch_tbz<S, T, true, true>(a);
+            else launch_tbz<S, T, true, false>(a);
         } else {
-            if (pre) launch_tbz<S, T, false, true, false>(a);
-            else launch_tbz<S, T, false, false, false>(a);
+            if (pre) launch_tbz<S, T, false, true>(a);
+            else launch_tbz<S, T, false, false>(a);
         }
         return hipGetLastError();
     }
@@ -1556,11 +1549,10 @@ static hipError_t tb_attr(int b) {
 template <class S, class T, int NT, int U>
 static hipError_t tbz_attr(int b) {
     const hipFuncAttribute at = hipFuncAttributeMaxDynamicSharedMemorySize;
-    hipError_t e = hipFuncSetAttribute((const void*)k_step_tbz<S, T, false, false, NT, U, false>, at, b);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tbz<S, T, true, false, NT, U, false>, at, b);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tbz<S, T, false, true, NT, U, false>, at, b);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tbz<S, T, true, true, NT, U, false>, at, b);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tbz<S, T, false, false, NT, U, true>, at, b);
+    hipError_t e = hipFuncSetAttribute((const void*)k_step_tbz<S, T, false, false, NT, U>, at, b);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tbz<S, T, true, false, NT, U>, at, b);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tbz<S, T, false, true, NT, U>, at, b);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tbz<S, T, true, true, NT, U>, at, b);
     return e;
 }
 
