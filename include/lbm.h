@@ -260,6 +260,22 @@ lbm_status lbm_set_blocking_3d(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y,
  * out-of-range arguments, LBM_E_HIP if the LDS opt-in fails. */
 lbm_status lbm_set_adjoint_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y);
 
+/* Blocking of the D3Q19 adjoint launches that pull their pre-states from a
+ * recomputed segment: nsteps = 2 takes two reverse steps per launch. A
+ * workgroup owns tile_x x tile_y nodes in x and y and tile_z consecutive z
+ * planes; the first step runs plane by plane over the tile grown by one
+ * node in x and y, keeping three planes of adjoint populations in LDS
+ * (walls on x and y faces as ghost cells, 0 behind open faces), and the
+ * second gathers from them; each step pulls its own pre-state from the
+ * segment, and the tile's sensitivity takes one FP64 read-modify-write per
+ * launch. nsteps = 1 turns it off. Requires at least 256 nodes per block,
+ * (tile_x + 2) * (tile_y + 2) <= 512 (256 for LBM_F64), 3 (tile_x + 2) x
+ * (tile_y + 2) x (8 + one compute-type value + 19 adjoint values) bytes
+ * within 159 KB, and the state and the adjoint populations below 4 GB
+ * each. Errors: LBM_E_INVALID for a D2Q9 context or out-of-range
+ * arguments, LBM_E_HIP if the LDS opt-in fails. */
+lbm_status lbm_set_adjoint_blocking_3d(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y, int tile_z);
+
 /* Thread-local message of the last failing call on this thread. */
 const char* lbm_last_error(void);
 

@@ -21,9 +21,8 @@ STATUS_NAMES = {0: "LBM_OK", 1: "LBM_E_INVALID", 2: "LBM_E_NOMEM", 3: "LBM_E_HIP
 
 EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_set_gamma", "lbm_reset", "lbm_forward",
             "lbm_window_history", "lbm_adjoint", "lbm_window_replay", "lbm_get_state",
-            "lbm_set_state", "lbm_get_fields", "lbm_timing", "lbm_set_blocking", "lbm_set_blocking_3d", "lbm_set_adjoint_blocking",
-            "lbm_last_error",
-            "lbm_destroy"]
+            "lbm_set_state", "lbm_get_fields", "lbm_timing", "lbm_set_blocking", "lbm_set_blocking_3d",
+            "lbm_set_adjoint_blocking", "lbm_set_adjoint_blocking_3d", "lbm_last_error", "lbm_destroy"]
 
 
 class lbm_config(ctypes.Structure):
@@ -82,6 +81,7 @@ def _load():
     lib.lbm_set_blocking.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.lbm_set_adjoint_blocking.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.lbm_set_blocking_3d.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.lbm_set_adjoint_blocking_3d.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.lbm_last_error.argtypes = []
     lib.lbm_last_error.restype = ctypes.c_char_p
     lib.lbm_destroy.argtypes = [P]

@@ -171,6 +171,7 @@ struct lbm_ctx {
     int tb_steps, tile_x, tile_y;    // temporal blocking of forward launches (1 = off)
     int tile_z;                      // D3Q19 tiles are tile_x x tile_y x tile_z
     int adj_steps, adj_tile_x, adj_tile_y;   // blocked adjoint launches (adj_steps 1 = off)
+    int adj_tile_z;                          // D3Q19: z planes per workgroup
     Timer tm;
 };
 
@@ -442,7 +443,28 @@ lbm_status set_blocking_3d(lbm_ctx* c, int nsteps, int tile_x, int tile_y, int t
         c->tile_z = tile_z;
     }
     c->tb_steps = nsteps;
-    c->adj_steps = 1;
+    return LBM_OK;
+}
+
+lbm_status set_adj_blocking_3d(lbm_ctx* c, int nsteps, int tile_x, int tile_y, int tile_z) {
+    if (c->cfg.lattice != LBM_D3Q19) return fail(LBM_E_INVALID, "3D blocking needs the D3Q19 lattice");
+    if (nsteps != 1 && nsteps != 2) return fail(LBM_E_INVALID, "D3Q19 adjoint blocking takes 1 or 2 steps");
+    if (nsteps == 2) {
+        if (tile_x < 1 || tile_y < 1 || tile_z < 1 || (long)tile_x * tile_y * tile_z < 256)
+            return fail(LBM_E_INVALID, "tile must hold at least 256 nodes");
+        const long cells_max = c->L.as == 8 ? 256 : 512;   // one cell per thread; FP64 uses 256 threads
+        if ((long)(tile_x + 2) * (tile_y + 2) > cells_max)
+            return fail(LBM_E_INVALID, "(tile_x + 2) * (tile_y + 2) too large (512, FP64 256)");
+        if (adj_tbz_lds_bytes(tile_x, tile_y, c->L.as, c->L.cs) > TB_LDS_MAX)
+            return fail(LBM_E_INVALID, "tile needs more than 159 KB of LDS");
+        if ((size_t)c->L.Q * c->L.N * c->L.ss > TBZ_STATE_MAX || (size_t)c->L.Q * c->L.N * c->L.as > TBZ_STATE_MAX)
+            return fail(LBM_E_INVALID, "state too large for D3Q19 blocking (limit 4 GB)");
+        HIPCHK(tb_prepare(c->cfg.prec));
+        c->adj_tile_x = tile_x;
+        c->adj_tile_y = tile_y;
+        c->adj_tile_z = tile_z;
+    }
+    c->adj_steps = nsteps;
     return LBM_OK;
 }
 
@@ -510,6 +532,11 @@ lbm_status lbm_set_blocking_3d(lbm_ctx* c, int nsteps, int tile_x, int tile_y, i
 lbm_status lbm_set_adjoint_blocking(lbm_ctx* c, int nsteps, int tile_x, int tile_y) {
     if (!c) return fail(LBM_E_INVALID, "NULL context");
     return set_adj_blocking(c, nsteps, tile_x, tile_y);
+}
+
+lbm_status lbm_set_adjoint_blocking_3d(lbm_ctx* c, int nsteps, int tile_x, int tile_y, int tile_z) {
+    if (!c) return fail(LBM_E_INVALID, "NULL context");
+    return set_adj_blocking_3d(c, nsteps, tile_x, tile_y, tile_z);
 }
 
 
@@ -607,6 +634,7 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
     c->adj_steps = 1;
     c->adj_tile_x = 32;
     c->adj_tile_y = 16;
+    c->adj_tile_z = 8;
     c->tile_x = 32;
     c->tile_y = 16;
     c->tile_z = 8;
@@ -812,6 +840,7 @@ lbm_status lbm_adjoint(lbm_ctx* c, int window, double* dJdgamma_dev, double* J_o
     aa.nsteps = 1;
     aa.tile_x = c->adj_tile_x;
     aa.tile_y = c->adj_tile_y;
+    aa.tile_z = c->adj_tile_z;
     aa.gseg = c->seg[0];
     aa.slot = L.SB;
     aa.ns = ns;

@@ -544,11 +544,13 @@ __device__ __forceinline__ int open_code_xy(const Geo& g, int x, int y) {
     return 0;
 }
 
-// Ghost-cell stores of a D3Q19 node on non-periodic x or y faces: each
-// direction b leaving across such a face stores v[b] at cell + c_b (in x, y)
-// in plane opp(b) of the slot of the plane the direction reaches (slot[0]
-// for c_bz = -1, slot[1] for 0, slot[2] for +1; slots are Q * psz apart).
-template <class LT, class T>
+// Ghost-cell stores of a D3Q19 node on non-periodic x or y faces. Forward
+// (SGN = +1): each direction b leaving across such a face stores v[b] at
+// cell + c_b (in x, y) in plane opp(b) of the slot of the plane the
+// direction reaches (slot[c_bz + 1]). Adjoint (SGN = -1): each direction b
+// whose -c_b leaves stores v[b] at cell - c_b in plane opp(b) of
+// slot[1 - c_bz]. Slots are Q * psz apart.
+template <class LT, class T, int SGN>
 __device__ __forceinline__ void tbz_ghosts(const Geo& g, LT* __restrict__ ring, int psz, int LW, int LH,
                                            const int slot[3], const TbCell& c, const T v[19]) {
     using L = D3Q19;
@@ -558,9 +560,9 @@ __device__ __forceinline__ void tbz_ghosts(const Geo& g, LT* __restrict__ ring, 
     const bool fy0 = !g.per_y && c.y == 0, fy1 = !g.per_y && c.y == g.ny - 1;
 #pragma unroll
     for (int b = 1; b < L::Q; ++b) {
-        const int sx = L::cx[b], sy = L::cy[b];
+        const int sx = SGN * L::cx[b], sy = SGN * L::cy[b];
         const bool leaves = (sx < 0 && fx0) || (sx > 0 && fx1) || (sy < 0 && fy0) || (sy > 0 && fy1);
-        if (leaves) ring[(slot[L::cz[b] + 1] * L::Q + L::opp[b]) * psz + c.cell + sy * LW + sx] = (LT)v[b];
+        if (leaves) ring[(slot[SGN * L::cz[b] + 1] * L::Q + L::opp[b]) * psz + c.cell + sy * LW + sx] = (LT)v[b];
     }
 }
 
@@ -737,7 +739,7 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
                 collide<L, T>(mo, s[u], out);
 #pragma unroll
                 for (int a = 0; a < L::Q; ++a) dst[a * psz + c1[u].cell] = (LT)out[a];
-                if (f1[u]) tbz_ghosts<LT, T>(g, ring, psz, LW, LH, slot, c1[u], out);
+                if (f1[u]) tbz_ghosts<LT, T, 1>(g, ring, psz, LW, LH, slot, c1[u], out);
             }
         }
     };
@@ -1137,6 +1139,261 @@ __global__ __launch_bounds__(TB) void k_adjoint_tb(const A* __restrict__ nu_in, 
     }
 }
 
+// Source of every kappa_a of the adjoint streaming into node (x, y, z), as
+// element indices into nu_hat that include the plane: kappa_a(y) =
+// nu_hat_a(y + c_a), periodic wraps; where y + c_a leaves through a wall,
+// nu_hat_opp(a)(y); where it leaves through an open face (open node), no
+// source: GATHER_ZERO, read as 0.
+constexpr unsigned GATHER_ZERO = 0xFFFFFFFFu;
+
+template <class L>
+__device__ __forceinline__ void gather_index(const Geo& g, int n, int x, int y, int z, bool open,
+                                             unsigned e[L::Q]) {
+    const int N = g.N;
+    const bool interior = x > 0 && x < g.nx - 1 && y > 0 && y < g.ny - 1 &&
+                          (L::D == 2 || (z > 0 && z < g.nz - 1));
+    if (interior) {
+#pragma unroll
+        for (int a = 0; a < L::Q; ++a) {
+            const int off = L::cx[a] + L::cy[a] * g.nx + L::cz[a] * g.nx * g.ny;
+            e[a] = (unsigned)(a * N + off) + (unsigned)n;
+        }
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) {
+        int xt = x + L::cx[a], yt = y + L::cy[a], zt = z + L::cz[a];
+        bool out = false;
+        if (xt < 0 || xt >= g.nx) {
+            if (g.per_x) xt = xt < 0 ? xt + g.nx : xt - g.nx;
+            else out = true;
+        }
+        if (yt < 0 || yt >= g.ny) {
+            if (g.per_y) yt = yt < 0 ? yt + g.ny : yt - g.ny;
+            else out = true;
+        }
+        if (L::D == 3 && (zt < 0 || zt >= g.nz)) {
+            if (g.per_z) zt = zt < 0 ? zt + g.nz : zt - g.nz;
+            else out = true;
+        }
+        e[a] = !out ? (unsigned)(a * N + (zt * g.ny + yt) * g.nx + xt)
+                    : (open ? GATHER_ZERO : (unsigned)(L::opp[a] * N + n));
+    }
+}
+
+// Two adjoint steps per launch for D3Q19 over a recomputed segment,
+// marching along z (the mirror of k_step_tbz): transitions k_hi and
+// k_hi - 1. Step 1 takes nu_hat^{k_hi} from global memory to
+// nu_hat^{k_hi - 1} plane by plane over the xy tile grown by one node,
+// into a three-slot LDS ring; step 2 of plane z gathers its kappa from the
+// ring (planes z - 1, z, z + 1) and writes nu_hat^{k_hi - 2} for the tile.
+// Each step pulls its own pre-state f^{k-1} from G^{k-2} in the segment.
+// Walls on x and y faces are ghost cells written by step 1 (nu_hat_b, or 0
+// on an open node, at y - c_b in plane opp(b) of the slot of plane
+// z - c_bz); a wall on a z face is taken in the step-2 gather itself
+// (kappa_a = nu_hat_opp(a) of the node, uniform over the workgroup). The
+// step-1 sensitivity of the tile's nodes waits in an FP64 ring and is added
+// after it, with step 2's, in one read-modify-write per node. As in
+// k_step_tbz every global access is a raw buffer access issued on every
+// plane (out-of-range offsets for no-ops), and the loads of the next plane
+// are in flight while the current one computes.
+//
+// LDS: three slots each of the sensitivity (FP64), s (compute type) and the
+// Q adjoint planes of (ox + 2) x (oy + 2) values. TB threads (256 for planes
+// of up to 256 region cells and for FP64, else 512) take one cell each of a
+// plane.
+template <class S, class T, class A, int TB>
+__global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in, A* __restrict__ nu_out,
+                                                    const S* __restrict__ gseg, size_t slot, long kseg,
+                                                    const T* __restrict__ sfield, double* __restrict__ sens, Geo g,
+                                                    Phys ph, Obj ob, long k_hi, long ns, long dW, double wgt, int ox,
+                                                    int oy, int oz, int tiles_x, int tiles_y) {
+    using L = D3Q19;
+    using R = typename BufReg<S>::type;
+    extern __shared__ unsigned char lds_raw[];
+    const int LW = ox + 2, LH = oy + 2, psz = LW * LH;
+    double* dsring = reinterpret_cast<double*>(lds_raw);
+    T* sring = reinterpret_cast<T*>(dsring + 3 * psz);
+    A* ring = reinterpret_cast<A*>(sring + 3 * psz);
+    const int b = xcd_block();
+    const int tx = b % tiles_x, ty = (b / tiles_x) % tiles_y, tz = b / (tiles_x * tiles_y);
+    const int x0 = tx * ox - 1, y0 = ty * oy - 1;
+    const int zs = tz * oz, nzc = min(oz, g.nz - zs);
+    const int N = g.N, nxy = g.nx * g.ny;
+    const T d0 = (T)g.drho_out;
+    const size_t sbytes = (size_t)L::Q * N * sizeof(S), abytes = (size_t)L::Q * N * sizeof(A);
+    const BufRsrc rG1 = buf_rsrc(gseg + (size_t)(k_hi - 2 - kseg) * slot, sbytes);   // G^{k_hi - 2}
+    const BufRsrc rG2 = buf_rsrc(gseg + (size_t)(k_hi - 3 - kseg) * slot, sbytes);   // G^{k_hi - 3}
+    const BufRsrc rnu = buf_rsrc(nu_in, abytes);
+    const BufRsrc rout = buf_rsrc(nu_out, abytes);
+    const BufRsrc rs = buf_rsrc(sfield, (size_t)N * sizeof(T));
+    const BufRsrc rsens = buf_rsrc(sens, (size_t)N * sizeof(double));
+    const double w1 = (k_hi > ns && (k_hi - ns) % dW == 0) ? wgt : 0.0;
+    const double w2 = (k_hi - 1 > ns && (k_hi - 1 - ns) % dW == 0) ? wgt : 0.0;
+
+    // this thread's cell of the region (step 1) and of the tile (step 2)
+    const TbPhase p1 = tb_phase(g, 0, LW, LH, x0, y0, false);
+    const TbPhase p2 = tb_phase(g, 1, LW, LH, x0, y0, true);
+    const TbCell none = {1, 1, 0, 0, 0, LW + 1};
+    TbCell c1 = none, c2 = none;
+    const int i = (int)threadIdx.x;
+    const bool v1 = i < p1.count, v2 = i < p2.count;
+    const bool f1 = v1 && tb_cell(g, i, p1, LW, x0, y0, c1);
+    const bool f2 = v2 && tb_cell(g, i, p2, LW, x0, y0, c2);
+    const int o1 = f1 ? open_code_xy(g, c1.x, c1.y) : 0;
+    const int o2 = f2 ? open_code_xy(g, c2.x, c2.y) : 0;
+    const T u1 = o1 ? (T)g.u_in[c1.y] : (T)0;
+    const T u2 = o2 ? (T)g.u_in[c2.y] : (T)0;
+    const bool own1 = v1 && tb_owned(g, c1, 1, ox, oy, x0, y0);
+
+    auto level_z = [&](int j, int& z) {
+        z = zs - 1 + j;
+        if (j < 0 || j > nzc + 1) return false;
+        if (g.per_z) {
+            z = z < 0 ? z + g.nz : (z >= g.nz ? z - g.nz : z);
+            return true;
+        }
+        return z >= 0 && z < g.nz;
+    };
+    // step-1 inputs of level j: pre-state, nu_hat gather, s
+    R hp1[L::Q];
+    A nk[L::Q];
+    T s1 = (T)0;
+    auto load1 = [&](int j) {
+        int z;
+        const bool ok = level_z(j, z);
+        const int zc = ok ? z : 0;
+        const bool live = ok && v1;
+        const int n = zc * nxy + c1.n;
+        const bool zf = !g.per_z && (zc == 0 || zc == g.nz - 1);
+        unsigned e[L::Q];
+        pull_index<L>(g, n, c1.x, c1.y, zc, e);
+#pragma unroll
+        for (int a = 0; a < L::Q; ++a) buf_ld(rG1, live ? e[a] * (unsigned)sizeof(S) : BUF_OOB, hp1[a]);
+        gather_index<L>(g, n, c1.x, c1.y, zc, o1 != 0 && !zf, e);
+#pragma unroll
+        for (int a = 0; a < L::Q; ++a)
+            buf_ld(rnu, live && e[a] != GATHER_ZERO ? e[a] * (unsigned)sizeof(A) : BUF_OOB, nk[a]);
+        buf_ld(rs, live ? (unsigned)n * (unsigned)sizeof(T) : BUF_OOB, s1);
+    };
+    // step-2 inputs of level k: pre-state and the old sensitivity
+    R hp2[L::Q];
+    double sold = 0.0;
+    auto load2 = [&](int k) {
+        const bool ok = k >= 1 && k <= nzc;
+        const int z = ok ? zs + k - 1 : 0;
+        const bool live = ok && v2;
+        const int n = z * nxy + c2.n;
+        unsigned e[L::Q];
+        pull_index<L>(g, n, c2.x, c2.y, z, e);
+#pragma unroll
+        for (int a = 0; a < L::Q; ++a) buf_ld(rG2, live ? e[a] * (unsigned)sizeof(S) : BUF_OOB, hp2[a]);
+        buf_ld(rsens, live ? (unsigned)n * 8u : BUF_OOB, sold);
+    };
+    // one adjoint node update: pre-state h (post-boundary), kappa -> mu, ds
+    auto update = [&](T (&h)[L::Q], const T (&kap)[L::Q], T s, int oc, T u0, int x, int y, double w, T (&mu)[L::Q]) {
+        Moments<L, T> m;
+        moments<L, T>(h, ph, m);
+        MomentGrad<L, T> gr;
+        gr.gr = 0;
+#pragma unroll
+        for (int p = 0; p < L::D; ++p) gr.gj[p] = 0;
+#pragma unroll
+        for (int q = 0; q < Sym<L::D>::K; ++q) gr.GP[q] = 0;
+        const T ds = collide_adjoint<L, T>(m, ph, s, kap, gr);
+        if (w != 0.0) adjoint_source<L, T>(ob, ph, x, y, m, w, gr);
+        expand<L, T>(m, gr, mu);
+        if (oc) zou_he_adjoint_rows<L, T>(oc, u0, mu);
+        return ds;
+    };
+    auto step1 = [&](int j) {
+        int z;
+        if (!level_z(j, z)) return;
+        const bool zf = !g.per_z && (z == 0 || z == g.nz - 1);
+        const int oc = zf ? 0 : o1;
+        const int slots[3] = {(j + 2) % 3, j % 3, (j + 1) % 3};   // planes z - 1, z, z + 1
+        if (!v1) return;
+        T h[L::Q], kap[L::Q], mu[L::Q];
+#pragma unroll
+        for (int a = 0; a < L::Q; ++a) {
+            h[a] = from_reg<T>(hp1[a]);
+            kap[a] = (T)nk[a];
+        }
+        if (oc) zou_he_rows<L, T>(oc, u1, d0, h);
+        const T ds = update(h, kap, s1, oc, u1, c1.x, c1.y, w1, mu);
+        A* dst = ring + slots[1] * L::Q * psz;
+#pragma unroll
+        for (int a = 0; a < L::Q; ++a) dst[a * psz + c1.cell] = (A)mu[a];
+        sring[slots[1] * psz + c1.cell] = s1;
+        if (own1) dsring[slots[1] * psz + c1.cell] = (double)ds;
+        if (f1) {
+            // ghost cells of the adjoint wall rule (0 on an open node)
+            if (oc) {
+#pragma unroll
+                for (int a = 0; a < L::Q; ++a) mu[a] = (T)0;
+            }
+            tbz_ghosts<A, T, -1>(g, ring, psz, LW, LH, slots, c1, mu);
+        }
+    };
+    auto step2 = [&](int k) {
+        const bool ok = k >= 1 && k <= nzc;
+        const int z = ok ? zs + k - 1 : 0;
+        const int n = z * nxy + c2.n;
+        T mu[L::Q];
+        double snew = 0.0;
+#pragma unroll
+        for (int a = 0; a < L::Q; ++a) mu[a] = (T)0;
+        if (ok) {
+            const bool zlo = !g.per_z && z == 0, zhi = !g.per_z && z == g.nz - 1;
+            const int oc = (zlo || zhi) ? 0 : o2;
+            const int sm = (k + 2) % 3, s0 = k % 3, sp = (k + 1) % 3;
+            int off[L::Q];   // uniform gather offset of each direction, relative to the cell
+#pragma unroll
+            for (int a = 0; a < L::Q; ++a) {
+                const int shift = L::cy[a] * LW + L::cx[a];
+                if (L::cz[a] == 0) {
+                    off[a] = (s0 * L::Q + a) * psz + shift;
+                } else {
+                    const bool refl = L::cz[a] > 0 ? zhi : zlo;   // target beyond a z wall
+                    const int sl = L::cz[a] > 0 ? sp : sm;
+                    off[a] = refl ? (s0 * L::Q + L::opp[a]) * psz : (sl * L::Q + a) * psz + shift;
+                }
+            }
+            T h[L::Q], kap[L::Q];
+#pragma unroll
+            for (int a = 0; a < L::Q; ++a) {
+                h[a] = from_reg<T>(hp2[a]);
+                kap[a] = (T)ring[off[a] + c2.cell];
+            }
+            if (oc) zou_he_rows<L, T>(oc, u2, d0, h);
+            const T ds = update(h, kap, sring[s0 * psz + c2.cell], oc, u2, c2.x, c2.y, w2, mu);
+            snew = (sold + dsring[s0 * psz + c2.cell]) + (double)ds;
+        }
+        const bool live = ok && v2;
+#pragma unroll
+        for (int a = 0; a < L::Q; ++a)
+            buf_st(rout, live ? ((unsigned)a * N + (unsigned)n) * (unsigned)sizeof(A) : BUF_OOB, (A)mu[a]);
+        buf_st(rsens, live ? (unsigned)n * 8u : BUF_OOB, snew);
+    };
+    // ring level j: step 1 of level j, the step-1 loads of level j + 1, then
+    // step 2 of level j - 1 and the step-2 loads of level j. The loop starts
+    // at level -1 (only loads) so that every pass issues the same memory
+    // operations.
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) {
+        hp1[a] = hp2[a] = (R)0;
+        nk[a] = (A)0;
+    }
+    for (int j = -1; j <= nzc + 1; ++j) {
+        step1(j);
+        load1(j + 1);
+        lds_barrier();
+        step2(j - 1);
+        load2(j);
+        lds_barrier();
+    }
+}
+
 // Per-sample sums of the block partials in a fixed order (deterministic).
 __global__ __launch_bounds__(BLOCK) void k_reduce_samples(const double* __restrict__ partials, long nblocks,
                                                           double* __restrict__ samples) {
@@ -1322,6 +1579,27 @@ static hipError_t adj_t(const AdjLaunch& a) {
     A* nout = (A*)a.nu_out;
     const S* st = (const S*)a.state;
     const T* sf = (const T*)a.s;
+    if (L::D == 3 && a.nsteps > 1) {
+        if (a.seed || a.direct || a.nsteps != 2) return hipErrorInvalidValue;
+        const int tiles_x = (g.nx + a.tile_x - 1) / a.tile_x;
+        const int tiles_y = (g.ny + a.tile_y - 1) / a.tile_y;
+        const int tiles_z = (g.nz + a.tile_z - 1) / a.tile_z;
+        const size_t lds = adj_tbz_lds_bytes(a.tile_x, a.tile_y, sizeof(A), sizeof(T));
+        const dim3 grid(tiles_x * tiles_y * tiles_z);
+        const S* gs = (const S*)a.gseg;
+        const size_t slot = a.slot / sizeof(S);
+#define LBM_ADJ_TBZ(TBV)                                                                                      \
+    hipLaunchKernelGGL((k_adjoint_tbz<S, T, A, TBV>), grid, dim3(TBV), lds, a.stream, nin, nout, gs, slot,      \
+                       a.kseg, sf, a.sens, g, a.ph, a.ob, a.k_hi, a.ns, a.dW, a.wgt, a.tile_x, a.tile_y,        \
+                       a.tile_z, tiles_x, tiles_y)
+        if (sizeof(A) == 8 || tbz_threads(a.tile_x, a.tile_y) == 256) {
+            LBM_ADJ_TBZ(256);   // FP64: one cell per thread of 256 (register budget)
+        } else if constexpr (sizeof(A) == 4) {
+            LBM_ADJ_TBZ(512);
+        }
+#undef LBM_ADJ_TBZ
+        return hipGetLastError();
+    }
     if (L::D == 2 && a.nsteps > 1) {
         if (a.seed || a.direct) return hipErrorInvalidValue;
         const int tiles_x = (g.nx + a.tile_x - 1) / a.tile_x;
@@ -1511,6 +1789,12 @@ size_t tbz_lds_bytes_prec(int tile_x, int tile_y, int prec) {
 
 int tbz_threads(int tile_x, int tile_y) { return (long)(tile_x + 2) * (tile_y + 2) <= 256 ? 256 : 512; }
 
+size_t adj_tbz_lds_bytes(int tile_x, int tile_y, size_t asize, size_t tsize) {
+    // three plane slots: FP64 sensitivity, s, then the Q adjoint planes
+    const size_t psz = (size_t)(tile_x + 2) * (tile_y + 2);
+    return 3 * psz * (8 + tsize + 19 * asize);
+}
+
 int tbz_cells(int tile_x, int tile_y) { return (long)(tile_x + 2) * (tile_y + 2) <= 512 ? 1 : 2; }
 
 long tb_blocks(int nx, int ny, int tile_x, int tile_y) {
@@ -1558,7 +1842,14 @@ static hipError_t tbz_attr(int b) {
 
 template <class S, class T, class A>
 static hipError_t tb_attr_all(int b) {
-    hipError_t e = tbz_attr<S, T, 256, 1>(b);
+    hipError_t e = hipFuncSetAttribute((const void*)k_adjoint_tbz<S, T, A, 256>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if constexpr (sizeof(A) == 4) {
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_adjoint_tbz<S, T, A, 512>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    }
+    if (e == hipSuccess) e = tbz_attr<S, T, 256, 1>(b);
     if (e == hipSuccess) e = tbz_attr<S, T, 512, 1>(b);
     if constexpr (sizeof(T) == 4) {
         if (e == hipSuccess) e = tbz_attr<S, T, 512, 2>(b);

@@ -36,9 +36,10 @@ struct AdjLaunch {
     double* sens;
     int direct, seed;
     double src_w;          // weight of the objective source on f^{k-1} (0: none)
-    // blocked launch (nsteps > 1, D2Q9): steps k_hi .. k_hi - nsteps + 1, all
+    // blocked launch (nsteps > 1; D3Q19: 2): steps k_hi .. k_hi - nsteps + 1, all
     // pulling their pre-state from G^{k-2} = gseg + (k - 2 - kseg) * slot bytes
     int nsteps, tile_x, tile_y;
+    int tile_z;            // D3Q19 (nsteps = 2): z planes per workgroup
     const void* gseg;
     size_t slot;
     long kseg, k_hi, ns, dW;
@@ -100,6 +101,7 @@ size_t tbz_lds_bytes(int tile_x, int tile_y, size_t lsize, size_t vsize);
 size_t tbz_lds_bytes_prec(int tile_x, int tile_y, int prec);
 int tbz_threads(int tile_x, int tile_y);
 int tbz_cells(int tile_x, int tile_y);
+size_t adj_tbz_lds_bytes(int tile_x, int tile_y, size_t asize, size_t tsize);
 hipError_t tb_prepare(int prec);
 int tb_threads(int nsteps, int tile_x, int tile_y);
 

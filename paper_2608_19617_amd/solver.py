@@ -200,6 +200,10 @@ class Solver:
         B.check(B.lib.lbm_set_blocking_3d(self._ctx, int(nsteps), int(tile_x), int(tile_y), int(tile_z)))
         self.blocking = (int(nsteps), int(tile_x), int(tile_y), int(tile_z))
 
+    def set_adjoint_blocking_3d(self, nsteps, tile_x=32, tile_y=13, tile_z=64):
+        """Two-step blocking of D3Q19 adjoint launches over recomputed segments."""
+        B.check(B.lib.lbm_set_adjoint_blocking_3d(self._ctx, int(nsteps), int(tile_x), int(tile_y), int(tile_z)))
+
     def set_adjoint_blocking(self, nsteps, tile_x=32, tile_y=16):
         """Blocking of the adjoint launches over recomputed segments (D2Q9)."""
         B.check(B.lib.lbm_set_adjoint_blocking(self._ctx, int(nsteps), int(tile_x), int(tile_y)))

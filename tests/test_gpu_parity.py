@@ -323,6 +323,60 @@ def test_blocked_d3q19_matches_single_steps(Solver, prec, case):
         assert rel_l2(res["a"][0], f_o) <= 1e-12
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("case", [0, 1, 2])
+def test_blocked_d3q19_adjoint_matches_single_steps(Solver, prec, case):
+    """Two-step D3Q19 adjoint launches (z-marching blocks, adjoint wall rule
+    as ghost cells or z reflections, 0 behind open faces, one
+    read-modify-write of the sensitivity per launch; 256- and 512-thread
+    blocks) give the dJ/dgamma of single-step adjoint launches after the
+    same forward launches (single and blocked)."""
+    name, w = _small_3d_cases()[case]
+    w.window_len, w.sample_every, w.ckpt_every, w.max_windows = 8, 2, 8, 2
+    prob = oracle_problem(w)
+    f0 = random_start_state(prob, seed=41 + case)
+    tol = {"f64": 1e-13, "f32": 1e-6, "f16s": 1e-5}[prec]
+    blocks = [(8, 8, 4), (7, 5, 8), (14, 14, 2) if prec == "f64" else (16, 14, 2)]
+    # each blocked adjoint against the single-step adjoint of the same forward
+    # launches (forward blocking changes the rounding below FP64)
+    runs = [((1,), (1,)), ((1,), (2,) + blocks[0]), ((2, 8, 8, 4), (1,))] + \
+           [((2, 8, 8, 4), (2,) + blk) for blk in blocks]
+    res = {}
+    for fwd, adj in runs:
+        sv = Solver(w, prec)
+        sv.set_blocking_3d(*fwd) if len(fwd) > 1 else sv.set_blocking_3d(1)
+        sv.set_adjoint_blocking_3d(*adj) if len(adj) > 1 else sv.set_adjoint_blocking_3d(1)
+        sv.set_state(f0, 0)
+        sv.forward(2 * w.window_len)
+        g, J = sv.adjoint()
+        res[(fwd, adj)] = (g.cpu().numpy(), J)
+        sv.close()
+    for (fwd, adj), (g, J) in res.items():
+        g1, J1 = res[(fwd, (1,))]
+        assert rel_l2(g, g1) <= tol, (fwd, adj, rel_l2(g, g1))
+        assert J == J1, (fwd, adj, J, J1)
+
+
+def test_adjoint_blocking_3d_rejects_bad_blocks(Solver):
+    """Adjoint blocks below 256 nodes, xy regions above 512 cells (256 in
+    FP64), three steps, and a D2Q9 context are refused."""
+    from paper_2608_19617_amd.binding import LbmError
+    name, w = _small_3d_cases()[0]
+    for prec, bad in (("f32", ((2, 4, 4, 4), (2, 30, 16, 1), (3, 8, 8, 4))), ("f64", ((2, 16, 14, 2),))):
+        sv = Solver(w, prec)
+        for blk in bad:
+            with pytest.raises(LbmError):
+                sv.set_adjoint_blocking_3d(*blk)
+        sv.set_adjoint_blocking_3d(2, 8, 8, 4)
+        sv.close()
+    w2 = W.cylinder_channel(nx=64, ny=24, radius=4, center=(16, 12), window_len=8, sample_every=2,
+                            ckpt_every=4, n_windows=1)
+    sv = Solver(w2, "f32")
+    with pytest.raises(LbmError):
+        sv.set_adjoint_blocking_3d(2, 8, 8, 4)
+    sv.close()
+
+
 def test_blocking_3d_rejects_bad_blocks(Solver):
     """Blocks below 256 nodes, xy regions above 1024 cells and blocks whose
     ring exceeds the LDS are refused; a D2Q9 context refuses 3D blocking."""
