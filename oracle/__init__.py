@@ -20,6 +20,10 @@ forward   equilibrium, moments, LES closure, regularized collision, partial
 adjoint   adjoint boundary rules, adjoint streaming, explicit per-node
           collision Jacobian, sensitivity and the reverse sweep over the
           representative window (Sec. 3.2).
+design    density filter, Heaviside projection, volume fraction, their
+          chain-rule transposes and a projected-gradient design update
+          (Sec. "Topology optimization procedure", Algorithm "Optimization
+          iteration"; the update stands in for MMA).
 
 Parity status: every function is pinned by the CPU tests under tests/
 (lattice identities, conservation, closed-form Poiseuille and Taylor-Green
@@ -28,4 +32,4 @@ paper's printed optimisation results need the outer design loop and are not
 used ("parity unpinned" for those, which this package does not compute).
 """
 
-from . import lattice, forward, adjoint  # noqa: F401
+from . import lattice, forward, adjoint, design  # noqa: F401
