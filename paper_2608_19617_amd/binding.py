@@ -22,7 +22,9 @@ STATUS_NAMES = {0: "LBM_OK", 1: "LBM_E_INVALID", 2: "LBM_E_NOMEM", 3: "LBM_E_HIP
 EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_set_gamma", "lbm_reset", "lbm_forward",
             "lbm_window_history", "lbm_adjoint", "lbm_window_replay", "lbm_get_state",
             "lbm_set_state", "lbm_get_fields", "lbm_timing", "lbm_set_blocking", "lbm_set_blocking_3d",
-            "lbm_set_adjoint_blocking", "lbm_set_adjoint_blocking_3d", "lbm_last_error", "lbm_destroy"]
+            "lbm_set_adjoint_blocking", "lbm_set_adjoint_blocking_3d", "lbm_last_error", "lbm_destroy",
+            "lbm_design_workspace_bytes", "lbm_design_init", "lbm_design_map", "lbm_design_chain",
+            "lbm_design_update", "lbm_design_destroy"]
 
 
 class lbm_config(ctypes.Structure):
@@ -86,8 +88,16 @@ def _load():
     lib.lbm_last_error.restype = ctypes.c_char_p
     lib.lbm_destroy.argtypes = [P]
     lib.lbm_destroy.restype = None
+    dbl, i = ctypes.c_double, ctypes.c_int
+    lib.lbm_design_workspace_bytes.argtypes = [i, i, i, dbl, ctypes.POINTER(ctypes.c_size_t)]
+    lib.lbm_design_init.argtypes = [i, i, i, dbl, P, P, P, ctypes.c_size_t, P, ctypes.POINTER(P)]
+    lib.lbm_design_map.argtypes = [P, P, dbl, dbl, P, D]
+    lib.lbm_design_chain.argtypes = [P, P, dbl, dbl, P, P, P]
+    lib.lbm_design_update.argtypes = [P, P, P, P, dbl, dbl, dbl, dbl, P, D, D]
+    lib.lbm_design_destroy.argtypes = [P]
+    lib.lbm_design_destroy.restype = None
     for name in EXPORTED:
-        if name not in ("lbm_last_error", "lbm_destroy"):
+        if name not in ("lbm_last_error", "lbm_destroy", "lbm_design_destroy"):
             getattr(lib, name).restype = ctypes.c_int
     return lib
 

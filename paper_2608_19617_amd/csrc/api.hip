@@ -517,6 +517,9 @@ lbm_status set_adj_blocking(lbm_ctx* c, int nsteps, int tile_x, int tile_y) {
 
 }  // namespace
 
+// Error recording shared with the design-update entry points.
+lbm_status lbm::record_error(lbm_status st, const char* msg) { return fail(st, msg); }
+
 extern "C" {
 
 lbm_status lbm_set_blocking(lbm_ctx* c, int nsteps, int tile_x, int tile_y) {

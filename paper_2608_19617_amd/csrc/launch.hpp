@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
+#include "lbm.h"
 
 namespace lbm {
 
@@ -81,6 +82,9 @@ constexpr size_t TB_LDS_MAX = 159 * 1024;
 // Largest state (bytes) of a blocked D3Q19 launch, which addresses it with
 // 32-bit byte offsets and keeps the offsets above this for no-op accesses.
 constexpr size_t TBZ_STATE_MAX = 0xFFFFFF00u;
+
+// Sets the thread-local message that lbm_last_error returns; returns st.
+lbm_status record_error(lbm_status st, const char* msg);
 
 hipError_t launch_step(const StepLaunch& a);
 hipError_t launch_adjoint(const AdjLaunch& a);

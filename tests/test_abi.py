@@ -1,5 +1,5 @@
 """C-ABI contract on the CPU: the library loads, exports every symbol that
-include/lbm.h declares, validates configurations before any HIP call, and
+include/*.h declares, validates configurations before any HIP call, and
 its workspace sizing matches the documented layout. No kernel runs here."""
 
 import ctypes
@@ -13,10 +13,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared_functions():
-    text = open(os.path.join(ROOT, "include", "lbm.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)
-    return sorted(set(names))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names.update(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -34,13 +37,14 @@ def test_exports_every_declared_symbol(B):
 
 
 def test_header_is_plain_c():
-    """The header compiles as C (no HIP, torch or C++ types)."""
+    """The headers compile as C (no HIP, torch or C++ types)."""
     import subprocess
     import tempfile
     with tempfile.TemporaryDirectory() as d:
         src = os.path.join(d, "t.c")
         with open(src, "w") as fh:
-            fh.write('#include "lbm.h"\nint main(void){lbm_config c; (void)c; return 0;}\n')
+            fh.write('#include "lbm.h"\n#include "lbm_design.h"\n'
+                     'int main(void){lbm_config c; lbm_design* d = 0; (void)c; (void)d; return 0;}\n')
         r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
                             "-c", src, "-o", os.path.join(d, "t.o")], capture_output=True, text=True)
         assert r.returncode == 0, r.stderr
@@ -129,3 +133,27 @@ def test_product_path_has_no_cpu_fallback():
             assert "oracle" not in re.sub(r'""".*?"""', "", text, flags=re.S), fn
     src = open(os.path.join(pkg, "binding.py")).read()
     assert "raise ImportError" in src
+
+
+def test_design_entry_points_validate_before_any_hip_call(B):
+    """lbm_design_* reject bad sizes, radii, NULL pointers and small
+    workspaces with LBM_E_INVALID before touching the GPU."""
+    n = ctypes.c_size_t(0)
+    assert B.lib.lbm_design_workspace_bytes(0, 8, 1, 4.0, ctypes.byref(n)) == B.LBM_E_INVALID
+    assert B.lib.lbm_design_workspace_bytes(16, 8, 1, 0.5, ctypes.byref(n)) == B.LBM_E_INVALID
+    assert B.lib.lbm_design_workspace_bytes(16, 8, 1, 5.5, ctypes.byref(n)) == B.LBM_E_INVALID
+    assert B.lib.lbm_design_workspace_bytes(16, 8, 1, 4.0, None) == B.LBM_E_INVALID
+    assert B.lib.lbm_design_workspace_bytes(16, 8, 1, 4.0, ctypes.byref(n)) == B.LBM_OK
+    small, big = n.value, ctypes.c_size_t(0)
+    assert B.lib.lbm_design_workspace_bytes(64, 32, 16, 4.0, ctypes.byref(big)) == B.LBM_OK
+    # fields (mask, base, normalisation, filtered, two scratch) grow with the grid
+    assert big.value - small >= 64 * 32 * 16 * 41 - 16 * 8 * 41
+    out = ctypes.c_void_p()
+    fake = ctypes.c_void_p(256)
+    assert B.lib.lbm_design_init(16, 8, 1, 4.0, None, fake, fake, small, None, ctypes.byref(out)) == B.LBM_E_INVALID
+    assert B.lib.lbm_design_init(16, 8, 1, 4.0, fake, fake, ctypes.c_void_p(257), small, None,
+                                 ctypes.byref(out)) == B.LBM_E_INVALID
+    assert B.lib.lbm_design_init(16, 8, 1, 4.0, fake, fake, fake, small - 1, None,
+                                 ctypes.byref(out)) == B.LBM_E_INVALID
+    assert "workspace" in B.lib.lbm_last_error().decode()
+    assert B.lib.lbm_design_map(None, fake, 2.0, 0.5, fake, None) == B.LBM_E_INVALID
