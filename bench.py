@@ -49,10 +49,11 @@ def parse():
     ap.add_argument("--counters", action="store_true",
                     help="run one window and its adjoint of the workload plus a 256 MiB device copy "
                          "(for rocprofv3 --pmc byte counters) and exit")
-    ap.add_argument("--suite", choices=["hbm"], default=None,
+    ap.add_argument("--suite", choices=["hbm", "design"], default=None,
                     help="hbm: rooflines of the forward, recompute and adjoint kernels on grids far "
                          "larger than the caches (one JSON line per configuration) instead of the "
-                         "benchmark step")
+                         "benchmark step; design: timings of the design update (filter + projection, "
+                         "chain rule, volume-constrained step)")
     return ap.parse_args()
 
 
@@ -296,6 +297,57 @@ def hbm_suite(args, torch):
         print(json.dumps(line), flush=True)
 
 
+def design_suite(args, torch):
+    """Design update (lbm_design.h) on the cylinder-wake grid 2048 x 512 and
+    the D3Q19 channel 384 x 128 x 128, every node a design node, filter
+    radius 4: per-call times of the map (filter + projection + volume), the
+    chain rule and one volume-constrained step (which maps the design about
+    70 times while it bisects the multiplier), timed with CUDA events on the
+    current stream. The stencil reads each of its n_off neighbours from LDS:
+    2 n_off flop and n_off 8-byte LDS reads per node (n_off = 45 in 2D, 257 in
+    3D); its HBM bytes per node are x, W, base, mask read and x~, gamma
+    written (41 B; the chain rule: x~, g, W, mask read, dJ/dx, dV/dx written,
+    41 B)."""
+    import numpy as np
+    from paper_2608_19617_amd.design import Design
+    for shape in ((2048, 512), (384, 128, 128)):
+        N = int(np.prod(shape))
+        rng = np.random.default_rng(0)
+        mask = np.ones(shape, dtype=bool)
+        x = torch.as_tensor(rng.random(shape), device="cuda")
+        g = torch.as_tensor(rng.standard_normal(shape), device="cuda")
+        d = Design(shape, mask, np.zeros(shape), radius=4.0)
+        n_off = 45 if len(shape) == 2 else 257
+
+        def timed(fn, reps):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) * 1e-3 / reps
+
+        t_map = timed(lambda: d.map(x, 8.0, 0.5), 20)
+        t_chain = timed(lambda: d.chain(x, 8.0, 0.5, g), 20)
+        gJ, gV = d.chain(x, 8.0, 0.5, g)
+        _, v0 = d.map(x, 8.0, 0.5)
+        t_upd = timed(lambda: d.update(x, -gV, gV, 8.0, 0.5, 0.2, v0 - 0.05), 3)
+        line = {"suite": "design", "grid": list(shape), "nodes": N, "dtype": "f64", "radius": 4.0,
+                "neighbours": n_off,
+                "map": {"us": round(t_map * 1e6, 1), "mlups": round(N / t_map / 1e6, 1),
+                        "hbm_GBs": round(41 * N / t_map / 1e9, 1),
+                        "fp64_TFLOPs": round(2 * n_off * N / t_map / 1e12, 2),
+                        "lds_TBs": round(8 * n_off * N / t_map / 1e12, 1)},
+                "chain": {"us": round(t_chain * 1e6, 1), "mlups": round(N / t_chain / 1e6, 1),
+                          "fp64_TFLOPs": round(4 * n_off * N / t_chain / 1e12, 2)},
+                "update_ms": round(t_upd * 1e3, 2)}
+        d.close()
+        print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -311,6 +363,9 @@ def main():
         return
     if args.suite == "hbm":
         hbm_suite(args, torch)
+        return
+    if args.suite == "design":
+        design_suite(args, torch)
         return
     from paper_2608_19617_amd import workloads as W
     from paper_2608_19617_amd.solver import Solver
