@@ -322,3 +322,24 @@ def window_gradient(prob, gamma, f_start):
         if m - 1 >= 1 and (m - 1) % dW == 0:
             nu = nu + wgt * objective_gradient(prob, states[m - 1])
     return J, fw.design_map_derivative(prob, gamma) * sens, nu
+
+
+def full_gradient(prob, gamma, n_windows):
+    """J of window n_windows (the last) and dJ/dgamma through the whole
+    history from f^0: the full-time adjoint that Sec. "Comparison with
+    full-time adjoint optimization" compares against. The reverse sweep of
+    the last window (with its objective sources) continues from the adjoint
+    of that window's start state through every earlier step down to the
+    first transition, with no objective source there; f^0 does not depend
+    on gamma."""
+    s = fw.design_map(prob, gamma)
+    W = prob.window_len
+    states = [fw.initial_state(prob)]
+    for _ in range((n_windows - 1) * W):
+        states.append(fw.step(prob, states[-1], s))
+    J, g_window, nu = window_gradient(prob, gamma, states[-1])
+    sens = np.zeros(prob.shape, dtype=np.result_type(states[0], s))
+    for m in range(len(states) - 1, 0, -1):
+        nu, dsens = adjoint_step(prob, states[m - 1], s, nu)
+        sens = sens + dsens
+    return J, g_window + fw.design_map_derivative(prob, gamma) * sens

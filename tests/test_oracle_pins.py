@@ -498,6 +498,35 @@ def test_window_gradient_complex_step(name, prob, gamma):
     assert np.linalg.norm(cs) > 0
 
 
+@pytest.mark.parametrize("name,prob,gamma", _window_cases()[:3], ids=lambda v: v if isinstance(v, str) else "")
+def test_full_gradient_complex_step(name, prob, gamma):
+    """Full-time adjoint (Sec. "Comparison with full-time adjoint
+    optimization"): the last window's objective with the whole history from
+    f^0 depending on gamma, differentiated by the chained reverse sweep,
+    equals its complex-step derivative on every design entry; it differs from
+    the window-restricted gradient, whose start state is held fixed."""
+    n = 3
+    J, g = ad.full_gradient(prob, gamma, n)
+
+    def start(gm):
+        s = fw.design_map(prob, gm)
+        f = fw.initial_state(prob).astype(complex if np.iscomplexobj(gm) else float)
+        for _ in range((n - 1) * prob.window_len):
+            f = fw.step(prob, f, s)
+        return f
+
+    assert J == pytest.approx(fw.window_objective(prob, gamma, start(gamma)), rel=1e-15, abs=0)
+    h = 1e-30
+    cs = np.zeros_like(g)
+    for idx in np.ndindex(*gamma.shape):
+        gc = gamma.astype(complex)
+        gc[idx] += 1j * h
+        cs[idx] = fw.window_objective(prob, gc, start(gc)).imag / h
+    assert np.linalg.norm(g - cs) <= 1e-12 * np.linalg.norm(cs)
+    _, g_win, _ = ad.window_gradient(prob, gamma, start(gamma))
+    assert np.linalg.norm(g - g_win) > 1e-6 * np.linalg.norm(g)
+
+
 @pytest.mark.parametrize("name,prob,gamma", _window_cases(), ids=lambda v: v if isinstance(v, str) else "")
 def test_step_dot_product(name, prob, gamma, rng):
     """<L df, nu> = <df, L^T nu> for one step, with L df by complex step."""
