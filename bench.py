@@ -49,11 +49,12 @@ def parse():
     ap.add_argument("--counters", action="store_true",
                     help="run one window and its adjoint of the workload plus a 256 MiB device copy "
                          "(for rocprofv3 --pmc byte counters) and exit")
-    ap.add_argument("--suite", choices=["hbm", "design"], default=None,
+    ap.add_argument("--suite", choices=["hbm", "design", "fulltime"], default=None,
                     help="hbm: rooflines of the forward, recompute and adjoint kernels on grids far "
                          "larger than the caches (one JSON line per configuration) instead of the "
                          "benchmark step; design: timings of the design update (filter + projection, "
-                         "chain rule, volume-constrained step)")
+                         "chain rule, volume-constrained step); fulltime: one optimisation iteration "
+                         "with the window adjoint against the full-time adjoint (time and storage)")
     return ap.parse_args()
 
 
@@ -348,6 +349,62 @@ def design_suite(args, torch):
         print(json.dumps(line), flush=True)
 
 
+def fulltime_suite(args, torch):
+    """The comparison of Sec. "Comparison with full-time adjoint
+    optimization" at MI355X scale: the cylinder wake 2048 x 512 (disk D = 64)
+    run for 4 windows of 5000 steps (dW = 50, K = 250), then dJ/dgamma of the
+    last window with the window-restricted adjoint and with the full-time
+    adjoint (the sweep chained back to t = 0; earlier windows replayed once
+    from their start states), at the paper's Re = 51.2 of that comparison and
+    in the LES regime (Re = 1000). Reports the time of each part, the
+    workspace of both methods, the bytes of the stored trajectory that the
+    full-time method needs without replays (every state of the run, as in the
+    paper), and the norms and cosine of the two gradients."""
+    import numpy as np
+    from paper_2608_19617_amd import workloads as W
+    from paper_2608_19617_amd.solver import Solver
+    for re in (51.2, 1000.0):
+        w = W.cylinder_wake(nx=2048, ny=512, radius=32, re=re, window_len=5000, sample_every=50,
+                            ckpt_every=250, max_windows=4, eps=-1.0)
+        w.full_history = True
+        n_win = 4
+        sv = Solver(w, args.prec)
+        sv.set_gamma(w.gamma)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sv.forward(n_win * w.window_len)
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        g_w, J = sv.adjoint()
+        torch.cuda.synchronize()
+        t_win = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        g_f, _ = sv.adjoint_full()
+        torch.cuda.synchronize()
+        t_full = time.perf_counter() - t0
+        gw, gf = g_w.cpu().numpy().ravel(), g_f.cpu().numpy().ravel()
+        ws_full = sv.workspace_bytes
+        sv.close()
+        w.full_history = False
+        sv = Solver(w, args.prec)
+        ws_win = sv.workspace_bytes
+        sv.close()
+        state_bytes = 9 * w.nodes * {"f64": 8, "f32": 4, "f16s": 2}[args.prec]
+        nw, nf = float(np.linalg.norm(gw)), float(np.linalg.norm(gf))
+        line = {"suite": "fulltime", "workload": f"cylinder wake 2048x512 Re {re}, 4 windows of 5000 steps",
+                "dtype": args.prec, "steps": n_win * w.window_len, "J": J,
+                "forward_s": round(t_fwd, 3), "window_adjoint_s": round(t_win, 3),
+                "full_time_adjoint_s": round(t_full, 3),
+                "iteration_s": {"window": round(t_fwd + t_win, 3), "full_time": round(t_fwd + t_full, 3)},
+                "workspace_GB": {"window": round(ws_win / 1e9, 3),
+                                 "full_time_two_level": round(ws_full / 1e9, 3),
+                                 "full_trajectory": round(n_win * w.window_len * state_bytes / 1e9, 1)},
+                "gradient_norm": {"window": nw, "full_time": nf},
+                "gradient_cosine": float(gw @ gf / (nw * nf)) if nw > 0 and nf > 0 else None}
+        print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -366,6 +423,9 @@ def main():
         return
     if args.suite == "design":
         design_suite(args, torch)
+        return
+    if args.suite == "fulltime":
+        fulltime_suite(args, torch)
         return
     from paper_2608_19617_amd import workloads as W
     from paper_2608_19617_amd.solver import Solver

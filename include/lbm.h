@@ -113,6 +113,8 @@ typedef struct {
     int sec_in_x, sec_in_lo, sec_in_hi;    /* inlet pressure section: x, rows [lo, hi), all z */
     int sec_out_x, sec_out_lo, sec_out_hi; /* outlet pressure section */
     int ckpt_every;              /* K: checkpoint interval, must divide window_len */
+    int full_history;            /* 1: also keep the start state of every window (for
+                                    lbm_adjoint_full); 0: the two newest windows only */
 } lbm_config;
 
 /* Result of lbm_forward. w_eff is the 1-based index of the last completed
@@ -133,7 +135,8 @@ typedef struct lbm_ctx lbm_ctx;
 
 /* Bytes of device workspace that lbm_init needs for this configuration
  * (state ping-pong, two checkpoint rings of |W|/K slots, K recompute slots,
- * adjoint buffers, sample partials). Validates the configuration. */
+ * adjoint buffers, sample partials; with full_history also max_windows
+ * window-start states and a third ring). Validates the configuration. */
 lbm_status lbm_workspace_bytes(const lbm_config* cfg, size_t* bytes);
 
 /* Creates a context. gamma_dev: device FP64 array of N design values in
@@ -168,6 +171,19 @@ lbm_status lbm_window_history(lbm_ctx* ctx, double* J, double* M, double* rel, i
  * state is not changed. Recomputes each K-step segment from its HBM
  * checkpoint. */
 lbm_status lbm_adjoint(lbm_ctx* ctx, int window, double* dJdgamma_dev, double* J_out);
+
+/* Full-time adjoint (the comparison case of Sec. "Comparison with full-time
+ * adjoint optimization"): dJ/dgamma of the same objective J (the last
+ * completed window) with the adjoint carried back through every earlier
+ * window to the start of the history (t = 0 after lbm_init, lbm_reset or
+ * lbm_set_gamma; the lbm_set_state step otherwise), so that the state
+ * entering the window is not held fixed. Needs cfg.full_history = 1: the
+ * start state of every window is kept, each earlier window is replayed from
+ * it once to rebuild its K-step checkpoints, and its reverse sweep takes no
+ * objective source. Errors: LBM_E_STATE without full history, without a
+ * completed window, or when more than max_windows windows have run since
+ * the start of the history. Writes dJ/dgamma (device FP64, N) and J. */
+lbm_status lbm_adjoint_full(lbm_ctx* ctx, double* dJdgamma_dev, double* J_out);
 
 /* Replays the last completed window from its (fixed) start state with the
  * design field gamma_dev (device FP64, N values) and returns its objective:

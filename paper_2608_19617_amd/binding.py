@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "LBM_OK", 1: "LBM_E_INVALID", 2: "LBM_E_NOMEM", 3: "LBM_E_HIP
                 4: "LBM_E_UNSTABLE", 5: "LBM_E_STATE"}
 
 EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_set_gamma", "lbm_reset", "lbm_forward",
-            "lbm_window_history", "lbm_adjoint", "lbm_window_replay", "lbm_get_state",
+            "lbm_window_history", "lbm_adjoint", "lbm_adjoint_full", "lbm_window_replay", "lbm_get_state",
             "lbm_set_state", "lbm_get_fields", "lbm_timing", "lbm_set_blocking", "lbm_set_blocking_3d",
             "lbm_set_adjoint_blocking", "lbm_set_adjoint_blocking_3d", "lbm_last_error", "lbm_destroy",
             "lbm_design_workspace_bytes", "lbm_design_init", "lbm_design_map", "lbm_design_chain",
@@ -42,6 +42,7 @@ class lbm_config(ctypes.Structure):
         ("sec_in_x", ctypes.c_int), ("sec_in_lo", ctypes.c_int), ("sec_in_hi", ctypes.c_int),
         ("sec_out_x", ctypes.c_int), ("sec_out_lo", ctypes.c_int), ("sec_out_hi", ctypes.c_int),
         ("ckpt_every", ctypes.c_int),
+        ("full_history", ctypes.c_int),
     ]
 
 
@@ -75,6 +76,7 @@ def _load():
     lib.lbm_forward.argtypes = [P, ctypes.c_long, ctypes.c_int, ctypes.POINTER(lbm_fwd_report)]
     lib.lbm_window_history.argtypes = [P, D, D, D, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.lbm_adjoint.argtypes = [P, ctypes.c_int, P, D]
+    lib.lbm_adjoint_full.argtypes = [P, P, D]
     lib.lbm_window_replay.argtypes = [P, P, D]
     lib.lbm_get_state.argtypes = [P, D, ctypes.POINTER(ctypes.c_long)]
     lib.lbm_set_state.argtypes = [P, D, ctypes.c_long]

@@ -34,6 +34,8 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
+    int nstart;                // window-start states kept (full history)
+    size_t off_starts, off_ringrep;
     int Q, D;
     long N;
     size_t ss, cs, as;         // bytes per stored / compute / adjoint value
@@ -66,6 +68,7 @@ lbm_status validate(const lbm_config* c) {
     if (c->ckpt_every < 1 || c->window_len % c->ckpt_every != 0)
         return fail(LBM_E_INVALID, "ckpt_every must divide window_len");
     if (c->max_windows < 1) return fail(LBM_E_INVALID, "max_windows must be >= 1");
+    if (c->full_history != 0 && c->full_history != 1) return fail(LBM_E_INVALID, "full_history must be 0 or 1");
     if (std::isnan(c->eps)) return fail(LBM_E_INVALID, "eps is NaN");
     if (c->objective < 0 || c->objective > 1 || c->monitor < 0 || c->monitor > 1)
         return fail(LBM_E_INVALID, "unknown objective or monitor");
@@ -127,6 +130,10 @@ void layout(const lbm_config* c, Layout& L) {
     L.off_roww = o;    o += align_up(c->ny);
     L.off_rowe = o;    o += align_up(c->ny);
     L.off_uin = o;     o += align_up(c->ny * 8);
+    // full history: the start state of every window and a ring for replays
+    L.nstart = c->full_history ? c->max_windows : 0;
+    L.off_starts = o;  o += (size_t)L.nstart * L.SB;
+    L.off_ringrep = o; o += c->full_history ? (size_t)L.R * L.SB : 0;
     L.total = o;
 }
 
@@ -158,6 +165,7 @@ struct lbm_ctx {
     void* G[2];
     std::vector<void*> ring[2];
     std::vector<void*> seg;
+    std::vector<void*> starts, ring_rep;   // full history: window-start states, replay ring
     void *s, *s_rep, *nu[2];
     double *gamma, *sens, *partials[2], *samples, *acc;
     Geo geo;
@@ -300,6 +308,7 @@ lbm_status start_from_slot(lbm_ctx* c, long k) {
     a.src = ring_slot_for_step(c, k);
     a.dst = c->G[0];
     HIPCHK(launch_aux(a));
+    if (!c->starts.empty()) HIPCHK(launch_copy(a.src, c->starts[0], c->L.SB, c->stream));
     c->cur = 0;
     c->step = k;
     c->base = k;
@@ -515,6 +524,110 @@ lbm_status set_adj_blocking(lbm_ctx* c, int nsteps, int tile_x, int tile_y) {
     return LBM_OK;
 }
 
+// Reverse sweep over one window whose first step is ns: transitions n_e down
+// to n_s, each K-step segment restarted from ring[seg] (its pre-collision
+// checkpoint) and recomputed into the seg slots. objective_window: the
+// window of the objective, which starts from the terminal condition and adds the sampled
+// objective source; otherwise the sweep continues from c->nu[cur] (the
+// adjoint of the next window's start state) with no source.
+lbm_status adjoint_window(lbm_ctx* c, const std::vector<void*>& ring, long ns, bool objective_window, int& cur) {
+    const long W = c->cfg.window_len, dW = c->cfg.sample_every, K = c->cfg.ckpt_every;
+    const Layout& L = c->L;
+    const double wgt = objective_window ? (double)dW / W : 0.0;
+    lbm_status st;
+    StepLaunch sa = step_args(c);
+    sa.s = c->s;
+    AdjLaunch aa;
+    aa.lattice = c->cfg.lattice;
+    aa.prec = c->cfg.prec;
+    aa.s = c->s;
+    aa.sens = c->sens;
+    aa.geo = c->geo;
+    aa.ph = c->ph;
+    aa.ob = c->ob;
+    aa.stream = c->stream;
+    aa.nsteps = 1;
+    aa.tile_x = c->adj_tile_x;
+    aa.tile_y = c->adj_tile_y;
+    aa.tile_z = c->adj_tile_z;
+    aa.gseg = c->seg[0];
+    aa.slot = L.SB;
+    aa.ns = ns;
+    aa.dW = dW;
+    aa.wgt = wgt;
+    for (int seg = L.R - 1; seg >= 0; --seg) {
+        const long c0 = ns - 1 + (long)seg * K;       // checkpoint step
+        aa.kseg = c0;
+        const bool last = seg == L.R - 1;
+        const bool seed = last && objective_window;
+        const long nrec = seed ? K - 1 : K - 2;       // step launches after the restart
+        if (seed || K >= 2) {
+            AuxLaunch ca = aux_args(c, AUX_COLLIDE);
+            ca.src = ring[seg];
+            ca.dst = c->seg[0];
+            HIPCHK(launch_aux(ca));
+            // recompute G^{c0+1} .. G^{c0+nrec} into seg[1 .. nrec]; blocked
+            // launches keep every intermediate state (seg slots are SB apart).
+            // D3Q19 recomputes in single steps: its two-step launch, which
+            // then also stores the first step's state, measured slower.
+            const long rec_max = c->cfg.lattice == LBM_D3Q19 ? 1 : c->tb_steps;
+            for (long j = 1; j <= nrec;) {
+                long n = nrec - j + 1;
+                if (n > rec_max) n = rec_max;
+                sa.nsteps = (int)n;
+                sa.gin = c->seg[j - 1];
+                sa.gout = c->seg[j + n - 1];
+                sa.allout = n > 1 ? c->seg[j] : nullptr;
+                sa.allout_slot = L.SB;
+                if ((st = t_launch(c, 2, n)) != LBM_OK) return st;
+                HIPCHK(launch_step(sa));
+                j += n;
+            }
+            sa.allout = nullptr;
+            sa.nsteps = 1;
+            if ((st = t_close(c)) != LBM_OK) return st;
+        }
+        if (seed) {
+            // terminal condition: nu_hat^{n_e} = BC^T (dJ/df^{n_e}), f^{n_e} = BC(S(G^{n_e - 1}))
+            aa.nu_in = nullptr;
+            aa.nu_out = c->nu[cur];
+            aa.state = c->seg[K - 1];
+            aa.direct = 0;
+            aa.seed = 1;
+            aa.src_w = wgt;
+            HIPCHK(launch_adjoint(aa));
+        }
+        for (long k = c0 + K; k >= c0 + 1;) {
+            aa.nu_in = c->nu[cur];
+            aa.nu_out = c->nu[cur ^ 1];
+            aa.seed = 0;
+            aa.nsteps = 1;
+            long n = 1;
+            if (k - 1 == c0) {
+                aa.direct = 1;
+                aa.state = ring[seg];
+            } else {
+                // steps k .. c0 + 2 pull their pre-state from the segment
+                aa.direct = 0;
+                aa.state = c->seg[k - 2 - c0];
+                n = k - (c0 + 1);
+                if (n > c->adj_steps) n = c->adj_steps;
+                if (n > 1) {
+                    aa.nsteps = (int)n;
+                    aa.k_hi = k;
+                }
+            }
+            aa.src_w = (k > ns && (k - ns) % dW == 0) ? wgt : 0.0;
+            if ((st = t_launch(c, 1, n)) != LBM_OK) return st;
+            HIPCHK(launch_adjoint(aa));
+            cur ^= 1;
+            k -= n;
+        }
+        if ((st = t_close(c)) != LBM_OK) return st;
+    }
+    return LBM_OK;
+}
+
 }  // namespace
 
 // Error recording shared with the design-update entry points.
@@ -589,6 +702,9 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
     for (int p = 0; p < 2; ++p)
         for (int r = 0; r < L.R; ++r) c->ring[p].push_back(at(c, L.off_ring + ((size_t)p * L.R + r) * L.SB));
     for (int k = 0; k < L.nseg; ++k) c->seg.push_back(at(c, L.off_seg + (size_t)k * L.SB));
+    for (int k = 0; k < L.nstart; ++k) c->starts.push_back(at(c, L.off_starts + (size_t)k * L.SB));
+    if (cfg->full_history)
+        for (int r = 0; r < L.R; ++r) c->ring_rep.push_back(at(c, L.off_ringrep + (size_t)r * L.SB));
     c->s = at(c, L.off_s);
     c->s_rep = at(c, L.off_srep);
     c->gamma = (double*)at(c, L.off_gamma);
@@ -761,6 +877,11 @@ lbm_status lbm_forward(lbm_ctx* c, long n_steps, int stop_on_converge, lbm_fwd_r
         }
         if ((st = t_launch(c, n > 1 ? 3 : 0, n)) != LBM_OK) return st;
         HIPCHK(launch_step(a));
+        if (mw == 0 && !c->starts.empty()) {
+            // full history: the start state of the next window
+            const long r = (m - c->base) / W;
+            if (r < (long)c->starts.size()) HIPCHK(launch_copy(a.pre, c->starts[r], L.SB, c->stream));
+        }
         c->cur ^= 1;
         c->step = m;
         done += n;
@@ -821,103 +942,60 @@ lbm_status lbm_adjoint(lbm_ctx* c, int window, double* dJdgamma_dev, double* J_o
     if (g == 0) return fail(LBM_E_STATE, "no completed window");
     if (window != 0 && window != g) return fail(LBM_E_STATE, "only the last completed window can be differentiated");
     if (c->unstable) return fail(LBM_E_STATE, "state is unstable");
-    const long W = c->cfg.window_len, dW = c->cfg.sample_every, K = c->cfg.ckpt_every;
+    const long W = c->cfg.window_len;
     const Layout& L = c->L;
-    const long ns = (g - 1) * W + 1;
-    const double wgt = (double)dW / W;
-    const int p = (int)(g % 2);
     lbm_status st;
     HIPCHK(launch_fill(c->sens, L.N, 0.0, c->stream));
-
-    StepLaunch sa = step_args(c);
-    sa.s = c->s;
-    AdjLaunch aa;
-    aa.lattice = c->cfg.lattice;
-    aa.prec = c->cfg.prec;
-    aa.s = c->s;
-    aa.sens = c->sens;
-    aa.geo = c->geo;
-    aa.ph = c->ph;
-    aa.ob = c->ob;
-    aa.stream = c->stream;
-    aa.nsteps = 1;
-    aa.tile_x = c->adj_tile_x;
-    aa.tile_y = c->adj_tile_y;
-    aa.tile_z = c->adj_tile_z;
-    aa.gseg = c->seg[0];
-    aa.slot = L.SB;
-    aa.ns = ns;
-    aa.dW = dW;
-    aa.wgt = wgt;
     int cur = 0;
-    for (int seg = L.R - 1; seg >= 0; --seg) {
-        const long c0 = ns - 1 + (long)seg * K;       // checkpoint step
-        aa.kseg = c0;
-        const bool last = seg == L.R - 1;
-        const long nrec = last ? K - 1 : K - 2;       // step launches after the restart
-        if (last || K >= 2) {
-            AuxLaunch ca = aux_args(c, AUX_COLLIDE);
-            ca.src = c->ring[p][seg];
-            ca.dst = c->seg[0];
-            HIPCHK(launch_aux(ca));
-            // recompute G^{c0+1} .. G^{c0+nrec} into seg[1 .. nrec]; blocked
-            // launches keep every intermediate state (seg slots are SB apart).
-            // D3Q19 recomputes in single steps: its two-step launch, which
-            // then also stores the first step's state, measured slower.
-            const long rec_max = c->cfg.lattice == LBM_D3Q19 ? 1 : c->tb_steps;
-            for (long j = 1; j <= nrec;) {
-                long n = nrec - j + 1;
-                if (n > rec_max) n = rec_max;
-                sa.nsteps = (int)n;
-                sa.gin = c->seg[j - 1];
-                sa.gout = c->seg[j + n - 1];
-                sa.allout = n > 1 ? c->seg[j] : nullptr;
-                sa.allout_slot = L.SB;
-                if ((st = t_launch(c, 2, n)) != LBM_OK) return st;
-                HIPCHK(launch_step(sa));
-                j += n;
-            }
-            sa.allout = nullptr;
-            sa.nsteps = 1;
-            if ((st = t_close(c)) != LBM_OK) return st;
-        }
-        if (last) {
-            // terminal condition: nu_hat^{n_e} = BC^T (dJ/df^{n_e}), f^{n_e} = BC(S(G^{n_e - 1}))
-            aa.nu_in = nullptr;
-            aa.nu_out = c->nu[cur];
-            aa.state = c->seg[K - 1];
-            aa.direct = 0;
-            aa.seed = 1;
-            aa.src_w = wgt;
-            HIPCHK(launch_adjoint(aa));
-        }
-        for (long k = c0 + K; k >= c0 + 1;) {
-            aa.nu_in = c->nu[cur];
-            aa.nu_out = c->nu[cur ^ 1];
-            aa.seed = 0;
-            aa.nsteps = 1;
-            long n = 1;
-            if (k - 1 == c0) {
-                aa.direct = 1;
-                aa.state = c->ring[p][seg];
-            } else {
-                // steps k .. c0 + 2 pull their pre-state from the segment
-                aa.direct = 0;
-                aa.state = c->seg[k - 2 - c0];
-                n = k - (c0 + 1);
-                if (n > c->adj_steps) n = c->adj_steps;
-                if (n > 1) {
-                    aa.nsteps = (int)n;
-                    aa.k_hi = k;
-                }
-            }
-            aa.src_w = (k > ns && (k - ns) % dW == 0) ? wgt : 0.0;
-            if ((st = t_launch(c, 1, n)) != LBM_OK) return st;
-            HIPCHK(launch_adjoint(aa));
-            cur ^= 1;
-            k -= n;
+    if ((st = adjoint_window(c, c->ring[g % 2], (g - 1) * W + 1, true, cur)) != LBM_OK) return st;
+    HIPCHK(launch_finalize(c->gamma, c->sens, dJdgamma_dev, L.N, c->cfg.s_map, c->cfg.s_q, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if ((st = t_drain(c)) != LBM_OK) return st;
+    if (J_out) *J_out = c->J.back();
+    return LBM_OK;
+}
+
+lbm_status lbm_adjoint_full(lbm_ctx* c, double* dJdgamma_dev, double* J_out) {
+    if (!c || !dJdgamma_dev) return fail(LBM_E_INVALID, "NULL argument");
+    if (c->starts.empty()) return fail(LBM_E_STATE, "the full-time adjoint needs cfg.full_history = 1");
+    const long g = last_window(c);
+    if (g == 0) return fail(LBM_E_STATE, "no completed window");
+    if (c->unstable) return fail(LBM_E_STATE, "state is unstable");
+    const long W = c->cfg.window_len, K = c->cfg.ckpt_every;
+    const long g0 = c->base / W + 1;                  // first window of the history
+    if (g - g0 + 1 > (long)c->starts.size())
+        return fail(LBM_E_STATE, "more windows than max_windows since the start of the history");
+    const Layout& L = c->L;
+    lbm_status st;
+    HIPCHK(launch_fill(c->sens, L.N, 0.0, c->stream));
+    int cur = 0;
+    if ((st = adjoint_window(c, c->ring[g % 2], (g - 1) * W + 1, true, cur)) != LBM_OK) return st;
+    StepLaunch a = step_args(c);
+    a.s = c->s;
+    for (long gw = g - 1; gw >= g0; --gw) {
+        // rebuild window gw's checkpoints by replaying it from its start state
+        HIPCHK(launch_copy(c->starts[gw - g0], c->ring_rep[0], L.SB, c->stream));
+        AuxLaunch ca = aux_args(c, AUX_COLLIDE);
+        ca.src = c->ring_rep[0];
+        ca.dst = c->seg[0];
+        HIPCHK(launch_aux(ca));
+        int sc = 0;
+        for (long m0 = 0; m0 < W - K;) {
+            const long n = plan_launch(c, m0, K, W, W - K - m0, false);
+            const long m = m0 + n;
+            a.nsteps = (int)n;
+            a.gin = c->seg[sc];
+            a.gout = c->seg[sc ^ 1];
+            a.pre = (m % K == 0) ? c->ring_rep[m / K] : nullptr;
+            a.sample = 0;
+            if ((st = t_launch(c, 2, n)) != LBM_OK) return st;
+            HIPCHK(launch_step(a));
+            sc ^= 1;
+            m0 = m;
         }
         if ((st = t_close(c)) != LBM_OK) return st;
+        // its reverse sweep from the adjoint of the next window's start state
+        if ((st = adjoint_window(c, c->ring_rep, (gw - 1) * W + 1, false, cur)) != LBM_OK) return st;
     }
     HIPCHK(launch_finalize(c->gamma, c->sens, dJdgamma_dev, L.N, c->cfg.s_map, c->cfg.s_q, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));

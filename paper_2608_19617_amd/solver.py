@@ -61,6 +61,7 @@ def make_config(w, prec="f32"):
     c.sec_in_x, c.sec_in_lo, c.sec_in_hi = (int(v) for v in w.sec_in)
     c.sec_out_x, c.sec_out_lo, c.sec_out_hi = (int(v) for v in w.sec_out)
     c.ckpt_every = int(w.ckpt_every)
+    c.full_history = int(bool(getattr(w, "full_history", False)))
     return c, (west, east, u_in)
 
 
@@ -152,6 +153,17 @@ class Solver:
         out = torch.empty(self.N, dtype=torch.float64, device=self.device)
         J = ctypes.c_double(0.0)
         B.check(B.lib.lbm_adjoint(self._ctx, int(window), ctypes.c_void_p(out.data_ptr()), ctypes.byref(J)))
+        rev = tuple(reversed(self.shape))
+        g = out.reshape(rev).permute(*range(len(rev) - 1, -1, -1))
+        return g, J.value
+
+    def adjoint_full(self):
+        """Full-time adjoint (needs the workload's full_history): dJ/dgamma of
+        the last window's objective through the whole history, (torch FP64
+        [x, y(, z)], J)."""
+        out = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        J = ctypes.c_double(0.0)
+        B.check(B.lib.lbm_adjoint_full(self._ctx, ctypes.c_void_p(out.data_ptr()), ctypes.byref(J)))
         rev = tuple(reversed(self.shape))
         g = out.reshape(rev).permute(*range(len(rev) - 1, -1, -1))
         return g, J.value

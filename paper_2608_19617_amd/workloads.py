@@ -50,6 +50,7 @@ class Workload:
     n_steps: int = 100               # forward steps of the workload
     s_map: str = "linear"
     s_q: float = 0.1
+    full_history: bool = False       # keep every window's start state (full-time adjoint)
     notes: dict = field(default_factory=dict)
 
     @property

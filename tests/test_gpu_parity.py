@@ -780,3 +780,72 @@ def test_cylinder_3d_full_size(Solver):
     e = rel_l2(res["f32"], res["f64"])
     print(f"cylinder 3D dJ/dgamma FP32 vs FP64: {e:.2e}")
     assert e <= 1e-4
+
+
+# ------------------------------------------------------ full-time adjoint
+
+def _full_cases():
+    w = W.cylinder_channel(nx=40, ny=18, radius=3, center=(12, 9), window_len=12, sample_every=3,
+                           ckpt_every=4, n_windows=3)
+    w.gamma = np.clip(w.gamma + 0.3 * W.random_design(w.shape, 2), 0, 1)
+    cases = [("channel", w)]
+    w3 = _small_3d_cases()[1][1]
+    w3.window_len, w3.sample_every, w3.ckpt_every, w3.max_windows = 6, 2, 3, 3
+    cases.append(("d3q19_walls_z", w3))
+    return cases
+
+
+@pytest.mark.parametrize("name,w", _full_cases(), ids=lambda v: v if isinstance(v, str) else "")
+def test_full_time_adjoint_matches_oracle(Solver, name, w):
+    """lbm_adjoint_full (every window's start state kept; earlier windows
+    replayed to rebuild their checkpoints; their reverse sweeps chained from
+    the adjoint of the next window's start state, with no objective source)
+    against the oracle's full-time gradient from f^0 (FP64 <= 1e-10), FP32
+    against FP64 (<= 1e-4); the window-restricted adjoint is unchanged by it
+    and differs from it."""
+    w.eps = -1.0
+    w.full_history = True
+    n = 3
+    prob = oracle_problem(w)
+    J_o, g_o = ad.full_gradient(prob, w.gamma, n)
+    res = {}
+    for prec in ("f64", "f32"):
+        sv = Solver(w, prec)
+        rep = sv.forward(n * w.window_len)
+        assert rep["windows_done"] == n
+        g_win, J_win = sv.adjoint()
+        g, J = sv.adjoint_full()
+        g_win2, _ = sv.adjoint()
+        assert np.array_equal(g_win.cpu().numpy(), g_win2.cpu().numpy())
+        res[prec] = (g.cpu().numpy(), J, g_win.cpu().numpy())
+        sv.close()
+    g64, J64, gw64 = res["f64"]
+    assert abs(J64 - J_o) <= 1e-12 * abs(J_o) + 1e-18
+    assert rel_l2(g64, g_o) <= 1e-10
+    assert rel_l2(g64, gw64) > 1e-6
+    assert rel_l2(res["f32"][0], g64) <= 1e-4
+
+
+def test_full_time_adjoint_errors(Solver):
+    """Without full history, before a window ends, or with more windows than
+    max_windows since the start of the history: LBM_E_STATE."""
+    from paper_2608_19617_amd.binding import LbmError
+    w = W.cylinder_channel(nx=40, ny=18, radius=3, center=(12, 9), window_len=8, sample_every=2,
+                           ckpt_every=4, n_windows=2)
+    sv = Solver(w, "f32")
+    sv.forward(w.window_len)
+    with pytest.raises(LbmError, match="full_history"):
+        sv.adjoint_full()
+    sv.close()
+    w.full_history = True
+    sv = Solver(w, "f32")
+    with pytest.raises(LbmError, match="LBM_E_STATE"):
+        sv.adjoint_full()
+    sv.forward(3 * w.window_len)
+    with pytest.raises(LbmError, match="max_windows"):
+        sv.adjoint_full()
+    sv.reset()
+    sv.forward(2 * w.window_len)
+    g, J = sv.adjoint_full()
+    assert np.isfinite(J) and np.all(np.isfinite(g.cpu().numpy()))
+    sv.close()
