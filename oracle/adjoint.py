@@ -6,7 +6,11 @@ and the adjoint streaming (Eq. adjoint_streaming), the adjoint wall rule and
 the adjoint Zou-He inlet and outlet rules (Eqs. adjoint_inlet_bc,
 adjoint_outlet_bc), the sensitivity (Eq. sensitivity), and the sampled
 objective source of Eq. weighted_temporal_sampling, solved backward from the
-end of the representative window to its beginning.
+end of the representative window to its beginning. The paper's own
+objectives are included: the drag of the cylinder example, whose samples
+depend on the design directly (an explicit dD/ds term beside the sources),
+and the wake-recovery objective, a function of the window-mean velocity
+whose sources carry 2 (u_bar - u_ref).
 
 Sign convention: the paper's multiplier lambda multiplies
 (f^{n+1} - f** ) in the Lagrangian, so the adjoint carried here is
@@ -249,12 +253,35 @@ def sensitivity_term(prob, f, kappa):
     return (kappa * diff).sum(axis=0)
 
 
-def objective_gradient(prob, f, kind=None):
-    """d j / d f on a post-boundary state, for j = 'dp' or 'diss_dp'."""
+def objective_gradient(prob, f, kind=None, s=None, u_bar=None):
+    """d j / d f on a post-boundary state, for j = 'dp', 'diss_dp', 'drag'
+    (needs the bounce-back fraction s) or 'wake' (the derivative of the
+    window value with respect to one sample's velocity, without the sample
+    weight; needs the window-mean velocity u_bar on M)."""
     kind = prob.objective if kind is None else kind
     lat = prob.lat
     cs2 = lat.cs2
-    g = np.zeros(f.shape, dtype=f.dtype)
+    g = np.zeros(f.shape, dtype=np.result_type(f, 0.0 if s is None else s))
+    if kind == "drag":
+        # D = -sum_box sum_alpha c_x,alpha s (f*_opp(alpha) - f*_alpha), with
+        # d f* / d f the collision Jacobian without the fluid-solid term
+        jac = collision_jacobian(prob, f, 0.0)
+        cx = lat.c[:, 0].astype(np.float64)
+        box = fw.box_slices(prob.force_box)
+        for a in range(lat.Q):
+            dFx = sum(cx[b] * (jac[lat.opp[b], a] - jac[b, a]) for b in range(lat.Q))
+            g[a][box] = -(s * dFx)[box]
+        return g
+    if kind == "wake":
+        # J = sum_M |u_bar - u_ref|^2, d u / d f_alpha = (c_alpha - u) / rho
+        msl = (slice(None),) + fw.box_slices(prob.meas_box)
+        rho = fw.density(f)[msl[1:]]
+        u = fw.velocity(prob, f)[msl]
+        r = 2.0 * (u_bar - prob.u_ref)
+        c = lat.c.astype(np.float64)
+        for a in range(lat.Q):
+            g[a][msl[1:]] = sum(r[p] * (c[a, p] - u[p]) for p in range(lat.d)) / rho
+        return g
     xi, lo, hi = prob.sec_in
     n_in = (hi - lo) * (prob.shape[2] if lat.d == 3 else 1)
     g[:, xi, lo:hi] += cs2 / n_in
@@ -276,6 +303,18 @@ def objective_gradient(prob, f, kind=None):
         g = g + (dZ * h + Z * dh) / (2 * cs2)
     elif kind != "dp":
         raise ValueError(kind)
+    return g
+
+
+def objective_design_gradient(prob, f, kind=None):
+    """Explicit d j / d s of a sample at fixed populations: nonzero for the
+    drag only, dD/ds = -sum_alpha c_x,alpha (f*_opp(alpha) - f*_alpha) on the
+    force box."""
+    kind = prob.objective if kind is None else kind
+    g = np.zeros(prob.shape, dtype=f.dtype)
+    if kind == "drag":
+        box = fw.box_slices(prob.force_box)
+        g[box] = -fw.solid_force(prob, f, 1.0)[0][box]
     return g
 
 
@@ -311,16 +350,27 @@ def window_gradient(prob, gamma, f_start):
     states = [f_start]
     for m in range(1, W + 1):
         states.append(fw.step(prob, states[-1], s))
-    J = 0.0
-    for m in range(dW, W + 1, dW):
-        J = J + wgt * fw.sample(prob, states[m], prob.objective)
-    nu = wgt * objective_gradient(prob, states[W])
-    sens = np.zeros(prob.shape, dtype=np.result_type(states[0], s))
+    u_bar = None
+    if prob.objective == "wake":
+        msl = (slice(None),) + fw.box_slices(prob.meas_box)
+        u_bar = sum(wgt * fw.velocity(prob, states[m])[msl] for m in range(dW, W + 1, dW))
+        J = fw.wake_value(prob, u_bar)
+    else:
+        J = 0.0
+        for m in range(dW, W + 1, dW):
+            J = J + wgt * fw.sample(prob, states[m], prob.objective, s)
+
+    def source(m):
+        return wgt * objective_gradient(prob, states[m], prob.objective, s, u_bar)
+
+    nu = source(W)
+    sens = wgt * objective_design_gradient(prob, states[W])
     for m in range(W, 0, -1):
         nu, dsens = adjoint_step(prob, states[m - 1], s, nu)
         sens = sens + dsens
         if m - 1 >= 1 and (m - 1) % dW == 0:
-            nu = nu + wgt * objective_gradient(prob, states[m - 1])
+            nu = nu + source(m - 1)
+            sens = sens + wgt * objective_design_gradient(prob, states[m - 1])
     return J, fw.design_map_derivative(prob, gamma) * sens, nu
 
 

@@ -32,6 +32,16 @@ design notes of the repository):
   * window i is the |W| transitions ending at step i|W|; the criterion is
     strict, window 1 never converges, a zero current mean converges only if
     the previous mean is zero too.
+  * drag (Sec. 3.1, Eq. C_d and the drag objective of the cylinder example):
+    the force of Eq. external_force summed over the nodes of a box and the
+    directions, F = sum_i sum_alpha c_alpha F_alpha, acts on the fluid; the
+    drag is its negative x component, D = -F_x, the force the flow exerts on
+    the porous solid (positive for flow along +x). C_d = D / d_ref with
+    d_ref = rho_0 u_0^2 L_ref / 2 given.
+  * wake recovery (Sec. "Wake flow recovery"): the window value is
+    J = sum_{i in M} |u_bar_i - u_ref_i|^2 with u_bar the dW/|W|-weighted sum
+    of the sampled velocities u = j / rho over the window; M is a box and
+    u_ref is given (zero unless set).
 """
 
 import numpy as np
@@ -56,6 +66,12 @@ class Problem:
                 (dissipation plus pressure drop)
     monitor     quantity averaged for the window test ('dp' or 'diss_dp')
     sec_in, sec_out  (x, ylo, yhi) pressure sections (all z in 3D)
+    objective   also 'drag' (drag force over force_box) or 'wake' (wake
+                recovery over meas_box); monitor also 'cd' (drag / drag_ref)
+    force_box   ((x0, x1), (y0, y1)[, (z0, z1)]) half-open, None = whole grid
+    drag_ref    rho_0 u_0^2 L_ref / 2, the denominator of C_d
+    meas_box    measurement region M of the wake objective (as force_box)
+    u_ref       reference mean velocity on M, shape (d, *box shape); None = 0
     window_len, sample_every, eps, max_windows   window parameters
     rho_init, u_init   initial macroscopic fields (scalar / (d, *shape))
     """
@@ -64,7 +80,8 @@ class Problem:
                  u_in=None, rho_out=1.0, s_map="linear", s_q=0.1,
                  objective="dp", monitor=None, sec_in=None, sec_out=None,
                  window_len=1, sample_every=1, eps=-1.0, max_windows=1,
-                 rho_init=1.0, u_init=None):
+                 rho_init=1.0, u_init=None, force_box=None, drag_ref=1.0, meas_box=None,
+                 u_ref=None):
         self.shape = tuple(int(n) for n in shape)
         self.lat = D2Q9 if len(self.shape) == 2 else D3Q19
         d = self.lat.d
@@ -79,7 +96,9 @@ class Problem:
         self.s_map = s_map
         self.s_q = float(s_q)
         self.objective = objective
-        self.monitor = objective if monitor is None else monitor
+        if monitor is None:
+            monitor = "dp" if objective == "wake" else objective
+        self.monitor = monitor
         self.sec_in = sec_in if sec_in is not None else (0, 0, ny)
         self.sec_out = sec_out if sec_out is not None else (self.shape[0] - 1, 0, ny)
         self.window_len = int(window_len)
@@ -88,12 +107,22 @@ class Problem:
         self.max_windows = int(max_windows)
         self.rho_init = rho_init
         self.u_init = np.zeros((d,) + self.shape) if u_init is None else np.asarray(u_init)
+        full = tuple((0, n) for n in self.shape)
+        self.force_box = full if force_box is None else tuple(tuple(b) for b in force_box)
+        self.drag_ref = float(drag_ref)
+        self.meas_box = full if meas_box is None else tuple(tuple(b) for b in meas_box)
+        mshape = tuple(hi - lo for lo, hi in self.meas_box)
+        self.u_ref = np.zeros((d,) + mshape) if u_ref is None else np.asarray(u_ref)
         self._geom = None
         self._check()
 
     def _check(self):
         assert self.tau > 0.5
         assert self.window_len % self.sample_every == 0
+        for box in (self.force_box, self.meas_box):
+            assert len(box) == len(self.shape)
+            assert all(0 <= lo < hi <= n for (lo, hi), n in zip(box, self.shape))
+        assert self.u_ref.shape == (self.lat.d,) + tuple(hi - lo for lo, hi in self.meas_box)
         ny = self.shape[1]
         if not self.periodic[0]:
             for kinds in (self.west, self.east):
@@ -400,12 +429,51 @@ def dissipation(prob, f):
     return ((te - 0.5) * PP / (2 * rho * prob.lat.cs2 * te * te)).sum()
 
 
-def sample(prob, f, kind):
-    """Instantaneous objective / monitor value j(t) on a post-boundary state."""
+def box_slices(box):
+    """Index slices of a half-open box ((x0, x1), (y0, y1)[, (z0, z1)])."""
+    return tuple(slice(lo, hi) for lo, hi in box)
+
+
+def solid_force(prob, f, s):
+    """Eq. external_force summed over the directions: F = sum_alpha c_alpha
+    F_alpha at every node, F_alpha = s (f*_opp(alpha) - f*_alpha) on the
+    post-collision populations f* of the post-boundary state f. Shape
+    (d, *shape)."""
+    lat = prob.lat
+    fstar, _ = collide(prob, f)
+    F = s * (fstar[lat.opp] - fstar)
+    return momentum(lat, F)
+
+
+def drag_force(prob, f, s):
+    """D = -sum_{i in force_box} F_x(x_i): the x force that the fluid exerts
+    on the porous solid in the box (the negative of the x momentum that the
+    fluid-solid term removes from the fluid)."""
+    return -solid_force(prob, f, s)[0][box_slices(prob.force_box)].sum()
+
+
+def velocity(prob, f):
+    """u = j / rho, shape (d, *shape)."""
+    return momentum(prob.lat, f) / density(f)
+
+
+def wake_value(prob, u_bar):
+    """Wake-recovery objective J = sum_{i in M} |u_bar_i - u_ref_i|^2 for a
+    window-mean velocity u_bar given on M, shape (d, *box shape)."""
+    return ((u_bar - prob.u_ref) ** 2).sum()
+
+
+def sample(prob, f, kind, s=None):
+    """Instantaneous objective / monitor value j(t) on a post-boundary state
+    (s, the bounce-back fraction, is needed by 'drag' and 'cd')."""
     if kind == "dp":
         return pressure_drop(prob, f)
     if kind == "diss_dp":
         return dissipation(prob, f) + pressure_drop(prob, f)
+    if kind == "drag":
+        return drag_force(prob, f, s)
+    if kind == "cd":
+        return drag_force(prob, f, s) / prob.drag_ref
     raise ValueError(kind)
 
 
@@ -438,7 +506,10 @@ def run(prob, gamma, n_steps, stop_on_converge=False, keep=()):
     W, dW = prob.window_len, prob.sample_every
     wgt = dW / W
     Jacc = Macc = 0.0
-    out = dict(J=[], M=[], rel=[], converged=[], states={})
+    wake = prob.objective == "wake"
+    msl = (slice(None),) + box_slices(prob.meas_box)
+    ubar = 0.0
+    out = dict(J=[], M=[], rel=[], converged=[], states={}, u_bar=None)
     if 0 in keep:
         out["states"][0] = f.copy()
     k = 0
@@ -447,9 +518,16 @@ def run(prob, gamma, n_steps, stop_on_converge=False, keep=()):
         if k in keep:
             out["states"][k] = f.copy()
         if k % dW == 0:
-            Jacc += wgt * sample(prob, f, prob.objective)
-            Macc += wgt * sample(prob, f, prob.monitor)
+            if wake:
+                ubar = ubar + wgt * velocity(prob, f)[msl]
+            else:
+                Jacc += wgt * sample(prob, f, prob.objective, s)
+            Macc += wgt * sample(prob, f, prob.monitor, s)
         if k % W == 0:
+            if wake:
+                Jacc = wake_value(prob, ubar)
+                out["u_bar"] = ubar
+                ubar = 0.0
             out["J"].append(Jacc)
             out["M"].append(Macc)
             if len(out["M"]) == 1:
@@ -474,8 +552,13 @@ def window_objective(prob, gamma, f_start):
     W, dW = prob.window_len, prob.sample_every
     f = f_start
     J = 0.0
+    ubar = 0.0
+    msl = (slice(None),) + box_slices(prob.meas_box)
     for m in range(1, W + 1):
         f = step(prob, f, s)
         if m % dW == 0:
-            J = J + dW / W * sample(prob, f, prob.objective)
-    return J
+            if prob.objective == "wake":
+                ubar = ubar + dW / W * velocity(prob, f)[msl]
+            else:
+                J = J + dW / W * sample(prob, f, prob.objective, s)
+    return wake_value(prob, ubar) if prob.objective == "wake" else J
