@@ -79,7 +79,22 @@ enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };                 /* lattice */
 enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2 };      /* population storage */
 enum { LBM_WALL = 0, LBM_VELOCITY = 1, LBM_PRESSURE = 2 }; /* x-face row kinds */
 enum { LBM_S_LINEAR = 0, LBM_S_PAPER = 1 };           /* s(gamma) */
-enum { LBM_J_PRESSURE_DROP = 0, LBM_J_DISSIPATION_PLUS_DP = 1 }; /* objective / monitor */
+/* Objective / monitor kinds (Sec. 3.1 and the examples of Sec. 4):
+ *   LBM_J_PRESSURE_DROP        c_s^2 (mean rho over sec_in - mean over sec_out)
+ *   LBM_J_DISSIPATION_PLUS_DP  sum of the node dissipation 2 rho nu_eff S:S plus
+ *                              the pressure drop
+ *   LBM_J_DRAG                 objective: the drag D = sum over force_box of
+ *                              2 s rho u_x, the x force the flow exerts on the
+ *                              porous solid (minus the x part of the force of
+ *                              Eq. external_force summed over the directions);
+ *                              monitor: the drag coefficient C_d = D / drag_ref
+ *                              (Eq. C_d)
+ *   LBM_J_WAKE                 objective only (wake recovery): the window value
+ *                              J = sum over meas_box of |u_bar - u_ref|^2, u_bar
+ *                              the dW/|W|-weighted sum of the sampled u = j / rho
+ *                              over the window, u_ref set by
+ *                              lbm_set_wake_reference (zero until then) */
+enum { LBM_J_PRESSURE_DROP = 0, LBM_J_DISSIPATION_PLUS_DP = 1, LBM_J_DRAG = 2, LBM_J_WAKE = 3 };
 
 /*
  * Problem description. Storage precisions: LBM_F64 stores and computes in
@@ -115,6 +130,11 @@ typedef struct {
     int ckpt_every;              /* K: checkpoint interval, must divide window_len */
     int full_history;            /* 1: also keep the start state of every window (for
                                     lbm_adjoint_full); 0: the two newest windows only */
+    int force_box[6];            /* x0, x1, y0, y1, z0, z1: half-open node box of the drag
+                                    sum; x1 <= x0 means the whole grid; z ignored in 2D */
+    double drag_ref;             /* rho_0 u_0^2 L_ref / 2, the denominator of C_d; must be
+                                    > 0 when the monitor is LBM_J_DRAG */
+    int meas_box[6];             /* measurement region M of LBM_J_WAKE, as force_box */
 } lbm_config;
 
 /* Result of lbm_forward. w_eff is the 1-based index of the last completed
@@ -169,7 +189,9 @@ lbm_status lbm_window_history(lbm_ctx* ctx, double* J, double* M, double* rel, i
  * completed window (or pass 0 for it). Writes dJ/dgamma (device FP64, N
  * values) and, if J_out is not NULL, the window objective. The forward
  * state is not changed. Recomputes each K-step segment from its HBM
- * checkpoint. */
+ * checkpoint. The drag's samples depend on s directly: their explicit
+ * derivative, dW/|W| times 2 j_x summed over the window's samples, is kept
+ * by the forward on the force box and added here. */
 lbm_status lbm_adjoint(lbm_ctx* ctx, int window, double* dJdgamma_dev, double* J_out);
 
 /* Full-time adjoint (the comparison case of Sec. "Comparison with full-time
@@ -190,6 +212,20 @@ lbm_status lbm_adjoint_full(lbm_ctx* ctx, double* dJdgamma_dev, double* J_out);
  * the function lbm_adjoint differentiates, for finite-difference checks.
  * The forward state, checkpoints and the context's own gamma are unchanged. */
 lbm_status lbm_window_replay(lbm_ctx* ctx, const double* gamma_dev, double* J_out);
+
+/* Wake recovery (objective LBM_J_WAKE): sets the reference mean velocity
+ * u_ref on the measurement box M from device FP64 memory, D planes of |M|
+ * values (component p of box node (i, j, k) at p |M| + (k nyM + j) nxM + i,
+ * box coordinates relative to its low corner). Window values of later
+ * windows and replays, and the adjoint, use it. LBM_E_STATE if the
+ * objective is not LBM_J_WAKE. */
+lbm_status lbm_set_wake_reference(lbm_ctx* ctx, const double* u_ref_dev);
+
+/* Wake recovery: the window-mean velocity u_bar of the last completed
+ * window on M (layout of lbm_set_wake_reference) to device FP64 memory.
+ * With the flow of a reference design, this is the u_ref of the problem.
+ * LBM_E_STATE if the objective is not LBM_J_WAKE or no window completed. */
+lbm_status lbm_wake_mean_velocity(lbm_ctx* ctx, double* u_bar_dev);
 
 /* Exports the current state f^k (unshifted populations, FP64, Q*N values in
  * SoA order) to host memory, and its step k. */

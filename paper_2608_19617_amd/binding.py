@@ -14,13 +14,14 @@ LBM_D2Q9, LBM_D3Q19 = 0, 1
 LBM_F64, LBM_F32, LBM_F16S = 0, 1, 2
 LBM_WALL, LBM_VELOCITY, LBM_PRESSURE = 0, 1, 2
 LBM_S_LINEAR, LBM_S_PAPER = 0, 1
-LBM_J_PRESSURE_DROP, LBM_J_DISSIPATION_PLUS_DP = 0, 1
+LBM_J_PRESSURE_DROP, LBM_J_DISSIPATION_PLUS_DP, LBM_J_DRAG, LBM_J_WAKE = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "LBM_OK", 1: "LBM_E_INVALID", 2: "LBM_E_NOMEM", 3: "LBM_E_HIP",
                 4: "LBM_E_UNSTABLE", 5: "LBM_E_STATE"}
 
 EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_set_gamma", "lbm_reset", "lbm_forward",
-            "lbm_window_history", "lbm_adjoint", "lbm_adjoint_full", "lbm_window_replay", "lbm_get_state",
+            "lbm_window_history", "lbm_adjoint", "lbm_adjoint_full", "lbm_window_replay",
+            "lbm_set_wake_reference", "lbm_wake_mean_velocity", "lbm_get_state",
             "lbm_set_state", "lbm_get_fields", "lbm_timing", "lbm_set_blocking", "lbm_set_blocking_3d",
             "lbm_set_adjoint_blocking", "lbm_set_adjoint_blocking_3d", "lbm_last_error", "lbm_destroy",
             "lbm_design_workspace_bytes", "lbm_design_init", "lbm_design_map", "lbm_design_chain",
@@ -43,6 +44,7 @@ class lbm_config(ctypes.Structure):
         ("sec_out_x", ctypes.c_int), ("sec_out_lo", ctypes.c_int), ("sec_out_hi", ctypes.c_int),
         ("ckpt_every", ctypes.c_int),
         ("full_history", ctypes.c_int),
+        ("force_box", ctypes.c_int * 6), ("drag_ref", ctypes.c_double), ("meas_box", ctypes.c_int * 6),
     ]
 
 
@@ -78,6 +80,8 @@ def _load():
     lib.lbm_adjoint.argtypes = [P, ctypes.c_int, P, D]
     lib.lbm_adjoint_full.argtypes = [P, P, D]
     lib.lbm_window_replay.argtypes = [P, P, D]
+    lib.lbm_set_wake_reference.argtypes = [P, P]
+    lib.lbm_wake_mean_velocity.argtypes = [P, P]
     lib.lbm_get_state.argtypes = [P, D, ctypes.POINTER(ctypes.c_long)]
     lib.lbm_set_state.argtypes = [P, D, ctypes.c_long]
     lib.lbm_get_fields.argtypes = [P, P]

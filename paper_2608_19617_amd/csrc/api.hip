@@ -47,7 +47,27 @@ struct Layout {
     int nsamp;                 // samples per window
     size_t off_G, off_ring, off_seg, off_s, off_srep, off_gamma, off_nu, off_sens, off_part, off_samples,
         off_acc, off_roww, off_rowe, off_uin, total;
+    int fbox[6], mbox[6];      // force and measurement boxes, resolved
+    int ncomp;                 // window-field components: 1 (drag), D (wake), 0
+    long nb, nf;               // nodes of the accumulator box; nb * ncomp
+    size_t off_facc;           // three accumulators, the wake reference, reduction scratch
 };
+
+constexpr int FACC_PARTS = 1024;   // block partials of the wake window value
+
+// A half-open box x0, x1, y0, y1, z0, z1; x1 <= x0 selects the whole grid;
+// z is [0, 1) in 2D.
+bool resolve_box(const lbm_config* c, const int* b, int out[6]) {
+    const int n[3] = {c->nx, c->ny, c->nz};
+    const bool whole = b[1] <= b[0];
+    for (int a = 0; a < 3; ++a) {
+        const bool take_all = whole || (a == 2 && c->lattice == LBM_D2Q9);
+        out[2 * a] = take_all ? 0 : b[2 * a];
+        out[2 * a + 1] = take_all ? n[a] : b[2 * a + 1];
+        if (out[2 * a] < 0 || out[2 * a] >= out[2 * a + 1] || out[2 * a + 1] > n[a]) return false;
+    }
+    return true;
+}
 
 lbm_status validate(const lbm_config* c) {
     if (!c) return fail(LBM_E_INVALID, "config is NULL");
@@ -70,8 +90,14 @@ lbm_status validate(const lbm_config* c) {
     if (c->max_windows < 1) return fail(LBM_E_INVALID, "max_windows must be >= 1");
     if (c->full_history != 0 && c->full_history != 1) return fail(LBM_E_INVALID, "full_history must be 0 or 1");
     if (std::isnan(c->eps)) return fail(LBM_E_INVALID, "eps is NaN");
-    if (c->objective < 0 || c->objective > 1 || c->monitor < 0 || c->monitor > 1)
+    if (c->objective < LBM_J_PRESSURE_DROP || c->objective > LBM_J_WAKE || c->monitor < LBM_J_PRESSURE_DROP ||
+        c->monitor > LBM_J_DRAG)
         return fail(LBM_E_INVALID, "unknown objective or monitor");
+    int box[6];
+    if (!resolve_box(c, c->force_box, box)) return fail(LBM_E_INVALID, "bad force_box");
+    if (!resolve_box(c, c->meas_box, box)) return fail(LBM_E_INVALID, "bad meas_box");
+    if (c->monitor == LBM_J_DRAG && !(c->drag_ref > 0.0 && std::isfinite(c->drag_ref)))
+        return fail(LBM_E_INVALID, "drag_ref must be > 0 for the C_d monitor");
     if (c->sec_in_x < 0 || c->sec_in_x >= c->nx || c->sec_out_x < 0 || c->sec_out_x >= c->nx ||
         c->sec_in_lo < 0 || c->sec_in_hi > c->ny || c->sec_in_lo >= c->sec_in_hi || c->sec_out_lo < 0 ||
         c->sec_out_hi > c->ny || c->sec_out_lo >= c->sec_out_hi)
@@ -134,6 +160,14 @@ void layout(const lbm_config* c, Layout& L) {
     L.nstart = c->full_history ? c->max_windows : 0;
     L.off_starts = o;  o += (size_t)L.nstart * L.SB;
     L.off_ringrep = o; o += c->full_history ? (size_t)L.R * L.SB : 0;
+    // window field of the drag (explicit dD/ds) or of the wake (u_bar)
+    resolve_box(c, c->force_box, L.fbox);
+    resolve_box(c, c->meas_box, L.mbox);
+    const int* ab = c->objective == LBM_J_WAKE ? L.mbox : L.fbox;
+    L.nb = (long)(ab[1] - ab[0]) * (ab[3] - ab[2]) * (ab[5] - ab[4]);
+    L.ncomp = c->objective == LBM_J_DRAG ? 1 : (c->objective == LBM_J_WAKE ? L.D : 0);
+    L.nf = L.ncomp * L.nb;
+    L.off_facc = o;    o += L.ncomp ? 4 * align_up((size_t)L.nf * 8) + align_up(FACC_PARTS * 8) : 0;
     L.total = o;
 }
 
@@ -166,6 +200,9 @@ struct lbm_ctx {
     std::vector<void*> ring[2];
     std::vector<void*> seg;
     std::vector<void*> starts, ring_rep;   // full history: window-start states, replay ring
+    double* facc[3];                 // window-field accumulators (two forward, one replay)
+    double *uref, *fparts;           // wake reference; wake-value block partials
+    int fa, fw;                      // forward accumulator in use; last completed window's (-1: none)
     void *s, *s_rep, *nu[2];
     double *gamma, *sens, *partials[2], *samples, *acc;
     Geo geo;
@@ -309,6 +346,9 @@ lbm_status start_from_slot(lbm_ctx* c, long k) {
     a.dst = c->G[0];
     HIPCHK(launch_aux(a));
     if (!c->starts.empty()) HIPCHK(launch_copy(a.src, c->starts[0], c->L.SB, c->stream));
+    if (c->L.ncomp) HIPCHK(launch_fill(c->facc[0], c->L.nf, 0.0, c->stream));
+    c->fa = 0;
+    c->fw = -1;
     c->cur = 0;
     c->step = k;
     c->base = k;
@@ -327,10 +367,13 @@ lbm_status do_reset(lbm_ctx* c) {
     return start_from_slot(c, 0);
 }
 
-lbm_status window_end(lbm_ctx* c, double* accbuf, double* part, double out[3]) {
+// Window sums of the samples into accbuf[0..2] and to the host; for the
+// wake objective the window value comes from the accumulated u_bar (wake).
+lbm_status window_end(lbm_ctx* c, double* accbuf, double* part, double out[3], const double* wake = nullptr) {
     const Layout& L = c->L;
     const double wgt = (double)c->cfg.sample_every / c->cfg.window_len;
     HIPCHK(launch_reduce(part, L.pstride, L.nsamp, c->samples, wgt, accbuf, c->stream));
+    if (wake) HIPCHK(launch_sq_diff_sum(wake, c->uref, L.nf, c->fparts, FACC_PARTS, accbuf, c->stream));
     HIPCHK(hipMemcpyAsync(out, accbuf, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return LBM_OK;
@@ -545,6 +588,7 @@ lbm_status adjoint_window(lbm_ctx* c, const std::vector<void*>& ring, long ns, b
     aa.geo = c->geo;
     aa.ph = c->ph;
     aa.ob = c->ob;
+    aa.ob.fwin = c->fw >= 0 ? c->facc[c->fw] : nullptr;
     aa.stream = c->stream;
     aa.nsteps = 1;
     aa.tile_x = c->adj_tile_x;
@@ -746,6 +790,38 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
     c->ob.out_hi = cfg->sec_out_hi;
     c->ob.inv_nin = 1.0 / ((double)(cfg->sec_in_hi - cfg->sec_in_lo) * cfg->nz);
     c->ob.inv_nout = 1.0 / ((double)(cfg->sec_out_hi - cfg->sec_out_lo) * cfg->nz);
+    c->ob.fx0 = L.fbox[0];
+    c->ob.fx1 = L.fbox[1];
+    c->ob.fy0 = L.fbox[2];
+    c->ob.fy1 = L.fbox[3];
+    c->ob.fz0 = L.fbox[4];
+    c->ob.fz1 = L.fbox[5];
+    c->ob.inv_dref = cfg->monitor == LBM_J_DRAG ? 1.0 / cfg->drag_ref : 0.0;
+    {
+        const int* ab = cfg->objective == LBM_J_WAKE ? L.mbox : L.fbox;
+        c->ob.ax0 = ab[0];
+        c->ob.ay0 = ab[2];
+        c->ob.az0 = ab[4];
+        c->ob.anx = ab[1] - ab[0];
+        c->ob.any = ab[3] - ab[2];
+        c->ob.anz = ab[5] - ab[4];
+        c->ob.nb = (int)L.nb;
+    }
+    c->ob.wgt = (double)cfg->sample_every / cfg->window_len;
+    c->ob.facc = nullptr;
+    c->ob.fwin = nullptr;
+    c->ob.uref = nullptr;
+    c->facc[0] = c->facc[1] = c->facc[2] = nullptr;
+    c->uref = c->fparts = nullptr;
+    c->fa = 0;
+    c->fw = -1;
+    if (L.ncomp) {
+        const size_t fb = align_up((size_t)L.nf * 8);
+        for (int k = 0; k < 3; ++k) c->facc[k] = (double*)at(c, L.off_facc + k * fb);
+        c->uref = (double*)at(c, L.off_facc + 3 * fb);
+        c->fparts = (double*)at(c, L.off_facc + 4 * fb);
+        c->ob.uref = c->uref;
+    }
     c->step = c->base = 0;
     c->cur = 0;
     c->unstable = false;
@@ -776,6 +852,7 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
     INITCHK(hipMemcpyAsync(de, c->rowe.data(), ny, hipMemcpyHostToDevice, c->stream));
     INITCHK(hipMemcpyAsync(du, c->u_in.data(), ny * 8, hipMemcpyHostToDevice, c->stream));
     INITCHK(hipMemcpyAsync(c->gamma, gamma_dev, L.N * 8, hipMemcpyDeviceToDevice, c->stream));
+    if (L.ncomp) INITCHK(launch_fill(c->uref, L.nf, 0.0, c->stream));
     INITCHK(hipStreamSynchronize(c->stream));
 #undef INITCHK
     if ((st = check_gamma(c, c->gamma)) != LBM_OK) return bail(st);
@@ -875,6 +952,7 @@ lbm_status lbm_forward(lbm_ctx* c, long n_steps, int stop_on_converge, lbm_fwd_r
             const long js = (mw == 0 ? W : mw) / dW - 1;
             a.partials = c->partials[0] + js * L.pstride * 3;
         }
+        a.ob.facc = L.ncomp ? c->facc[c->fa] : nullptr;
         if ((st = t_launch(c, n > 1 ? 3 : 0, n)) != LBM_OK) return st;
         HIPCHK(launch_step(a));
         if (mw == 0 && !c->starts.empty()) {
@@ -888,7 +966,15 @@ lbm_status lbm_forward(lbm_ctx* c, long n_steps, int stop_on_converge, lbm_fwd_r
         if (mw == 0) {
             if ((st = t_close(c)) != LBM_OK) return st;
             double r[3];
-            if ((st = window_end(c, c->acc, c->partials[0], r)) != LBM_OK) return st;
+            const bool wake = c->cfg.objective == LBM_J_WAKE;
+            if ((st = window_end(c, c->acc, c->partials[0], r, wake ? c->facc[c->fa] : nullptr)) != LBM_OK)
+                return st;
+            if (L.ncomp) {
+                // this window's field is the adjoint's; the next one starts at zero
+                c->fw = c->fa;
+                c->fa = c->fa == 0 ? 1 : 0;
+                HIPCHK(launch_fill(c->facc[c->fa], L.nf, 0.0, c->stream));
+            }
             double rel = NAN;
             int conv = 0;
             if (!c->M.empty()) criterion(c->M.back(), r[1], c->cfg.eps, rel, conv);
@@ -948,6 +1034,7 @@ lbm_status lbm_adjoint(lbm_ctx* c, int window, double* dJdgamma_dev, double* J_o
     HIPCHK(launch_fill(c->sens, L.N, 0.0, c->stream));
     int cur = 0;
     if ((st = adjoint_window(c, c->ring[g % 2], (g - 1) * W + 1, true, cur)) != LBM_OK) return st;
+    if (c->cfg.objective == LBM_J_DRAG) HIPCHK(launch_box_add(c->sens, c->facc[c->fw], c->geo, c->ob, c->stream));
     HIPCHK(launch_finalize(c->gamma, c->sens, dJdgamma_dev, L.N, c->cfg.s_map, c->cfg.s_q, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     if ((st = t_drain(c)) != LBM_OK) return st;
@@ -997,6 +1084,7 @@ lbm_status lbm_adjoint_full(lbm_ctx* c, double* dJdgamma_dev, double* J_out) {
         // its reverse sweep from the adjoint of the next window's start state
         if ((st = adjoint_window(c, c->ring_rep, (gw - 1) * W + 1, false, cur)) != LBM_OK) return st;
     }
+    if (c->cfg.objective == LBM_J_DRAG) HIPCHK(launch_box_add(c->sens, c->facc[c->fw], c->geo, c->ob, c->stream));
     HIPCHK(launch_finalize(c->gamma, c->sens, dJdgamma_dev, L.N, c->cfg.s_map, c->cfg.s_q, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     if ((st = t_drain(c)) != LBM_OK) return st;
@@ -1020,6 +1108,10 @@ lbm_status lbm_window_replay(lbm_ctx* c, const double* gamma_dev, double* J_out)
     HIPCHK(launch_aux(ca));
     StepLaunch a = step_args(c);
     a.s = c->s_rep;
+    if (L.ncomp) {
+        HIPCHK(launch_fill(c->facc[2], L.nf, 0.0, c->stream));
+        a.ob.facc = c->facc[2];
+    }
     int cur = 0;
     for (long m0 = 0; m0 < W;) {
         const long n = plan_launch(c, m0, dW, W, W - m0, false);
@@ -1034,9 +1126,28 @@ lbm_status lbm_window_replay(lbm_ctx* c, const double* gamma_dev, double* J_out)
         m0 = m;
     }
     double r[3];
-    if ((st = window_end(c, c->acc + 4, c->partials[1], r)) != LBM_OK) return st;
+    if ((st = window_end(c, c->acc + 4, c->partials[1], r,
+                         c->cfg.objective == LBM_J_WAKE ? c->facc[2] : nullptr)) != LBM_OK)
+        return st;
     if (r[2] > 0.0) return fail(LBM_E_UNSTABLE, "replay became unstable");
     if (J_out) *J_out = r[0];
+    return LBM_OK;
+}
+
+lbm_status lbm_set_wake_reference(lbm_ctx* c, const double* u_ref_dev) {
+    if (!c || !u_ref_dev) return fail(LBM_E_INVALID, "NULL argument");
+    if (c->cfg.objective != LBM_J_WAKE) return fail(LBM_E_STATE, "the objective is not LBM_J_WAKE");
+    HIPCHK(hipMemcpyAsync(c->uref, u_ref_dev, (size_t)c->L.nf * 8, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_wake_mean_velocity(lbm_ctx* c, double* u_bar_dev) {
+    if (!c || !u_bar_dev) return fail(LBM_E_INVALID, "NULL argument");
+    if (c->cfg.objective != LBM_J_WAKE) return fail(LBM_E_STATE, "the objective is not LBM_J_WAKE");
+    if (last_window(c) == 0 || c->fw < 0) return fail(LBM_E_STATE, "no completed window");
+    HIPCHK(hipMemcpyAsync(u_bar_dev, c->facc[c->fw], (size_t)c->L.nf * 8, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
     return LBM_OK;
 }
 

@@ -35,13 +35,39 @@ struct Phys {
     double c2;                 // C_s^2 (filter width 1)
 };
 
-// Objective / monitor description (per-node contributions).
+// Objective / monitor description (per-node contributions). Kinds: 0
+// pressure drop, 1 dissipation + pressure drop, 2 drag (objective: the drag
+// force over the force box; monitor: C_d = drag * inv_dref), 3 wake
+// recovery (objective only).
 struct Obj {
-    int obj, mon;              // 0: pressure drop, 1: dissipation + pressure drop
+    int obj, mon;
     int in_x, in_lo, in_hi;
     int out_x, out_lo, out_hi;
     double inv_nin, inv_nout;  // 1 / section node counts
+    int fx0, fx1, fy0, fy1, fz0, fz1;   // force box, half-open
+    double inv_dref;           // 1 / (rho_0 u_0^2 L_ref / 2)
+    // window field accumulator: 2 dD/ds per force-box node (drag) or the
+    // velocity components per measurement-box node (wake), FP64, component
+    // planes of nb values over the box [ax0, ax0 + anx) x [ay0, ay0 + any)
+    // x [az0, az0 + nb / (anx * any)), x fastest
+    int ax0, ay0, az0, anx, any, anz, nb;
+    double wgt;                // dW / |W|
+    double* facc;              // forward / replay accumulation (null: none)
+    const double* fwin;        // the objective window's accumulation (adjoint)
+    const double* uref;        // wake reference mean velocity on the box
 };
+
+__device__ __forceinline__ bool in_force_box(const Obj& ob, int x, int y, int z) {
+    return x >= ob.fx0 && x < ob.fx1 && y >= ob.fy0 && y < ob.fy1 && z >= ob.fz0 && z < ob.fz1;
+}
+
+// Index of node (x, y, z) in the accumulator box, or -1 outside it.
+__device__ __forceinline__ int acc_index(const Obj& ob, int x, int y, int z) {
+    const int i = x - ob.ax0, j = y - ob.ay0, k = z - ob.az0;
+    if ((unsigned)i >= (unsigned)ob.anx || (unsigned)j >= (unsigned)ob.any || (unsigned)k >= (unsigned)ob.anz)
+        return -1;
+    return (k * ob.any + j) * ob.anx + i;
+}
 
 // q = floor(n / d) through an FP64 product (exact to within one for
 // n < 2^31), corrected once.

@@ -55,18 +55,35 @@ __device__ __forceinline__ void block_sum(double v[NC], double* out) {
 }
 
 // Per-node objective and monitor contributions on the post-boundary state
-// f^k: the pressure drop c_s^2 (mean_in rho - mean_out rho) written with
-// drho (the constant cancels), plus the node dissipation when asked for.
+// f^k with bounce-back fraction s: the pressure drop c_s^2 (mean_in rho -
+// mean_out rho) written with drho (the constant cancels), the node
+// dissipation, and the drag 2 s j_x (the collision keeps j, the fluid-solid
+// term removes 2 s j from the fluid) over the force box. The window field
+// accumulator receives dW/|W| times 2 j_x (drag: the explicit dD/ds) or u
+// (wake) on its box.
 template <class L, class T>
-__device__ __forceinline__ void node_samples(const Obj& ob, int x, int y, const Moments<L, T>& m,
+__device__ __forceinline__ void node_samples(const Obj& ob, int x, int y, int z, T s, const Moments<L, T>& m,
                                              double v[3]) {
     double dp = 0.0;
     if (x == ob.in_x && y >= ob.in_lo && y < ob.in_hi) dp += (1.0 / 3.0) * (double)m.drho * ob.inv_nin;
     if (x == ob.out_x && y >= ob.out_lo && y < ob.out_hi) dp -= (1.0 / 3.0) * (double)m.drho * ob.inv_nout;
     double diss = 0.0;
     if (ob.obj == 1 || ob.mon == 1) diss = (double)dissipation<L, T>(m);
-    v[0] = dp + (ob.obj == 1 ? diss : 0.0);
-    v[1] = dp + (ob.mon == 1 ? diss : 0.0);
+    double drag = 0.0;
+    if ((ob.obj == 2 || ob.mon == 2) && in_force_box(ob, x, y, z)) drag = 2.0 * (double)s * (double)m.j[0];
+    v[0] = (ob.obj <= 1 ? dp : 0.0) + (ob.obj == 1 ? diss : 0.0) + (ob.obj == 2 ? drag : 0.0);
+    v[1] = (ob.mon <= 1 ? dp : 0.0) + (ob.mon == 1 ? diss : 0.0) + (ob.mon == 2 ? drag * ob.inv_dref : 0.0);
+    if (ob.facc) {
+        const int i = acc_index(ob, x, y, z);
+        if (i >= 0) {
+            if (ob.obj == 2) {
+                ob.facc[i] += ob.wgt * 2.0 * (double)m.j[0];
+            } else {
+#pragma unroll
+                for (int p = 0; p < L::D; ++p) ob.facc[p * ob.nb + i] += ob.wgt * (double)(m.j[p] * m.irho);
+            }
+        }
+    }
     T uu = 0;
 #pragma unroll
     for (int p = 0; p < L::D; ++p) uu += m.j[p] * m.j[p];
@@ -114,9 +131,10 @@ __global__ __launch_bounds__(BLOCK) void k_step(const S* __restrict__ gin, S* __
         }
         Moments<L, T> m;
         moments<L, T>(h, ph, m);
-        if (SAMPLE) node_samples<L, T>(ob, x, y, m, v);
+        const T s = sfield[n];
+        if (SAMPLE) node_samples<L, T>(ob, x, y, z, s, m, v);
         T out[L::Q];
-        collide<L, T>(m, sfield[n], out);
+        collide<L, T>(m, s, out);
 #pragma unroll
         for (int a = 0; a < L::Q; ++a) plane(gout, a, g.N)[(unsigned)n] = (S)out[a];
     }
@@ -487,7 +505,7 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
             moments<L, T>(h, ph, mo);
             if (SAMPLE) {
                 double vv[3];
-                node_samples<L, T>(ob, c.x, c.y, mo, vv);
+                node_samples<L, T>(ob, c.x, c.y, 0, sbuf[c.cell], mo, vv);
                 v[0] += vv[0];
                 v[1] += vv[1];
                 v[2] += vv[2];
@@ -784,14 +802,15 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
                 }
                 Moments<L, T> mo;
                 moments<L, T>(h, ph, mo);
+                const T sc = sring[s0 * psz + c.cell];
                 if (SAMPLE && v2[u]) {
                     double vv[3];
-                    node_samples<L, T>(ob, c.x, c.y, mo, vv);
+                    node_samples<L, T>(ob, c.x, c.y, z, sc, mo, vv);
                     v[0] += vv[0];
                     v[1] += vv[1];
                     v[2] += vv[2];
                 }
-                collide<L, T>(mo, sring[s0 * psz + c.cell], out[u]);
+                collide<L, T>(mo, sc, out[u]);
             }
         }
 #pragma unroll
@@ -915,16 +934,35 @@ __global__ __launch_bounds__(BLOCK) void k_import(const double* __restrict__ f, 
     for (int a = 0; a < L::Q; ++a) plane(pre, a, g.N)[(unsigned)n] = (S)(plane(f, a, g.N)[(unsigned)n] - L::w[a]);
 }
 
-// Sampled-objective source on the adjoint moments of node (x, y): the
-// pressure-drop sections and, for the dissipation objective, its gradient.
+// Sampled-objective source on the adjoint moments of node (x, y, z) with
+// bounce-back fraction s, weighted src_w: the pressure-drop sections and the
+// dissipation gradient; the drag 2 s j_x (d/dj_x = 2 s); the wake term
+// sum_M |u_bar - u_ref|^2, whose derivative with respect to one sample's u
+// is a = 2 (u_bar - u_ref), with d u / d j = 1 / rho, d u / d rho = -u / rho.
 template <class L, class T>
-__device__ __forceinline__ void adjoint_source(const Obj& ob, const Phys& ph, int x, int y, const Moments<L, T>& m,
-                                               double src_w, MomentGrad<L, T>& gr) {
-    T dp = 0;
-    if (x == ob.in_x && y >= ob.in_lo && y < ob.in_hi) dp += (T)((1.0 / 3.0) * ob.inv_nin * src_w);
-    if (x == ob.out_x && y >= ob.out_lo && y < ob.out_hi) dp -= (T)((1.0 / 3.0) * ob.inv_nout * src_w);
-    gr.gr += dp;
-    if (ob.obj == 1) dissipation_adjoint<L, T>(m, ph, (T)src_w, gr);
+__device__ __forceinline__ void adjoint_source(const Obj& ob, const Phys& ph, int x, int y, int z, T s,
+                                               const Moments<L, T>& m, double src_w, MomentGrad<L, T>& gr) {
+    if (ob.obj <= 1) {
+        T dp = 0;
+        if (x == ob.in_x && y >= ob.in_lo && y < ob.in_hi) dp += (T)((1.0 / 3.0) * ob.inv_nin * src_w);
+        if (x == ob.out_x && y >= ob.out_lo && y < ob.out_hi) dp -= (T)((1.0 / 3.0) * ob.inv_nout * src_w);
+        gr.gr += dp;
+        if (ob.obj == 1) dissipation_adjoint<L, T>(m, ph, (T)src_w, gr);
+    } else if (ob.obj == 2) {
+        if (in_force_box(ob, x, y, z)) gr.gj[0] += (T)(2.0 * src_w) * s;
+    } else {
+        const int i = acc_index(ob, x, y, z);
+        if (i >= 0) {
+            T au = 0;
+#pragma unroll
+            for (int p = 0; p < L::D; ++p) {
+                const T a = (T)(2.0 * src_w * (ob.fwin[p * ob.nb + i] - ob.uref[p * ob.nb + i]));
+                gr.gj[p] += a * m.irho;
+                au += a * m.j[p];
+            }
+            gr.gr -= au * m.irho * m.irho;
+        }
+    }
 }
 
 // Adjoint step for transition k (f^{k-1} -> f^k), reverse order.
@@ -964,6 +1002,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(const A* __restrict__ nu_in, 
     for (int p = 0; p < L::D; ++p) gr.gj[p] = 0;
 #pragma unroll
     for (int k = 0; k < Sym<L::D>::K; ++k) gr.GP[k] = 0;
+    const T s = sfield[n];
     if (!SEED) {
         T kap[L::Q];
         const int N = g.N;
@@ -997,11 +1036,10 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(const A* __restrict__ nu_in, 
                 else kap[a] = (T)0;
             }
         }
-        const T s = sfield[n];
         const T ds = collide_adjoint<L, T>(m, ph, s, kap, gr);
         sens[n] += (double)ds;
     }
-    if (src_w != 0.0) adjoint_source<L, T>(ob, ph, x, y, m, src_w, gr);
+    if (src_w != 0.0) adjoint_source<L, T>(ob, ph, x, y, z, s, m, src_w, gr);
     T mu[L::Q];
     expand<L, T>(m, gr, mu);
     if (oc) zou_he_adjoint<L, T>(g, oc, y, mu);
@@ -1115,7 +1153,7 @@ __global__ __launch_bounds__(TB) void k_adjoint_tb(const A* __restrict__ nu_in, 
                 else if (!last) sacc[o] += (double)ds;
                 else sens[c.n] += sacc[o] + (double)ds;
             }
-            if (src_w != 0.0) adjoint_source<L, T>(ob, ph, c.x, c.y, m, src_w, gr);
+            if (src_w != 0.0) adjoint_source<L, T>(ob, ph, c.x, c.y, 0, s, m, src_w, gr);
             T mu[L::Q];
             expand<L, T>(m, gr, mu);
             if (oc) zou_he_adjoint_rows<L, T>(oc, u0, mu);
@@ -1291,7 +1329,8 @@ __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in,
         buf_ld(rsens, live ? (unsigned)n * 8u : BUF_OOB, sold);
     };
     // one adjoint node update: pre-state h (post-boundary), kappa -> mu, ds
-    auto update = [&](T (&h)[L::Q], const T (&kap)[L::Q], T s, int oc, T u0, int x, int y, double w, T (&mu)[L::Q]) {
+    auto update = [&](T (&h)[L::Q], const T (&kap)[L::Q], T s, int oc, T u0, int x, int y, int z, double w,
+                      T (&mu)[L::Q]) {
         Moments<L, T> m;
         moments<L, T>(h, ph, m);
         MomentGrad<L, T> gr;
@@ -1301,7 +1340,7 @@ __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in,
 #pragma unroll
         for (int q = 0; q < Sym<L::D>::K; ++q) gr.GP[q] = 0;
         const T ds = collide_adjoint<L, T>(m, ph, s, kap, gr);
-        if (w != 0.0) adjoint_source<L, T>(ob, ph, x, y, m, w, gr);
+        if (w != 0.0) adjoint_source<L, T>(ob, ph, x, y, z, s, m, w, gr);
         expand<L, T>(m, gr, mu);
         if (oc) zou_he_adjoint_rows<L, T>(oc, u0, mu);
         return ds;
@@ -1320,7 +1359,7 @@ __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in,
             kap[a] = (T)nk[a];
         }
         if (oc) zou_he_rows<L, T>(oc, u1, d0, h);
-        const T ds = update(h, kap, s1, oc, u1, c1.x, c1.y, w1, mu);
+        const T ds = update(h, kap, s1, oc, u1, c1.x, c1.y, z, w1, mu);
         A* dst = ring + slots[1] * L::Q * psz;
 #pragma unroll
         for (int a = 0; a < L::Q; ++a) dst[a * psz + c1.cell] = (A)mu[a];
@@ -1366,7 +1405,7 @@ __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in,
                 kap[a] = (T)ring[off[a] + c2.cell];
             }
             if (oc) zou_he_rows<L, T>(oc, u2, d0, h);
-            const T ds = update(h, kap, sring[s0 * psz + c2.cell], oc, u2, c2.x, c2.y, w2, mu);
+            const T ds = update(h, kap, sring[s0 * psz + c2.cell], oc, u2, c2.x, c2.y, z, w2, mu);
             snew = (sold + dsring[s0 * psz + c2.cell]) + (double)ds;
         }
         const bool live = ok && v2;
@@ -1451,6 +1490,36 @@ __global__ __launch_bounds__(BLOCK) void k_finalize(const double* __restrict__ g
 __global__ __launch_bounds__(BLOCK) void k_fill(double* __restrict__ p, long n, double v) {
     const long i = (long)blockIdx.x * BLOCK + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// Block partials of sum (a - b)^2 (each block strides over the values).
+__global__ __launch_bounds__(BLOCK) void k_sq_diff_parts(const double* __restrict__ a, const double* __restrict__ b,
+                                                         long n, double* __restrict__ parts) {
+    double v[1] = {0.0};
+    for (long i = (long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long)gridDim.x * BLOCK) {
+        const double d = a[i] - b[i];
+        v[0] += d * d;
+    }
+    block_sum<1>(v, parts + blockIdx.x);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_sum_parts(const double* __restrict__ parts, int nparts,
+                                                     double* __restrict__ out) {
+    double v[1] = {0.0};
+    for (int i = (int)threadIdx.x; i < nparts; i += BLOCK) v[0] += parts[i];
+    block_sum<1>(v, out);
+}
+
+// sens[node] += field[i], i the node's index in the accumulator box.
+__global__ __launch_bounds__(BLOCK) void k_box_add(double* __restrict__ sens, const double* __restrict__ field,
+                                                   Geo g, Obj ob) {
+    const int i = (int)(blockIdx.x * BLOCK + threadIdx.x);
+    if (i >= ob.nb) return;
+    const int x = ob.ax0 + i % ob.anx;
+    const int r = i / ob.anx;
+    const int y = ob.ay0 + r % ob.any;
+    const int z = ob.az0 + r / ob.any;
+    sens[((long)z * g.ny + y) * g.nx + x] += field[i];
 }
 
 __global__ __launch_bounds__(BLOCK) void k_copy_bytes(const unsigned int* __restrict__ a,
@@ -1723,6 +1792,21 @@ hipError_t launch_finalize(const double* gamma, const double* sens, double* out,
 
 hipError_t launch_fill(double* p, long n, double v, hipStream_t stream) {
     hipLaunchKernelGGL(k_fill, grid_for(n), dim3(BLOCK), 0, stream, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_sq_diff_sum(const double* a, const double* b, long n, double* parts, int nparts, double* out,
+                              hipStream_t stream) {
+    long nblk = (n + BLOCK - 1) / BLOCK;
+    if (nblk > nparts) nblk = nparts;
+    if (nblk < 1) nblk = 1;
+    hipLaunchKernelGGL(k_sq_diff_parts, dim3((unsigned)nblk), dim3(BLOCK), 0, stream, a, b, n, parts);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(BLOCK), 0, stream, parts, (int)nblk, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_box_add(double* sens, const double* field, const Geo& g, const Obj& ob, hipStream_t stream) {
+    hipLaunchKernelGGL(k_box_add, grid_for(ob.nb), dim3(BLOCK), 0, stream, sens, field, g, ob);
     return hipGetLastError();
 }
 

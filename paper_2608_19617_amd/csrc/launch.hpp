@@ -94,6 +94,12 @@ hipError_t launch_reduce(const double* partials, long nblocks, int nsamples, dou
 hipError_t launch_finalize(const double* gamma, const double* sens, double* out, long N, int map, double q,
                            hipStream_t stream);
 hipError_t launch_fill(double* p, long n, double v, hipStream_t stream);
+// out[0] = sum_i (a_i - b_i)^2 over n values: nparts block partials into
+// parts (nparts doubles), then one block sums them in a fixed order.
+hipError_t launch_sq_diff_sum(const double* a, const double* b, long n, double* parts, int nparts, double* out,
+                              hipStream_t stream);
+// sens[node] += field[i] over the nodes of the objective's accumulator box.
+hipError_t launch_box_add(double* sens, const double* field, const Geo& g, const Obj& ob, hipStream_t stream);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
 long blocks_for(long n);
 int tb_plane(int nsteps, int tile_x, int tile_y, size_t lsize, size_t vsize, size_t extra);

@@ -10,7 +10,8 @@ import torch
 from . import binding as B
 
 _PREC = {"f64": B.LBM_F64, "f32": B.LBM_F32, "f16s": B.LBM_F16S}
-_OBJ = {"dp": B.LBM_J_PRESSURE_DROP, "diss_dp": B.LBM_J_DISSIPATION_PLUS_DP}
+_OBJ = {"dp": B.LBM_J_PRESSURE_DROP, "diss_dp": B.LBM_J_DISSIPATION_PLUS_DP, "drag": B.LBM_J_DRAG,
+        "wake": B.LBM_J_WAKE, "cd": B.LBM_J_DRAG}
 _SMAP = {"linear": B.LBM_S_LINEAR, "paper": B.LBM_S_PAPER}
 
 
@@ -62,7 +63,19 @@ def make_config(w, prec="f32"):
     c.sec_out_x, c.sec_out_lo, c.sec_out_hi = (int(v) for v in w.sec_out)
     c.ckpt_every = int(w.ckpt_every)
     c.full_history = int(bool(getattr(w, "full_history", False)))
+    for name in ("force_box", "meas_box"):
+        box = getattr(w, name, None)
+        flat = [0, 0, 0, 0, 0, 0] if box is None else [int(v) for b in box for v in b]
+        flat += [0, 1] if len(flat) == 4 else []
+        getattr(c, name)[:] = flat
+    c.drag_ref = float(getattr(w, "drag_ref", 1.0))
     return c, (west, east, u_in)
+
+
+def box_shape(w, name):
+    """Node counts per axis of a Workload box (None: the whole grid)."""
+    box = getattr(w, name, None)
+    return tuple(w.shape) if box is None else tuple(hi - lo for lo, hi in box)
 
 
 def workspace_bytes(w, prec="f32"):
@@ -174,6 +187,26 @@ class Solver:
         J = ctypes.c_double(0.0)
         B.check(B.lib.lbm_window_replay(self._ctx, ctypes.c_void_p(g.data_ptr()), ctypes.byref(J)))
         return J.value
+
+    def set_wake_reference(self, u_ref):
+        """Wake objective: reference mean velocity on the measurement box,
+        indexed [component, x, y(, z)] relative to the box corner."""
+        shp = (self.D,) + box_shape(self.w, "meas_box")
+        u = np.asarray(u_ref.detach().cpu() if isinstance(u_ref, torch.Tensor) else u_ref, np.float64)
+        assert u.shape == shp, (u.shape, shp)
+        flat = np.concatenate([to_device_order(u[p]) for p in range(self.D)])
+        t = torch.from_numpy(flat).to(self.device)
+        B.check(B.lib.lbm_set_wake_reference(self._ctx, ctypes.c_void_p(t.data_ptr())))
+
+    def wake_mean_velocity(self):
+        """Wake objective: u_bar of the last completed window on the
+        measurement box, numpy [component, x, y(, z)]."""
+        box = box_shape(self.w, "meas_box")
+        nb = int(np.prod(box))
+        t = torch.empty(self.D * nb, dtype=torch.float64, device=self.device)
+        B.check(B.lib.lbm_wake_mean_velocity(self._ctx, ctypes.c_void_p(t.data_ptr())))
+        flat = t.cpu().numpy()
+        return np.stack([from_device_order(flat[p * nb:(p + 1) * nb], box) for p in range(self.D)])
 
     def get_state(self):
         """(f [alpha, x, y(, z)] FP64 numpy, step)."""

@@ -38,8 +38,8 @@ class Workload:
     rho_out: float = 1.0
     rho_init: float = 1.0
     u_init_mode: int = 1             # 1: u = (u_in(y), 0) everywhere at t = 0
-    objective: str = "dp"            # "dp" or "diss_dp"
-    monitor: str = "dp"
+    objective: str = "dp"            # "dp", "diss_dp", "drag" or "wake"
+    monitor: str = "dp"              # "dp", "diss_dp" or "cd"
     sec_in: tuple = (0, 0, 1)        # (x, ylo, yhi)
     sec_out: tuple = (0, 0, 1)
     window_len: int = 100
@@ -51,6 +51,9 @@ class Workload:
     s_map: str = "linear"
     s_q: float = 0.1
     full_history: bool = False       # keep every window's start state (full-time adjoint)
+    force_box: tuple = None          # ((x0, x1), (y0, y1)[, (z0, z1)]) of the drag; None: whole grid
+    drag_ref: float = 1.0            # rho_0 u_0^2 L_ref / 2 of the C_d monitor
+    meas_box: tuple = None           # measurement region of the wake objective; None: whole grid
     notes: dict = field(default_factory=dict)
 
     @property

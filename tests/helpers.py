@@ -6,8 +6,9 @@ import numpy as np
 from oracle import forward as fw
 
 
-def oracle_problem(w, window_len=None, sample_every=None):
-    """oracle.forward.Problem for a Workload (same inputs, independent code)."""
+def oracle_problem(w, window_len=None, sample_every=None, u_ref=None):
+    """oracle.forward.Problem for a Workload (same inputs, independent code);
+    u_ref: the wake objective's reference mean velocity (None: zero)."""
     d = len(w.shape)
     u_init = np.zeros((d,) + tuple(w.shape))
     if w.u_init_mode == 1:
@@ -21,7 +22,12 @@ def oracle_problem(w, window_len=None, sample_every=None):
         sec_in=w.sec_in, sec_out=w.sec_out,
         window_len=w.window_len if window_len is None else window_len,
         sample_every=w.sample_every if sample_every is None else sample_every,
-        eps=w.eps, max_windows=w.max_windows, rho_init=w.rho_init, u_init=u_init)
+        eps=w.eps, max_windows=w.max_windows, rho_init=w.rho_init, u_init=u_init,
+        force_box=_box3(w.force_box, d), drag_ref=w.drag_ref, meas_box=_box3(w.meas_box, d), u_ref=u_ref)
+
+
+def _box3(box, d):
+    return None if box is None else tuple(tuple(b) for b in box)[:d]
 
 
 def rel_l2(a, b):
