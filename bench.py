@@ -46,15 +46,18 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 / FP16S comparison")
     ap.add_argument("--max-windows", type=int, default=20)
+    ap.add_argument("--case", default="", help="paper suite: run only the workloads whose name contains this")
     ap.add_argument("--counters", action="store_true",
                     help="run one window and its adjoint of the workload plus a 256 MiB device copy "
                          "(for rocprofv3 --pmc byte counters) and exit")
-    ap.add_argument("--suite", choices=["hbm", "design", "fulltime"], default=None,
+    ap.add_argument("--suite", choices=["hbm", "design", "fulltime", "paper"], default=None,
                     help="hbm: rooflines of the forward, recompute and adjoint kernels on grids far "
                          "larger than the caches (one JSON line per configuration) instead of the "
                          "benchmark step; design: timings of the design update (filter + projection, "
                          "chain rule, volume-constrained step); fulltime: one optimisation iteration "
-                         "with the window adjoint against the full-time adjoint (time and storage)")
+                         "with the window adjoint against the full-time adjoint (time and storage); "
+                         "paper: the paper's cylinder-drag and wake-recovery examples at their sizes "
+                         "with their objectives and the finite-difference check of the adjoint")
     return ap.parse_args()
 
 
@@ -405,6 +408,100 @@ def fulltime_suite(args, torch):
         print(json.dumps(line), flush=True)
 
 
+def _timed(torch, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def _fd_check(torch, sv, gamma, g_adj, points, J):
+    """Forward-difference sensitivities of the representative window (each
+    perturbed design replayed from the window's start state) at the given
+    nodes, for perturbations 1e-3 and 1e-4, against the adjoint."""
+    import numpy as np
+    out = {}
+    adj = np.array([g_adj[p] for p in points])
+    for h in (1e-3, 1e-4):
+        fd = []
+        t0 = time.perf_counter()
+        for p in points:
+            gp = gamma.copy()
+            gp[p] += h
+            fd.append((sv.replay(gp) - J) / h)
+        torch.cuda.synchronize()
+        fd = np.array(fd)
+        top = float(np.max(np.abs(fd)))
+        out[f"h={h:g}"] = {"max_err_over_max_fd": float(np.max(np.abs(adj - fd)) / top) if top > 0 else None,
+                           "rel_l2": float(np.linalg.norm(adj - fd) / np.linalg.norm(fd)) if top > 0 else None,
+                           "replay_s": round(time.perf_counter() - t0, 3)}
+    return out
+
+
+def paper_suite(args, torch):
+    """The paper's own examples at their sizes and with their objectives:
+    the flow around a cylinder (200 x 100, radius 8, Re 3.2 / 12.8 / 51.2;
+    drag objective over the domain, C_d monitor, |W| = 5000, dW = 50,
+    eps = 1e-3, at most 20 windows) with the 60-point finite-difference check
+    of the adjoint (gamma + 1e-3 and + 1e-4 at the 60 nodes downstream of the
+    cylinder centre on its axis, the representative window replayed for
+    each), and the wake-flow recovery (200 x 50; Re 60 with d = 10 and Re 72
+    with d = 12): a reference run with the cylinder gives u_ref on M, then
+    the wake objective from the constant initial design, with a 20-point
+    check inside the design domain. FP64 for the checks (skipped with
+    --no-compare); the forward run and the adjoint are also timed in the
+    requested precision."""
+    import numpy as np
+    from paper_2608_19617_amd import workloads as W
+    from paper_2608_19617_amd.solver import Solver
+    cases = [("cylinder_drag", re, W.cylinder_drag(re)) for re in (3.2, 12.8, 51.2)]
+    for re, d, lmeas in ((60.0, 10, 33), (72.0, 12, 39)):
+        cases.append(("wake_recovery", re, W.wake_recovery(re, d, lmeas)))
+    for kind, re, w in cases:
+        if args.case not in w.name:
+            continue
+        u_ref, ref_line = None, None
+        if kind == "wake_recovery":
+            wr = W.wake_recovery(re, w.notes["d"], w.notes["l_measure"], reference=True)
+            sv = Solver(wr, "f64")
+            rep, t = _timed(torch, lambda: sv.forward(wr.n_steps, stop_on_converge=True))
+            u_ref = sv.wake_mean_velocity()
+            ref_line = {"windows": rep["windows_done"], "converged": rep["converged"], "C_d": rep["monitor"],
+                        "forward_s": round(t, 3)}
+            sv.close()
+        line = {"suite": "paper", "workload": w.name, "grid": list(w.shape), "re": re, "tau": w.tau,
+                "objective": w.objective, "window_len": w.window_len, "sample_every": w.sample_every,
+                "eps": w.eps}
+        if ref_line:
+            line["reference_run"] = ref_line
+        for prec in ("f64", args.prec) if args.prec != "f64" else ("f64",):
+            sv = Solver(w, prec)
+            if u_ref is not None:
+                sv.set_wake_reference(u_ref)
+            rep, t_fwd = _timed(torch, lambda: sv.forward(w.n_steps, stop_on_converge=True))
+            (g, J), t_adj = _timed(torch, lambda: sv.adjoint())
+            steps = rep["steps_done"]
+            res = {"windows": rep["windows_done"], "converged": rep["converged"], "C_d": rep["monitor"],
+                   "J": J, "forward_s": round(t_fwd, 4),
+                   "forward_MLUPS": round(steps * w.nodes / t_fwd / 1e6, 1),
+                   "adjoint_s": round(t_adj, 4),
+                   "adjoint_MLUPS": round(w.window_len * w.nodes / t_adj / 1e6, 1)}
+            if prec == "f64" and not args.no_compare:
+                gh = g.cpu().numpy()
+                if kind == "cylinder_drag":
+                    cx, cy = w.notes["center"]
+                    pts = [(cx + 1 + k, cy) for k in range(60)]
+                else:
+                    (x0, x1), (y0, y1) = w.force_box
+                    rng = np.random.default_rng(0)
+                    pts = [(int(x), int(y)) for x, y in zip(rng.integers(x0, x1, 20), rng.integers(y0, y1, 20))]
+                res["fd_check"] = dict(points=len(pts), **_fd_check(torch, sv, w.gamma, gh, pts, J))
+            line[prec] = res
+            sv.close()
+        print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -426,6 +523,9 @@ def main():
         return
     if args.suite == "fulltime":
         fulltime_suite(args, torch)
+        return
+    if args.suite == "paper":
+        paper_suite(args, torch)
         return
     from paper_2608_19617_amd import workloads as W
     from paper_2608_19617_amd.solver import Solver

@@ -202,6 +202,67 @@ def cylinder_3d(nx=384, ny=128, nz=128, radius=16, center=(96, 64), u_max=0.05, 
     return w
 
 
+def cylinder_drag(re=51.2, nx=200, ny=100, radius=8, u0=0.05, window_len=5000, sample_every=50, eps=1e-3,
+                  max_windows=20, ckpt_every=250, c_smag=0.1, s_q=0.1):
+    """Flow around a circular cylinder (Sec. "Flow around a circular
+    cylinder"): a 200 x 100 lattice with a cylinder of radius 8 at its centre
+    holding the initial design phi = 0.5 (gamma = 0.5 inside, fluid
+    outside); uniform inlet speed u0 on the west face, pressure outlet, walls
+    top and bottom; tau from Re = u0 2r / nu. Drag objective over the whole
+    domain with the C_d monitor (L_ref = 2r, rho_0 = 1) and the paper's
+    interpolation g(phi; q); |W| = 5000, dW = 50, eps = 1e-3."""
+    cx, cy = nx // 2, ny // 2
+    X, Y = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    g = np.where(np.hypot(X - cx, Y - cy) <= radius, 0.5, 0.0)
+    u = np.full(ny, u0)
+    u[0] = u[-1] = 0.0
+    return Workload(
+        name=f"cylinder_drag_{nx}x{ny}_re{re:g}", shape=(nx, ny), tau=tau_from_re(u0, 2 * radius, re),
+        c_smag=c_smag, gamma=g, west=_rows(ny, 1, ny - 1, VELOCITY), east=_rows(ny, 1, ny - 1, PRESSURE),
+        u_in=u, objective="drag", monitor="cd", drag_ref=0.5 * u0 ** 2 * 2 * radius, s_map="paper", s_q=s_q,
+        sec_in=(0, 1, ny - 1), sec_out=(nx - 1, 1, ny - 1),
+        window_len=window_len, sample_every=sample_every, ckpt_every=ckpt_every,
+        eps=eps, max_windows=max_windows, n_steps=max_windows * window_len,
+        notes={"center": (cx, cy), "radius": radius, "re": re})
+
+
+def wake_recovery(re=60.0, d=10, l_measure=33, nx=200, ny=50, l_m=6, u0=0.05, window_len=6000,
+                  sample_every=20, eps=5e-4, max_windows=20, ckpt_every=300, c_smag=0.1, s_q=0.1,
+                  reference=False, v0=0.5):
+    """Wake-flow recovery (Sec. "Wake flow recovery", Table wfr): a 200 x 50
+    channel with walls and a uniform inlet; the design domain D is 3d x 2d,
+    centred across the channel, its front edge at x = 3d; the measurement
+    square M of L_M x L_M nodes is centred across the channel with its centre
+    L_measure downstream of D's back edge. reference=True places a cylinder
+    of diameter d at the centre of D (gamma = 1 inside), the flow whose
+    window-mean velocity on M is u_ref; otherwise D holds the constant
+    initial design gamma = v0. Wake objective on M, C_d monitor of the drag
+    over D (L_ref = d)."""
+    x0, x1 = 3 * d, 6 * d
+    y0, y1 = ny // 2 - d, ny // 2 + d
+    xm = x1 + l_measure - l_m // 2
+    ym = ny // 2 - l_m // 2
+    X, Y = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    if reference:
+        cx, cy = (x0 + x1 - 1) / 2.0, (y0 + y1 - 1) / 2.0
+        g = np.where(np.hypot(X - cx, Y - cy) <= d / 2.0, 1.0, 0.0)
+    else:
+        g = np.zeros((nx, ny))
+        g[x0:x1, y0:y1] = v0
+    u = np.full(ny, u0)
+    u[0] = u[-1] = 0.0
+    box = ((x0, x1), (y0, y1))
+    return Workload(
+        name=f"wake_recovery_{nx}x{ny}_re{re:g}" + ("_reference" if reference else ""), shape=(nx, ny),
+        tau=tau_from_re(u0, d, re), c_smag=c_smag, gamma=g, west=_rows(ny, 1, ny - 1, VELOCITY),
+        east=_rows(ny, 1, ny - 1, PRESSURE), u_in=u, objective="wake", monitor="cd",
+        force_box=box, drag_ref=0.5 * u0 ** 2 * d, meas_box=((xm, xm + l_m), (ym, ym + l_m)),
+        s_map="paper", s_q=s_q, sec_in=(0, 1, ny - 1), sec_out=(nx - 1, 1, ny - 1),
+        window_len=window_len, sample_every=sample_every, ckpt_every=ckpt_every,
+        eps=eps, max_windows=max_windows, n_steps=max_windows * window_len,
+        notes={"design_box": box, "re": re, "d": d, "l_measure": l_measure})
+
+
 def random_design(shape, seed, lo=0.0, hi=1.0):
     """Uniform random design field (test input)."""
     return np.random.default_rng(seed).uniform(lo, hi, size=shape)

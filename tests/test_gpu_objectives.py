@@ -315,3 +315,26 @@ def test_drag_and_wake_full_size(Solver):
         rep = sv.forward(6)
         assert abs(rep["J_eff"] - want) <= 1e-4 * abs(want), (kind, rep["J_eff"], want)
         sv.close()
+
+
+@pytest.mark.parametrize("kind", ["cylinder_drag", "wake_recovery"])
+def test_paper_examples_full_size(Solver, kind):
+    """The paper's examples at their sizes with the paper's interpolation
+    and their objectives (cylinder 200 x 100 at Re 51.2: drag with the C_d
+    monitor; wake 200 x 50 at Re 60: wake value on the 6 x 6 measurement
+    square): one 20-step window (dW = 5) from a random state, FP64 J, C_d
+    mean and dJ/dgamma against the oracle, FP32 within its tolerances."""
+    if kind == "cylinder_drag":
+        w = W.cylinder_drag(51.2, window_len=20, sample_every=5, ckpt_every=10)
+    else:
+        w = W.wake_recovery(60.0, window_len=20, sample_every=5, ckpt_every=10)
+    w.max_windows = 1
+    u_ref = _u_ref(w, 13) if kind == "wake_recovery" else None
+    prob = oracle_problem(w)
+    f0 = random_start_state(prob, seed=36)
+    _, J_o, M_o, _, g_o = _oracle_window(w, f0, u_ref)
+    for prec, tol_J, tol_g in (("f64", 1e-12, 1e-11), ("f32", 1e-5, 1e-4)):
+        rep, _, g, J = _gpu_window(Solver, w, prec, f0, u_ref)
+        assert abs(J - J_o) <= tol_J * abs(J_o), (prec, J, J_o)
+        assert abs(rep["monitor"] - M_o) <= tol_J * abs(M_o)
+        assert rel_l2(g, g_o) <= tol_g, (prec, rel_l2(g, g_o))

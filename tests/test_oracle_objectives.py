@@ -191,3 +191,33 @@ def test_objective_full_gradient_complex_step(k):
         gc[idx] += 1j * h
         cs[idx] = fw.window_objective(prob, gc, start(gc)).imag / h
     assert np.linalg.norm(g - cs) <= 1e-12 * np.linalg.norm(cs)
+
+
+def test_paper_example_workloads():
+    """The paper's examples as built for the solver: the cylinder of radius 8
+    at the centre of 200 x 100 with phi = 0.5 inside and tau from Re on the
+    diameter; the wake case's design domain 3d x 2d centred across 200 x 50,
+    the L_M x L_M measurement square centred across the channel with its
+    centre L_measure downstream of the design domain; both give valid
+    oracle problems (boxes inside the grid, u_ref shape)."""
+    from paper_2608_19617_amd import workloads as W
+    from helpers import oracle_problem
+    w = W.cylinder_drag(12.8)
+    assert w.shape == (200, 100) and w.objective == "drag" and w.monitor == "cd"
+    assert np.count_nonzero(w.gamma) == np.count_nonzero(
+        np.hypot(*np.meshgrid(np.arange(200) - 100, np.arange(100) - 50, indexing="ij")) <= 8)
+    assert set(np.unique(w.gamma)) == {0.0, 0.5}
+    assert w.tau == pytest.approx(0.5 + 3 * 0.05 * 16 / 12.8)
+    oracle_problem(w)
+    for re, d, lmeas in ((60.0, 10, 33), (72.0, 12, 39)):
+        w = W.wake_recovery(re, d, lmeas)
+        (x0, x1), (y0, y1) = w.force_box
+        assert (x1 - x0, y1 - y0) == (3 * d, 2 * d) and y0 + y1 == 50
+        (mx0, mx1), (my0, my1) = w.meas_box
+        assert (mx1 - mx0, my1 - my0) == (6, 6) and my0 + my1 == 50
+        assert (mx0 + mx1) / 2 - x1 == lmeas
+        assert np.all(w.gamma[x0:x1, y0:y1] == 0.5) and w.gamma.sum() == 0.5 * 6 * d * d
+        ref = W.wake_recovery(re, d, lmeas, reference=True)
+        assert ref.gamma[:x0].sum() == 0 and ref.gamma[x1:].sum() == 0
+        assert ref.gamma.sum() == pytest.approx(np.pi * d * d / 4, rel=0.15)
+        oracle_problem(w, u_ref=np.zeros((2, 6, 6)))
