@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--counters", action="store_true",
                     help="run one window and its adjoint of the workload plus a 256 MiB device copy "
                          "(for rocprofv3 --pmc byte counters) and exit")
+    ap.add_argument("--counters-case", choices=["bfs", "cyl3d"], default="bfs",
+                    help="workload of --counters: the benchmark's backward-facing step (bfs) or 40 "
+                         "forward steps of the D3Q19 channel 384x128x128 in its default launches (cyl3d)")
     ap.add_argument("--suite", choices=["hbm", "design", "fulltime", "paper"], default=None,
                     help="hbm: rooflines of the forward, recompute and adjoint kernels on grids far "
                          "larger than the caches (one JSON line per configuration) instead of the "
@@ -62,15 +65,21 @@ def parse():
 
 
 def counters_run(args, torch):
-    """Workload for hardware-counter runs: one window forward and its adjoint,
+    """Workload for hardware-counter runs: one window forward and its adjoint
+    of the benchmark workload (or 40 forward steps of the D3Q19 channel),
     then a plain 256 MiB device-to-device copy whose byte counters calibrate
     FETCH_SIZE / WRITE_SIZE."""
     from paper_2608_19617_amd import workloads as W
     from paper_2608_19617_amd.solver import Solver
-    w = W.backward_facing_step(max_windows=args.max_windows)
-    sv = Solver(w, args.prec)
-    sv.forward(w.window_len)
-    sv.adjoint()
+    if args.counters_case == "cyl3d":
+        w = W.cylinder_3d(window_len=40, sample_every=20, ckpt_every=20, n_windows=1)
+        sv = Solver(w, args.prec)
+        sv.forward(w.window_len)
+    else:
+        w = W.backward_facing_step(max_windows=args.max_windows)
+        sv = Solver(w, args.prec)
+        sv.forward(w.window_len)
+        sv.adjoint()
     sv.close()
     a = torch.ones(256 * 2 ** 20 // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
