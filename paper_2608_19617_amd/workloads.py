@@ -263,6 +263,48 @@ def wake_recovery(re=60.0, d=10, l_measure=33, nx=200, ny=50, l_m=6, u0=0.05, wi
         notes={"design_box": box, "re": re, "d": d, "l_measure": l_measure})
 
 
+def u_bend_paper(re=400.0, u0=0.05, window_len=20000, sample_every=20, eps=0.05, max_windows=20,
+                 ckpt_every=500, c_smag=0.1, s_q=0.1):
+    """U-bend of the paper (Sec. "U-bend flow", Table ubend_parameters): Re 400
+    on 240 x 192 (L_d = 24, L_f = L_m = L_p = 48, L_r = 144) or Re 750 on
+    300 x 240 (30, 60, 60, 60, 180). The inlet leg (rows L_d + L_f + L_m ..
+    L_y - L_d) and the outlet leg (rows L_d .. L_d + L_f) open on the west
+    face and are joined beyond x = L_r by a half annulus of radii L_m / 2 and
+    L_m / 2 + L_f around (L_r, L_y / 2). Design domain: x >= L_r, and the box
+    L_p <= x < L_r, y < L_d + L_f. Initial design: the channel is fluid,
+    the rest solid (gamma = 1, also off the design domain). Uniform inlet u0,
+    west pressure outlet, walls elsewhere; J = window mean of the pressure
+    drop between sections at x = L_p across the legs; tau from Re on L_f."""
+    if re == 750.0:
+        nx, ny, ld, lf, lm, lp, lr = 300, 240, 30, 60, 60, 60, 180
+    else:
+        nx, ny, ld, lf, lm, lp, lr = 240, 192, 24, 48, 48, 48, 144
+    X, Y = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    out_lo, out_hi = ld, ld + lf
+    in_lo, in_hi = ld + lf + lm, ny - ld
+    yc = ny / 2.0 - 0.5
+    r = np.hypot(X - lr, Y - yc)
+    chan = np.zeros((nx, ny), bool)
+    chan[:lr, in_lo:in_hi] = True
+    chan[:lr, out_lo:out_hi] = True
+    chan |= (X >= lr) & (r >= lm / 2.0) & (r <= lm / 2.0 + lf)
+    design = (X >= lr) | ((X >= lp) & (Y < out_hi))
+    g = np.where(chan, 0.0, 1.0)
+    west = np.zeros(ny, np.int64)
+    west[in_lo:in_hi] = VELOCITY
+    west[out_lo:out_hi] = PRESSURE
+    u = np.zeros(ny)
+    u[in_lo:in_hi] = u0
+    return Workload(
+        name=f"u_bend_paper_{nx}x{ny}_re{re:g}", shape=(nx, ny), tau=tau_from_re(u0, lf, re), c_smag=c_smag,
+        gamma=g, west=west, east=np.zeros(ny, np.int64), u_in=u, u_init_mode=0,
+        objective="dp", monitor="dp", s_map="paper", s_q=s_q,
+        sec_in=(lp, in_lo, in_hi), sec_out=(lp, out_lo, out_hi),
+        window_len=window_len, sample_every=sample_every, ckpt_every=ckpt_every,
+        eps=eps, max_windows=max_windows, n_steps=max_windows * window_len,
+        notes={"design_mask": design, "re": re, "l_f": lf})
+
+
 def random_design(shape, seed, lo=0.0, hi=1.0):
     """Uniform random design field (test input)."""
     return np.random.default_rng(seed).uniform(lo, hi, size=shape)

@@ -317,17 +317,21 @@ def test_drag_and_wake_full_size(Solver):
         sv.close()
 
 
-@pytest.mark.parametrize("kind", ["cylinder_drag", "wake_recovery"])
+@pytest.mark.parametrize("kind", ["cylinder_drag", "wake_recovery", "u_bend_paper"])
 def test_paper_examples_full_size(Solver, kind):
     """The paper's examples at their sizes with the paper's interpolation
     and their objectives (cylinder 200 x 100 at Re 51.2: drag with the C_d
     monitor; wake 200 x 50 at Re 60: wake value on the 6 x 6 measurement
-    square): one 20-step window (dW = 5) from a random state, FP64 J, C_d
-    mean and dJ/dgamma against the oracle, FP32 within its tolerances."""
+    square; U-bend 240 x 192 at Re 400: pressure drop between the legs, west
+    inlet and west outlet): one 20-step window (dW = 5) from a random state,
+    FP64 J, monitor mean and dJ/dgamma against the oracle, FP32 within its
+    tolerances."""
     if kind == "cylinder_drag":
         w = W.cylinder_drag(51.2, window_len=20, sample_every=5, ckpt_every=10)
-    else:
+    elif kind == "wake_recovery":
         w = W.wake_recovery(60.0, window_len=20, sample_every=5, ckpt_every=10)
+    else:
+        w = W.u_bend_paper(400.0, window_len=20, sample_every=5, ckpt_every=10)
     w.max_windows = 1
     u_ref = _u_ref(w, 13) if kind == "wake_recovery" else None
     prob = oracle_problem(w)
@@ -338,3 +342,33 @@ def test_paper_examples_full_size(Solver, kind):
         assert abs(J - J_o) <= tol_J * abs(J_o), (prec, J, J_o)
         assert abs(rep["monitor"] - M_o) <= tol_J * abs(M_o)
         assert rel_l2(g, g_o) <= tol_g, (prec, rel_l2(g, g_o))
+
+
+def test_u_bend_fd_on_a_developed_flow(Solver):
+    """The paper's U-bend at Re 400 (240 x 192, FP64) after 60 000 steps from
+    rest: dJ/dgamma of a 2000-step window against forward differences
+    (h = 1e-6, the window replayed from its start state) at eight nodes
+    within three nodes of the channel, fluid and solid, <= 1e-3 of the
+    largest. (Over the paper's 20 000-step window this flow answers a
+    perturbation of 1e-4 nonlinearly, so a finite-difference check needs the
+    shorter window or a much smaller step.)"""
+    from scipy.ndimage import binary_dilation
+    w = W.u_bend_paper(400.0)
+    w.window_len, w.ckpt_every, w.eps, w.max_windows = 2000, 500, -1.0, 30
+    sv = Solver(w, "f64")
+    sv.forward(30 * w.window_len)
+    g, J = sv.adjoint()
+    g = g.cpu().numpy()
+    near = binary_dilation(w.gamma == 0.0, iterations=3) & w.notes["design_mask"]
+    cand = np.argwhere(near)
+    pts = [tuple(int(v) for v in cand[i]) for i in np.random.default_rng(0).choice(len(cand), 8, replace=False)]
+    adj, fd = [], []
+    for p in pts:
+        gp = w.gamma.copy()
+        h = 1e-6 if gp[p] + 1e-6 <= 1.0 else -1e-6
+        gp[p] += h
+        fd.append((sv.replay(gp) - J) / h)
+        adj.append(g[p])
+    sv.close()
+    adj, fd = np.array(adj), np.array(fd)
+    assert np.max(np.abs(adj - fd)) <= 1e-3 * np.max(np.abs(fd)), (adj, fd)

@@ -221,3 +221,26 @@ def test_paper_example_workloads():
         assert ref.gamma[:x0].sum() == 0 and ref.gamma[x1:].sum() == 0
         assert ref.gamma.sum() == pytest.approx(np.pi * d * d / 4, rel=0.15)
         oracle_problem(w, u_ref=np.zeros((2, 6, 6)))
+
+
+def test_paper_u_bend_workloads():
+    """The paper's U-bend as built for the solver: the legs of width L_f on
+    the west face L_m apart with margins L_d (Table ubend_parameters), the
+    half annulus beyond L_r, the design domain's initial solid fraction
+    inside the paper's bounds 0.52 <= V <= 0.65, the pressure sections at
+    x = L_p across the legs; a valid oracle problem."""
+    from paper_2608_19617_amd import workloads as W
+    from helpers import oracle_problem
+    for re, (nx, ny, ld, lf, lm, lp, lr) in ((400.0, (240, 192, 24, 48, 48, 48, 144)),
+                                             (750.0, (300, 240, 30, 60, 60, 60, 180))):
+        w = W.u_bend_paper(re)
+        assert w.shape == (nx, ny)
+        assert list(np.nonzero(w.west == fw.VELOCITY)[0]) == list(range(ld + lf + lm, ny - ld))
+        assert list(np.nonzero(w.west == fw.PRESSURE)[0]) == list(range(ld, ld + lf))
+        assert np.all(w.gamma[:lr, ld + lf + lm:ny - ld] == 0) and np.all(w.gamma[:lr, ld:ld + lf] == 0)
+        assert np.all(w.gamma[:lr, ld + lf:ld + lf + lm] == 1) and np.all(w.gamma[:, :ld] == 1)
+        D = w.notes["design_mask"]
+        assert 0.52 <= w.gamma[D].mean() <= 0.65
+        assert w.sec_in == (lp, ld + lf + lm, ny - ld) and w.sec_out == (lp, ld, ld + lf)
+        assert w.tau == pytest.approx(0.5 + 3 * 0.05 * lf / re)
+        oracle_problem(w)
