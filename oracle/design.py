@@ -23,8 +23,10 @@ Conventions (readings of the paper, listed in the design notes):
   dx~_i/dx_j = w_ij / W_i, W_i = sum_{k in D} w_ik (j in D).
 * Update (the MMA stand-in): with the gradients scaled by their largest
   magnitude on D, x(lam) = clip(x - m (g_J + lam g_V), max(0, x - m),
-  min(1, x + m)) on D; lam = 0 if V(gamma(x(0))) <= V_max, otherwise the
-  smallest lam (to bisection accuracy) with V(gamma(x(lam))) <= V_max.
+  min(1, x + m)) on D; lam = 0 if V_min <= V(gamma(x(0))) <= V_max,
+  otherwise the lam of smallest magnitude (to bisection accuracy) that
+  brings V(gamma(x(lam))) back inside: lam > 0 above V_max, lam < 0 below
+  V_min (the paper's constraints are two-sided).
 
 parity: filter, projection and volume are pinned by closed forms and
 invariants, the transposes by the dot-product identity and by complex-step
@@ -133,10 +135,13 @@ def _scaled(g, mask):
     return g / top if top > 0 else np.zeros_like(g)
 
 
-def update(x, dJdx, dVdx, mask, base, radius, beta, eta, move, vmax, iters=60):
-    """One projected-gradient step under the volume constraint: returns
-    (x_new, V(x_new), lam). Bracketing doubles lam from 1; bisection then
-    halves the bracket `iters` times and keeps its feasible end."""
+def update(x, dJdx, dVdx, mask, base, radius, beta, eta, move, vmax, vmin=0.0, iters=60):
+    """One projected-gradient step under vmin <= V <= vmax: returns
+    (x_new, V(x_new), lam). V(x(lam)) does not increase with lam (dV/dx >= 0),
+    so lam = 0 when V(x(0)) lies in the bounds, lam > 0 when it exceeds vmax
+    and lam < 0 when it is below vmin. Bracketing doubles |lam| from 1;
+    bisection then halves the bracket `iters` times and keeps its feasible
+    end."""
     sJ, sV = _scaled(dJdx, mask), _scaled(dVdx, mask)
     lo = np.maximum(0.0, x - move)
     hi = np.minimum(1.0, x + move)
@@ -148,16 +153,20 @@ def update(x, dJdx, dVdx, mask, base, radius, beta, eta, move, vmax, iters=60):
         return volume_fraction(physical_field(trial(lam), mask, base, radius, beta, eta), mask)
 
     v0 = vol(0.0)
-    if v0 <= vmax:
+    if vmin <= v0 <= vmax:
         return trial(0.0), v0, 0.0
-    a, b = 0.0, 1.0
+    if v0 > vmax:
+        sign, feasible = 1.0, (lambda v: v <= vmax)
+    else:
+        sign, feasible = -1.0, (lambda v: v >= vmin)
+    a, b = 0.0, sign
     for _ in range(60):
-        if vol(b) <= vmax:
+        if feasible(vol(b)):
             break
         a, b = b, 2.0 * b
     for _ in range(iters):
         c = 0.5 * (a + b)
-        if vol(c) <= vmax:
+        if feasible(vol(c)):
             b = c
         else:
             a = c

@@ -166,3 +166,34 @@ def test_update_bounds_and_volume_constraint(rng):
     xn2, v2, lam2 = dz.update(x, gJ, gV, mask, base, r, beta, eta, move, 1.0)
     assert lam2 == 0.0
     np.testing.assert_array_equal(xn2, np.where(mask, np.clip(x - move * sJ, lo, hi), x))
+
+
+def test_update_lower_volume_bound(rng):
+    """Two-sided constraint: a sensitivity that favours fluid (the descent
+    step alone removes volume) below V_min gives lam < 0 and V >= V_min with
+    the multiplier of smallest magnitude (a slightly smaller |lam| violates
+    it); inside the bounds the step is the plain clipped descent step (lam = 0);
+    V(x(lam)) does not increase with lam."""
+    shape = (20, 16)
+    mask = rng.random(shape) < 0.7
+    base = np.zeros(shape)
+    x = np.clip(0.5 + 0.2 * rng.standard_normal(shape), 0.0, 1.0)
+    r, beta, eta, move = 4.0, 4.0, 0.5, 0.1
+    gJ, gV = dz.chain(x, mask, r, beta, eta, 1.0 + 0.3 * rng.standard_normal(shape))
+    v_start = dz.volume_fraction(dz.physical_field(x, mask, base, r, beta, eta), mask)
+    vmin = v_start + 0.01
+    xn, v, lam = dz.update(x, gJ, gV, mask, base, r, beta, eta, move, 1.0, vmin=vmin)
+    assert lam < 0 and v >= vmin
+    assert np.all(np.abs(xn - x)[mask] <= move + 1e-15) and np.all(xn[~mask] == x[~mask])
+    sJ, sV = gJ / np.max(np.abs(gJ[mask])), gV / np.max(np.abs(gV[mask]))
+    lo, hi = np.maximum(0, x - move), np.minimum(1, x + move)
+
+    def vol(l):
+        t = np.where(mask, np.clip(x - move * (sJ + l * sV), lo, hi), x)
+        return dz.volume_fraction(dz.physical_field(t, mask, base, r, beta, eta), mask)
+
+    assert vol(0.999 * lam) < vmin
+    lams = np.linspace(-4, 4, 17)
+    assert np.all(np.diff([vol(l) for l in lams]) <= 1e-15)
+    xn2, v2, lam2 = dz.update(x, gJ, gV, mask, base, r, beta, eta, move, 1.0, vmin=0.0)
+    assert lam2 == 0.0 and v2 < v_start
