@@ -53,14 +53,16 @@ def parse():
     ap.add_argument("--counters-case", choices=["bfs", "cyl3d"], default="bfs",
                     help="workload of --counters: the benchmark's backward-facing step (bfs) or 40 "
                          "forward steps of the D3Q19 channel 384x128x128 in its default launches (cyl3d)")
-    ap.add_argument("--suite", choices=["hbm", "design", "fulltime", "paper"], default=None,
+    ap.add_argument("--suite", choices=["hbm", "design", "fulltime", "paper", "optimize"], default=None,
                     help="hbm: rooflines of the forward, recompute and adjoint kernels on grids far "
                          "larger than the caches (one JSON line per configuration) instead of the "
                          "benchmark step; design: timings of the design update (filter + projection, "
                          "chain rule, volume-constrained step); fulltime: one optimisation iteration "
                          "with the window adjoint against the full-time adjoint (time and storage); "
                          "paper: the paper's cylinder-drag and wake-recovery examples at their sizes "
-                         "with their objectives and the finite-difference check of the adjoint")
+                         "with their objectives and the finite-difference check of the adjoint; "
+                         "optimize: the paper's cylinder drag minimisation (Re 51.2) for up to 60 "
+                         "iterations of forward windows, adjoint and design update")
     return ap.parse_args()
 
 
@@ -527,6 +529,56 @@ def paper_suite(args, torch):
         print(json.dumps(line), flush=True)
 
 
+def optimize_suite(args, torch):
+    """The optimisation loop on the paper's cylinder example (Re 51.2,
+    200 x 100, |W| = 5000, dW = 50, eps = 1e-3): minimise the drag under
+    0.014 <= V <= 0.016 over the design domain 10 <= x < 190, 5 <= y < 95
+    (the initial design x = 0.5 inside the cylinder of radius 8, 0
+    elsewhere; filter radius 4, beta from 2 doubling every 10 iterations to
+    16, move limit 0.2, eps_o = 0.005, at most 60 iterations). Each iteration
+    runs the forward windows from t = 0 to the criterion, the adjoint over
+    the representative window and the volume-constrained design update, all
+    on the GPU. Reports the time per iteration and the objective and volume
+    history."""
+    import numpy as np
+    from paper_2608_19617_amd import workloads as W
+    from paper_2608_19617_amd.optimize import optimize
+    w = W.cylinder_drag(51.2)
+    cx, cy = w.notes["center"]
+    mask = np.zeros(w.shape, dtype=bool)
+    mask[10:190, 5:95] = True
+    X, Y = np.meshgrid(np.arange(w.shape[0]), np.arange(w.shape[1]), indexing="ij")
+    x0 = np.where(np.hypot(X - cx, Y - cy) <= w.notes["radius"], 0.5, 0.0)
+    base = np.zeros(w.shape)
+    for prec in ("f32", "f64") if args.prec != "f64" else ("f64",):
+        times = []
+        last = [time.perf_counter()]
+
+        def tick(rec):
+            torch.cuda.synchronize()
+            now = time.perf_counter()
+            times.append(now - last[0])
+            last[0] = now
+
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        last[0] = t0
+        x, hist = optimize(w, mask, x0, prec=prec, radius=4.0, eta=0.5, beta=2.0, beta_max=16.0, beta_every=10,
+                           move=0.2, vmin=0.014, vmax=0.016, n_max=60, eps_o=0.005, base=base, callback=tick)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        J = [h["J"] for h in hist]
+        V = [h["V"] for h in hist]
+        line = {"suite": "optimize", "workload": "cylinder drag 200x100 Re 51.2, 0.014 <= V <= 0.016",
+                "dtype": prec, "iterations": len(hist), "total_s": round(total, 3),
+                "s_per_iteration": round(total / max(len(hist), 1), 4),
+                "median_iteration_s": round(float(np.median(times)), 4) if times else None,
+                "J_first": J[0], "J_last": J[-1], "J_min": min(J), "V_first": V[0], "V_last": V[-1],
+                "windows_last": hist[-1]["w_eff"], "J_history": [round(j, 6) for j in J],
+                "V_history": [round(v, 5) for v in V]}
+        print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -551,6 +603,9 @@ def main():
         return
     if args.suite == "paper":
         paper_suite(args, torch)
+        return
+    if args.suite == "optimize":
+        optimize_suite(args, torch)
         return
     from paper_2608_19617_amd import workloads as W
     from paper_2608_19617_amd.solver import Solver

@@ -18,9 +18,13 @@
  *     of 1 - phi over the design domain).
  *   - Update: with g_J = dJ/dx and g_V = dV/dx each divided by its largest
  *     magnitude on D, x(lam) = clip(x - move (g_J + lam g_V),
- *     max(0, x - move), min(1, x + move)) on D (x elsewhere); lam = 0 when
- *     V(x(0)) <= vmax, else the smallest lam with V(x(lam)) <= vmax, found
- *     by doubling from 1 and 60 bisection halvings (the feasible end).
+ *     max(0, x - move), min(1, x + move)) on D (x elsewhere); V(x(lam))
+ *     does not increase with lam. lam = 0 when vmin <= V(x(0)) <= vmax;
+ *     above vmax the smallest lam > 0 with V(x(lam)) <= vmax, below vmin the
+ *     lam < 0 of smallest magnitude with V(x(lam)) >= vmin, each found by
+ *     doubling |lam| from 1 and 60 bisection halvings (the feasible end).
+ *     If the move limit keeps V out of the bounds, the most feasible step
+ *     after 60 doublings is returned.
  *
  * Memory and streams: the caller owns all device memory (the workspace
  * sized by lbm_design_workspace_bytes and every field). All work goes to
@@ -67,13 +71,13 @@ lbm_status lbm_design_map(lbm_design* d, const double* x_dev, double beta, doubl
 lbm_status lbm_design_chain(lbm_design* d, const double* x_dev, double beta, double eta,
                             const double* dJdgamma_dev, double* dJdx_dev, double* dVdx_dev);
 
-/* Projected-gradient step under V <= vmax (see the conventions above):
- * x_new_dev (device FP64, N; may not alias x_dev) receives x(lam); volume
- * and lambda (host, may be NULL) receive V(x(lam)) and lam. Requires
- * 0 < move <= 1 and 0 <= vmax <= 1. */
+/* Projected-gradient step under vmin <= V <= vmax (see the conventions
+ * above): x_new_dev (device FP64, N; may not alias x_dev) receives x(lam);
+ * volume and lambda (host, may be NULL) receive V(x(lam)) and lam. Requires
+ * 0 < move <= 1 and 0 <= vmin <= vmax <= 1. */
 lbm_status lbm_design_update(lbm_design* d, const double* x_dev, const double* dJdx_dev,
-                             const double* dVdx_dev, double beta, double eta, double move, double vmax,
-                             double* x_new_dev, double* volume, double* lambda);
+                             const double* dVdx_dev, double beta, double eta, double move, double vmin,
+                             double vmax, double* x_new_dev, double* volume, double* lambda);
 
 /* Frees the host-side context. */
 void lbm_design_destroy(lbm_design* d);

@@ -99,7 +99,7 @@ def _load():
     lib.lbm_design_init.argtypes = [i, i, i, dbl, P, P, P, ctypes.c_size_t, P, ctypes.POINTER(P)]
     lib.lbm_design_map.argtypes = [P, P, dbl, dbl, P, D]
     lib.lbm_design_chain.argtypes = [P, P, dbl, dbl, P, P, P]
-    lib.lbm_design_update.argtypes = [P, P, P, P, dbl, dbl, dbl, dbl, P, D, D]
+    lib.lbm_design_update.argtypes = [P, P, P, P, dbl, dbl, dbl, dbl, dbl, P, D, D]
     lib.lbm_design_destroy.argtypes = [P]
     lib.lbm_design_destroy.restype = None
     for name in EXPORTED:

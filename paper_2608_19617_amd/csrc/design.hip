@@ -448,13 +448,13 @@ lbm_status lbm_design_chain(lbm_design* d, const double* x_dev, double beta, dou
 }
 
 lbm_status lbm_design_update(lbm_design* d, const double* x_dev, const double* dJdx_dev,
-                             const double* dVdx_dev, double beta, double eta, double move, double vmax,
-                             double* x_new_dev, double* volume, double* lambda) {
+                             const double* dVdx_dev, double beta, double eta, double move, double vmin,
+                             double vmax, double* x_new_dev, double* volume, double* lambda) {
     if (!d || !x_dev || !dJdx_dev || !dVdx_dev || !x_new_dev) return dz_bad("NULL argument");
     if (x_new_dev == x_dev) return dz_bad("x_new_dev must not alias x_dev");
     if (!dz_params(beta, eta)) return dz_bad("need beta > 0 and 0 < eta < 1");
-    if (!(move > 0.0 && move <= 1.0) || !(vmax >= 0.0 && vmax <= 1.0))
-        return dz_bad("need 0 < move <= 1 and 0 <= vmax <= 1");
+    if (!(move > 0.0 && move <= 1.0) || !(vmin >= 0.0 && vmin <= vmax && vmax <= 1.0))
+        return dz_bad("need 0 < move <= 1 and 0 <= vmin <= vmax <= 1");
     const DzLayout& L = d->L;
     double* part = d->fld(L.partials);
     double* top = d->fld(L.scal) + 2;
@@ -474,11 +474,14 @@ lbm_status lbm_design_update(lbm_design* d, const double* x_dev, const double* d
     double* xt = d->fld(L.xtrial);
     lbm_status st = vol_at(0.0, xt, &v);
     if (st != LBM_OK) return st;
-    if (v > vmax) {
-        double a = 0.0, b = 1.0, vb = 0.0;
+    if (v > vmax || v < vmin) {
+        // V(x(lam)) does not increase with lam: lam > 0 above vmax, < 0 below vmin
+        const bool above = v > vmax;
+        auto feasible = [&](double vv) { return above ? vv <= vmax : vv >= vmin; };
+        double a = 0.0, b = above ? 1.0 : -1.0, vb = 0.0;
         for (int k = 0; k < 60; ++k) {
             if ((st = vol_at(b, xt, &vb)) != LBM_OK) return st;
-            if (vb <= vmax) break;
+            if (feasible(vb)) break;
             a = b;
             b = 2.0 * b;
         }
@@ -486,7 +489,7 @@ lbm_status lbm_design_update(lbm_design* d, const double* x_dev, const double* d
             const double c = 0.5 * (a + b);
             double vc = 0.0;
             if ((st = vol_at(c, xt, &vc)) != LBM_OK) return st;
-            if (vc <= vmax) b = c;
+            if (feasible(vc)) b = c;
             else a = c;
         }
         lam = b;

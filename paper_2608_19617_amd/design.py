@@ -67,14 +67,15 @@ class Design:
                                        ctypes.c_void_p(gV.data_ptr())))
         return self._field(gJ), self._field(gV)
 
-    def update(self, x, dJdx, dVdx, beta, eta, move, vmax):
-        """(x_new [x, y(, z)], volume fraction, multiplier) of one step."""
+    def update(self, x, dJdx, dVdx, beta, eta, move, vmax, vmin=0.0):
+        """(x_new [x, y(, z)], volume fraction, multiplier) of one step under
+        vmin <= V <= vmax."""
         xf, gJ, gV = self._flat(x), self._flat(dJdx), self._flat(dVdx)
         xn = torch.empty(self.N, dtype=torch.float64, device=self.device)
         v, lam = ctypes.c_double(0.0), ctypes.c_double(0.0)
         B.check(B.lib.lbm_design_update(self._ctx, ctypes.c_void_p(xf.data_ptr()), ctypes.c_void_p(gJ.data_ptr()),
                                         ctypes.c_void_p(gV.data_ptr()), float(beta), float(eta), float(move),
-                                        float(vmax), ctypes.c_void_p(xn.data_ptr()), ctypes.byref(v),
+                                        float(vmin), float(vmax), ctypes.c_void_p(xn.data_ptr()), ctypes.byref(v),
                                         ctypes.byref(lam)))
         return self._field(xn), v.value, lam.value
 

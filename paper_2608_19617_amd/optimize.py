@@ -17,7 +17,7 @@ from .solver import Solver
 
 
 def optimize(w, mask, x0, prec="f32", radius=4.0, eta=0.5, beta=2.0, beta_max=16.0, beta_every=10,
-             move=0.2, vmax=0.5, n_max=50, eps_o=1e-3, base=None, callback=None):
+             move=0.2, vmax=0.5, n_max=50, eps_o=1e-3, base=None, callback=None, vmin=0.0):
     """Returns (x, history): the design variables ([x, y(, z)] FP64 torch
     tensor on the GPU) and one record per iteration (J_eff, volume fraction,
     beta, representative window, multiplier). `base` is gamma off the design
@@ -33,7 +33,7 @@ def optimize(w, mask, x0, prec="f32", radius=4.0, eta=0.5, beta=2.0, beta_max=16
             rep = sv.forward(w.max_windows * w.window_len, stop_on_converge=True)
             g, J = sv.adjoint()
             gJ, gV = dz.chain(x, beta, eta, g)
-            x_new, _, lam = dz.update(x, gJ, gV, beta, eta, move, vmax)
+            x_new, _, lam = dz.update(x, gJ, gV, beta, eta, move, vmax, vmin)
             rec = {"iter": m, "J": J, "V": V, "beta": beta, "w_eff": int(rep["w_eff"]), "lam": lam}
             hist.append(rec)
             if callback is not None:

@@ -85,6 +85,30 @@ def test_design_update_matches_oracle(Design, shape, r):
     d.close()
 
 
+@pytest.mark.parametrize("shape,r", CASES[:3], ids=lambda v: str(v))
+def test_design_update_lower_bound_matches_oracle(Design, shape, r):
+    """Two-sided constraint: a sensitivity that favours fluid with V_min above
+    the descent step's volume (negative multiplier), and bounds that the
+    plain step meets (lam = 0), against the oracle."""
+    mask, base, x, _ = _case(shape, 9)
+    d = Design(shape, mask, base, radius=r)
+    beta, eta, move = 4.0, 0.5, 0.1
+    g = 1.0 + 0.3 * np.random.default_rng(10).standard_normal(shape)
+    gJ_o, gV_o = dz.chain(x, mask, r, beta, eta, g)
+    v0 = dz.volume_fraction(dz.physical_field(x, mask, base, r, beta, eta), mask)
+    for vmin, vmax in ((v0 + 0.01, 1.0), (0.0, 1.0)):
+        xn, V, lam = d.update(x, gJ_o, gV_o, beta, eta, move, vmax, vmin)
+        xn_o, V_o, lam_o = dz.update(x, gJ_o, gV_o, mask, base, r, beta, eta, move, vmax, vmin=vmin)
+        assert np.max(np.abs(xn.cpu().numpy() - xn_o)) <= 1e-12
+        assert abs(V - V_o) <= 1e-13
+        assert lam == pytest.approx(lam_o, rel=1e-12, abs=0)
+        if vmin > 0:
+            assert lam < 0 and V >= vmin
+        else:
+            assert lam == 0.0
+    d.close()
+
+
 def test_design_full_size_wake(Design):
     """Cylinder-wake grid 2048 x 512 with a 320 x 160 design window (r = 4):
     physical field, volume and chain rule against the oracle on the whole
@@ -115,9 +139,9 @@ def test_design_errors(Design):
         with pytest.raises(LbmError, match="LBM_E_INVALID"):
             d.map(x, beta, eta)
     gJ, gV = d.chain(x, 2.0, 0.5, g)
-    for move, vmax in ((0.0, 0.5), (0.1, 1.5)):
+    for move, vmax, vmin in ((0.0, 0.5, 0.0), (0.1, 1.5, 0.0), (0.1, 0.4, 0.5), (0.1, 0.5, -0.1)):
         with pytest.raises(LbmError, match="LBM_E_INVALID"):
-            d.update(x, gJ, gV, 2.0, 0.5, move, vmax)
+            d.update(x, gJ, gV, 2.0, 0.5, move, vmax, vmin)
     d.close()
     with pytest.raises(LbmError, match="empty"):
         Design((20, 12), np.zeros((20, 12), bool), base)
