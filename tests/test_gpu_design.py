@@ -181,3 +181,24 @@ def test_optimisation_loop_matches_oracle(Design):
         assert hist[m]["lam"] == pytest.approx(lam, rel=1e-8, abs=1e-12)
         b = min(2 * b, 16.0)
     assert np.max(np.abs(x.cpu().numpy() - xo)) <= 1e-9
+
+
+def test_optimisation_prescribed_window_mode(Design):
+    """optimize(steps=n |W|) (a prescribed window: the last of n windows from
+    t = 0) gives the same iterations as the representative-window mode when
+    the criterion is off and the run is n windows long."""
+    from paper_2608_19617_amd import workloads as W
+    from paper_2608_19617_amd.optimize import optimize
+    w = W.cylinder_channel(nx=48, ny=20, radius=3, center=(14, 10), window_len=12, sample_every=3,
+                           ckpt_every=4, n_windows=2)
+    w.eps = -1.0
+    mask = np.zeros(w.shape, dtype=bool)
+    mask[8:28, 3:17] = True
+    base = np.where(mask, 0.0, w.gamma)
+    x0 = np.where(mask, 0.3, 0.0)
+    kw = dict(prec="f64", radius=2.5, eta=0.5, beta=2.0, beta_every=1, move=0.2, vmax=0.25, n_max=2, eps_o=0.0,
+              base=base)
+    x1, h1 = optimize(w, mask, x0, **kw)
+    x2, h2 = optimize(w, mask, x0, steps=2 * w.window_len, **kw)
+    assert [h["J"] for h in h1] == [h["J"] for h in h2]
+    assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
