@@ -869,7 +869,9 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
             int t = (int)std::lround(std::sqrt((double)L.N / 256.0));
             t = t < 16 ? 16 : (t > 25 ? 25 : t);
             tx = ty = t;
-            nt = cfg->prec == LBM_F64 ? 4 : 10;
+            // FP64 on the smallest tiles: 8 steps (measured 23-26% faster
+            // than 4 on the 200 x 100 and 160 x 64 cylinders)
+            nt = cfg->prec == LBM_F64 ? (t == 16 ? 8 : 4) : 10;
             while (nt > 2 && tb_lds_bytes_prec(nt, tx, ty, cfg->prec) > TB_LDS_MAX) --nt;
         } else if (cfg->prec == LBM_F32) {
             nt = 6;
