@@ -607,6 +607,37 @@ def optimize_suite(args, torch):
         r["reevaluated_vs_representative"] = r["J_reevaluated"] / ref - 1.0
     print(json.dumps({"suite": "optimize", "comparison": "representative vs prescribed windows, Re 51.2",
                       "dtype": args.prec, "runs": runs}), flush=True)
+    # the paper's other two examples: wake recovery (Re 60; u_ref from the
+    # cylinder's converged mean flow; 0.1 <= V <= 0.9; eps_o = 5e-3, at most
+    # 200 iterations) and the U-bend (Re 400; 0.52 <= V <= 0.65; eps_o = 1e-5,
+    # at most 90 iterations)
+    from paper_2608_19617_amd.solver import Solver as _S
+    wr = W.wake_recovery(60.0, 10, 33, reference=True)
+    sv = _S(wr, args.prec)
+    sv.forward(wr.n_steps, stop_on_converge=True)
+    u_ref = sv.wake_mean_velocity()
+    sv.close()
+    ww = W.wake_recovery(60.0, 10, 33)
+    (bx0, bx1), (by0, by1) = ww.force_box
+    wmask = np.zeros(ww.shape, dtype=bool)
+    wmask[bx0:bx1, by0:by1] = True
+    ub = W.u_bend_paper(400.0)
+    for name, wk, m, xi, bs, vmn, vmx, eps_o, nmax, ur in (
+            ("wake recovery 200x50 Re 60, 0.1 <= V <= 0.9", ww, wmask, np.where(wmask, 0.5, 0.0), np.zeros(ww.shape),
+             0.1, 0.9, 5e-3, 200, u_ref),
+            ("U-bend 240x192 Re 400, 0.52 <= V <= 0.65", ub, ub.notes["design_mask"], ub.gamma, ub.gamma,
+             0.52, 0.65, 1e-5, 90, None)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, hist = optimize(wk, m, xi, prec=args.prec, radius=4.0, eta=0.5, beta=2.0, beta_max=16.0, beta_every=10,
+                           move=0.2, vmin=vmn, vmax=vmx, n_max=nmax, eps_o=eps_o, base=bs, u_ref=ur)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        J = [h["J"] for h in hist]
+        print(json.dumps({"suite": "optimize", "workload": name, "dtype": args.prec, "iterations": len(hist),
+                          "total_s": round(total, 3), "s_per_iteration": round(total / len(hist), 4),
+                          "J_first": J[0], "J_last": J[-1], "J_min": min(J), "V_first": hist[0]["V"],
+                          "V_last": hist[-1]["V"], "J_history": [float("%.6g" % j) for j in J]}), flush=True)
 
 
 def main():

@@ -17,16 +17,20 @@ from .solver import Solver
 
 
 def optimize(w, mask, x0, prec="f32", radius=4.0, eta=0.5, beta=2.0, beta_max=16.0, beta_every=10,
-             move=0.2, vmax=0.5, n_max=50, eps_o=1e-3, base=None, callback=None, vmin=0.0, steps=None):
+             move=0.2, vmax=0.5, n_max=50, eps_o=1e-3, base=None, callback=None, vmin=0.0, steps=None,
+             u_ref=None):
     """Returns (x, history): the design variables ([x, y(, z)] FP64 torch
     tensor on the GPU) and one record per iteration (J_eff, volume fraction,
     beta, representative window, multiplier). `base` is gamma off the design
     domain (default: the workload's gamma). steps = None: each iteration runs
     the windows until the consecutive-window test passes (the representative
     window); otherwise a prescribed window: `steps` steps from t = 0 and the
-    last of its windows (steps a multiple of the window length)."""
+    last of its windows (steps a multiple of the window length). u_ref: the
+    reference mean velocity of the wake objective on its measurement box."""
     dz = Design(w.shape, mask, w.gamma if base is None else base, radius)
     sv = Solver(w, prec)
+    if u_ref is not None:
+        sv.set_wake_reference(u_ref)
     x = torch.as_tensor(x0, dtype=torch.float64).to(sv.device)
     hist, J_prev = [], None
     try:
