@@ -157,3 +157,54 @@ def test_design_entry_points_validate_before_any_hip_call(B):
                                  ctypes.byref(out)) == B.LBM_E_INVALID
     assert "workspace" in B.lib.lbm_last_error().decode()
     assert B.lib.lbm_design_map(None, fake, 2.0, 0.5, fake, None) == B.LBM_E_INVALID
+
+
+def test_grid_limits_rejected(B):
+    """Degenerate and maximum sizes: fewer than 3 nodes per axis, nz != 1 in
+    2D, nz < 3 in 3D, and Q * nodes at 2^31 or beyond are rejected; the
+    largest 2D grid below the limit is accepted."""
+    for over in ({"nx": 2}, {"ny": 2}, {"nz": 2}):
+        cfg, keep = _cfg(B)
+        for k, v in over.items():
+            setattr(cfg, k, v)
+        assert _bytes(B, cfg)[0] == B.LBM_E_INVALID, over
+    cfg, keep = _cfg(B)
+    cfg.lattice, cfg.nz = B.LBM_D3Q19, 2
+    assert _bytes(B, cfg)[0] == B.LBM_E_INVALID
+    cfg, keep = _cfg(B)
+    cfg.nx = (2 ** 31) // (9 * cfg.ny) + 1        # 9 nx ny >= 2^31
+    assert _bytes(B, cfg)[0] == B.LBM_E_INVALID
+    cfg.nx = (2 ** 31 - 1) // (9 * cfg.ny)        # just below
+    assert _bytes(B, cfg)[0] == B.LBM_OK
+
+
+def test_objective_configs(B):
+    """The paper's objectives: unknown kinds, the wake as a monitor, boxes
+    outside the grid or empty, and the C_d monitor without drag_ref are
+    rejected; the drag and wake objectives add their window-field
+    accumulators (three fields and the reference over the box) to the
+    workspace."""
+    for obj, mon in ((4, 0), (-1, 0), (0, B.LBM_J_WAKE), (0, 5)):
+        cfg, keep = _cfg(B)
+        cfg.objective, cfg.monitor = obj, mon
+        assert _bytes(B, cfg)[0] == B.LBM_E_INVALID, (obj, mon)
+    for box in ((0, 41, 0, 16, 0, 1), (5, 10, 7, 7, 0, 1), (-1, 5, 0, 5, 0, 1), (5, 10, 0, 17, 0, 1)):
+        for name in ("force_box", "meas_box"):
+            cfg, keep = _cfg(B)
+            getattr(cfg, name)[:] = box
+            assert _bytes(B, cfg)[0] == B.LBM_E_INVALID, (name, box)
+    cfg, keep = _cfg(B)
+    cfg.monitor, cfg.drag_ref = B.LBM_J_DRAG, 0.0
+    assert _bytes(B, cfg)[0] == B.LBM_E_INVALID
+    cfg.drag_ref = 0.5
+    assert _bytes(B, cfg)[0] == B.LBM_OK
+    cfg, keep = _cfg(B)
+    st, base = _bytes(B, cfg)
+    cfg.objective = B.LBM_J_DRAG
+    cfg.force_box[:] = (5, 15, 2, 12, 0, 1)              # 100 nodes, one component
+    st, drag = _bytes(B, cfg)
+    assert st == B.LBM_OK and 4 * 100 * 8 + 1024 * 8 <= drag - base <= 4 * (100 * 8 + 256) + 1024 * 8 + 256
+    cfg.objective = B.LBM_J_WAKE
+    cfg.meas_box[:] = (20, 26, 5, 11, 0, 1)              # 36 nodes, two components
+    st, wake = _bytes(B, cfg)
+    assert st == B.LBM_OK and 4 * 72 * 8 + 1024 * 8 <= wake - base <= 4 * (72 * 8 + 256) + 1024 * 8 + 256
