@@ -31,10 +31,13 @@ HBM_PEAK_GBS = 8000.0
 # of the Q populations in storage precision plus the bounce-back fraction
 # plane in compute precision (boundary kinds come from coordinates).
 FWD_BYTES = {"f64": 9 * 8 * 2 + 8, "f32": 9 * 4 * 2 + 4, "f16s": 9 * 2 * 2 + 4}
-# Adjoint step: adjoint populations read + write, pre-state read, s, FP64
-# sensitivity read-modify-write.
-ADJ_BYTES = {"f64": 9 * 8 * 2 + 9 * 8 + 8 + 16, "f32": 9 * 4 * 2 + 9 * 4 + 4 + 16,
-             "f16s": 9 * 4 * 2 + 9 * 2 + 4 + 16}
+# Adjoint step (D2Q9): adjoint populations read + write (FP64 in FP64 mode,
+# else FP32), the pre-state's moment record read (6 values of the compute
+# type), s, FP64 sensitivity read-modify-write.
+ADJ_BYTES = {"f64": 9 * 8 * 2 + 6 * 8 + 8 + 16, "f32": 9 * 4 * 2 + 6 * 4 + 4 + 16,
+             "f16s": 9 * 4 * 2 + 6 * 4 + 4 + 16}
+# Recompute step (D2Q9): a forward step that also writes the moment record.
+REC_BYTES = {p: FWD_BYTES[p] + 6 * (8 if p == "f64" else 4) for p in FWD_BYTES}
 
 
 def parse():
@@ -270,10 +273,12 @@ def hbm_suite(args, torch):
     for prec in ("f64", "f32", "f16s"):
         w = W.cylinder_wake(nx=8192, ny=2048, radius=128, window_len=500, sample_every=20, ckpt_every=50,
                             max_windows=2)
-        cases.append(("cylinder wake 8192x2048 (C3 x4 per axis)", w, prec, FWD_BYTES[prec], ADJ_BYTES[prec]))
+        cases.append(("cylinder wake 8192x2048 (C3 x4 per axis)", w, prec, FWD_BYTES[prec], ADJ_BYTES[prec],
+                      REC_BYTES[prec]))
     w3 = W.cylinder_3d(window_len=100, sample_every=20, ckpt_every=20, n_windows=2)
-    cases.append(("cylinder 3D 384x128x128 D3Q19", w3, "f32", FWD_BYTES_3D["f32"], ADJ_BYTES_3D["f32"]))
-    for name, w, prec, fb, ab in cases:
+    cases.append(("cylinder 3D 384x128x128 D3Q19", w3, "f32", FWD_BYTES_3D["f32"], ADJ_BYTES_3D["f32"],
+                  FWD_BYTES_3D["f32"]))
+    for name, w, prec, fb, ab, rb in cases:
         sv = Solver(w, prec)
         sv.set_gamma(w.gamma)
         sv.forward(w.window_len)                  # spin-up window
@@ -305,7 +310,8 @@ def hbm_suite(args, torch):
                             "achieved_GBs": round(ab * N / adj_s / 1e9, 1),
                             "frac_of_hbm_peak": round(ab * N / adj_s / 1e9 / HBM_PEAK_GBS, 4)},
                 "recompute": {"steps": int(ta["rec_steps"]), "us_per_step": round(rec_s * 1e6, 3),
-                              "frac_of_hbm_peak": round(fb * N / rec_s / 1e9 / HBM_PEAK_GBS, 4)},
+                              "bytes_per_lup": rb,
+                              "frac_of_hbm_peak": round(rb * N / rec_s / 1e9 / HBM_PEAK_GBS, 4)},
                 "reverse_sweep": {"s": round(t_sweep, 4),
                                   "mlups_per_window_lup": round(N * w.window_len / t_sweep / 1e6, 1)}}
         sv.close()

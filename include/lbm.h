@@ -154,9 +154,11 @@ typedef struct {
 typedef struct lbm_ctx lbm_ctx;
 
 /* Bytes of device workspace that lbm_init needs for this configuration
- * (state ping-pong, two checkpoint rings of |W|/K slots, K recompute slots,
- * adjoint buffers, sample partials; with full_history also max_windows
- * window-start states and a third ring). Validates the configuration. */
+ * (state ping-pong, two checkpoint rings of |W|/K slots, the recompute
+ * slots of a segment: for D2Q9 two states and K - 1 moment records of 6
+ * values per node, for D3Q19 K states; adjoint buffers, sample partials;
+ * with full_history also max_windows window-start states and a third
+ * ring). Validates the configuration. */
 lbm_status lbm_workspace_bytes(const lbm_config* cfg, size_t* bytes);
 
 /* Creates a context. gamma_dev: device FP64 array of N design values in

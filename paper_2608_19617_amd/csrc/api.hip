@@ -41,11 +41,13 @@ struct Layout {
     size_t ss, cs, as;         // bytes per stored / compute / adjoint value
     size_t SB;                 // bytes of one population state
     int R;                     // checkpoint slots per window
-    int nseg;                  // recompute slots
+    int nseg;                  // recompute state slots
+    int nrec;                  // recompute record slots (D2Q9: K - 1, at least 1; D3Q19: 0)
+    size_t RB;                 // bytes of one moment record of all nodes
     long nblocks;
     long pstride;
     int nsamp;                 // samples per window
-    size_t off_G, off_ring, off_seg, off_s, off_srep, off_gamma, off_nu, off_sens, off_part, off_samples,
+    size_t off_G, off_ring, off_seg, off_rec, off_s, off_srep, off_gamma, off_nu, off_sens, off_part, off_samples,
         off_acc, off_roww, off_rowe, off_uin, total;
     int fbox[6], mbox[6];      // force and measurement boxes, resolved
     int ncomp;                 // window-field components: 1 (drag), D (wake), 0
@@ -137,7 +139,12 @@ void layout(const lbm_config* c, Layout& L) {
     L.as = L.cs;
     L.SB = align_up((size_t)L.Q * L.N * L.ss);
     L.R = c->window_len / c->ckpt_every;
-    L.nseg = c->ckpt_every < 2 ? 2 : c->ckpt_every;
+    // D2Q9 segments keep moment records of every recomputed step and two
+    // states for the recompute's ping-pong; D3Q19 segments keep every state
+    const bool d2 = c->lattice == LBM_D2Q9;
+    L.nseg = d2 ? 2 : (c->ckpt_every < 2 ? 2 : c->ckpt_every);
+    L.nrec = d2 ? (c->ckpt_every < 2 ? 1 : c->ckpt_every - 1) : 0;
+    L.RB = align_up((size_t)(d2 ? 6 : 10) * L.N * L.cs);
     L.nblocks = blocks_for(L.N);
     L.pstride = 2 * L.nblocks + 64;      // partial slots per sample, for any launch grid
     L.nsamp = c->window_len / c->sample_every;
@@ -145,6 +152,7 @@ void layout(const lbm_config* c, Layout& L) {
     L.off_G = o;       o += 2 * L.SB;
     L.off_ring = o;    o += 2 * (size_t)L.R * L.SB;
     L.off_seg = o;     o += (size_t)L.nseg * L.SB;
+    L.off_rec = o;     o += (size_t)L.nrec * L.RB;
     L.off_s = o;       o += align_up(L.N * L.cs);
     L.off_srep = o;    o += align_up(L.N * L.cs);
     L.off_gamma = o;   o += align_up(L.N * 8);
@@ -199,6 +207,7 @@ struct lbm_ctx {
     void* G[2];
     std::vector<void*> ring[2];
     std::vector<void*> seg;
+    std::vector<void*> recs;                // moment records of a recomputed D2Q9 segment
     std::vector<void*> starts, ring_rep;   // full history: window-start states, replay ring
     double* facc[3];                 // window-field accumulators (two forward, one replay)
     double *uref, *fparts;           // wake reference; wake-value block partials
@@ -287,8 +296,8 @@ StepLaunch step_args(lbm_ctx* c) {
     a.tile_x = c->tile_x;
     a.tile_y = c->tile_y;
     a.tile_z = c->tile_z;
-    a.allout = nullptr;
-    a.allout_slot = 0;
+    a.rec = nullptr;
+    a.rec_slot = 0;
     return a;
 }
 
@@ -599,36 +608,104 @@ lbm_status adjoint_window(lbm_ctx* c, const std::vector<void*>& ring, long ns, b
     aa.ns = ns;
     aa.dW = dW;
     aa.wgt = wgt;
+    aa.rec = 0;
     for (int seg = L.R - 1; seg >= 0; --seg) {
         const long c0 = ns - 1 + (long)seg * K;       // checkpoint step
         aa.kseg = c0;
         const bool last = seg == L.R - 1;
         const bool seed = last && objective_window;
+        if (c->cfg.lattice == LBM_D2Q9) {
+            // recompute G^{c0+1} .. G^{c0+K-1} through two state slots, keeping
+            // the moment record R^m of every pre-collision state f^m,
+            // m = c0+1 .. c0+K-1, in recs[m - c0 - 1]: the pre-states of
+            // transitions c0+2 .. c0+K
+            int gc = 0;
+            if (seed || K >= 2) {
+                AuxLaunch ca = aux_args(c, AUX_COLLIDE);
+                ca.src = ring[seg];
+                ca.dst = c->seg[0];
+                HIPCHK(launch_aux(ca));
+                const long nrec = K - 1;
+                for (long j = 1; j <= nrec;) {
+                    long n = nrec - j + 1;
+                    if (n > c->tb_steps) n = c->tb_steps;
+                    sa.nsteps = (int)n;
+                    sa.gin = c->seg[gc];
+                    sa.gout = c->seg[gc ^ 1];
+                    sa.rec = c->recs[j - 1];
+                    sa.rec_slot = L.RB;
+                    if ((st = t_launch(c, 2, n)) != LBM_OK) return st;
+                    HIPCHK(launch_step(sa));
+                    gc ^= 1;
+                    j += n;
+                }
+                sa.rec = nullptr;
+                sa.nsteps = 1;
+                if ((st = t_close(c)) != LBM_OK) return st;
+            }
+            if (seed) {
+                // terminal condition: nu_hat^{n_e} = BC^T (dJ/df^{n_e}), f^{n_e} = BC(S(G^{n_e - 1}))
+                aa.nu_in = nullptr;
+                aa.nu_out = c->nu[cur];
+                aa.state = c->seg[gc];
+                aa.direct = 0;
+                aa.rec = 0;
+                aa.seed = 1;
+                aa.src_w = wgt;
+                HIPCHK(launch_adjoint(aa));
+            }
+            for (long k = c0 + K; k >= c0 + 1;) {
+                aa.nu_in = c->nu[cur];
+                aa.nu_out = c->nu[cur ^ 1];
+                aa.seed = 0;
+                aa.nsteps = 1;
+                long n = 1;
+                if (k - 1 == c0) {
+                    aa.direct = 1;
+                    aa.rec = 0;
+                    aa.state = ring[seg];
+                } else {
+                    // transitions k .. c0 + 2 read the records of their pre-states
+                    aa.direct = 0;
+                    aa.rec = 1;
+                    aa.state = c->recs[k - 2 - c0];
+                    aa.gseg = c->recs[0];
+                    aa.slot = L.RB;
+                    n = k - (c0 + 1);
+                    if (n > c->adj_steps) n = c->adj_steps;
+                    if (n > 1) {
+                        aa.nsteps = (int)n;
+                        aa.k_hi = k;
+                    }
+                }
+                aa.src_w = (k > ns && (k - ns) % dW == 0) ? wgt : 0.0;
+                if ((st = t_launch(c, 1, n)) != LBM_OK) return st;
+                HIPCHK(launch_adjoint(aa));
+                cur ^= 1;
+                k -= n;
+            }
+            aa.rec = 0;
+            if ((st = t_close(c)) != LBM_OK) return st;
+            continue;
+        }
+        aa.gseg = c->seg[0];
+        aa.slot = L.SB;
         const long nrec = seed ? K - 1 : K - 2;       // step launches after the restart
         if (seed || K >= 2) {
             AuxLaunch ca = aux_args(c, AUX_COLLIDE);
             ca.src = ring[seg];
             ca.dst = c->seg[0];
             HIPCHK(launch_aux(ca));
-            // recompute G^{c0+1} .. G^{c0+nrec} into seg[1 .. nrec]; blocked
-            // launches keep every intermediate state (seg slots are SB apart).
-            // D3Q19 recomputes in single steps: its two-step launch, which
-            // then also stores the first step's state, measured slower.
-            const long rec_max = c->cfg.lattice == LBM_D3Q19 ? 1 : c->tb_steps;
-            for (long j = 1; j <= nrec;) {
-                long n = nrec - j + 1;
-                if (n > rec_max) n = rec_max;
-                sa.nsteps = (int)n;
+            // D3Q19: recompute G^{c0+1} .. G^{c0+nrec} into seg[1 .. nrec] in
+            // single steps (a two-step launch, which would also have to store
+            // the first step's state, measured slower)
+            for (long j = 1; j <= nrec; ++j) {
+                sa.nsteps = 1;
                 sa.gin = c->seg[j - 1];
-                sa.gout = c->seg[j + n - 1];
-                sa.allout = n > 1 ? c->seg[j] : nullptr;
-                sa.allout_slot = L.SB;
-                if ((st = t_launch(c, 2, n)) != LBM_OK) return st;
+                sa.gout = c->seg[j];
+                if ((st = t_launch(c, 2, 1)) != LBM_OK) return st;
                 HIPCHK(launch_step(sa));
-                j += n;
             }
-            sa.allout = nullptr;
-            sa.nsteps = 1;
             if ((st = t_close(c)) != LBM_OK) return st;
         }
         if (seed) {
@@ -746,6 +823,7 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
     for (int p = 0; p < 2; ++p)
         for (int r = 0; r < L.R; ++r) c->ring[p].push_back(at(c, L.off_ring + ((size_t)p * L.R + r) * L.SB));
     for (int k = 0; k < L.nseg; ++k) c->seg.push_back(at(c, L.off_seg + (size_t)k * L.SB));
+    for (int k = 0; k < L.nrec; ++k) c->recs.push_back(at(c, L.off_rec + (size_t)k * L.RB));
     for (int k = 0; k < L.nstart; ++k) c->starts.push_back(at(c, L.off_starts + (size_t)k * L.SB));
     if (cfg->full_history)
         for (int r = 0; r < L.R; ++r) c->ring_rep.push_back(at(c, L.off_ringrep + (size_t)r * L.SB));

@@ -360,6 +360,29 @@ struct Moments {
     T te, ite;  // tau_eff (Eq. tau_eff) and its reciprocal
 };
 
+// Completes the moments from rho, 1/rho and Pi: Pi:Pi, ||Pi||, and the
+// effective relaxation time of Eq. tau_eff with its reciprocal.
+template <class L, class T>
+__device__ __forceinline__ void moments_finish(const Phys& ph, Moments<L, T>& m) {
+    constexpr int D = L::D;
+    using SY = Sym<D>;
+    T PP = 0;
+#pragma unroll
+    for (int p = 0; p < D; ++p) {
+#pragma unroll
+        for (int q = p; q < D; ++q) {
+            const T v = m.Pi[SY::idx[p][q]];
+            PP += (p == q ? (T)1 : (T)2) * v * v;
+        }
+    }
+    m.PP = PP;
+    m.norm = fsqrt((T)2 * PP);
+    const T tau = (T)ph.tau;
+    m.R = fsqrt(tau * tau + (T)(18.0 * ph.c2) * m.norm * m.irho);
+    m.te = (T)0.5 * (tau + m.R);
+    m.ite = rcp(m.te);
+}
+
 // Directions come in opposite pairs (a, opp(a)); sums over a pair of the
 // even (c c) and odd (c) moments share h_a + h_opp and h_a - h_opp.
 template <class L, class T>
@@ -394,7 +417,6 @@ __device__ __forceinline__ void moments(const T h[L::Q], const Phys& ph, Moments
     }
     const T rho = (T)1 + drho;
     const T irho = rcp(rho);
-    T PP = 0;
 #pragma unroll
     for (int p = 0; p < D; ++p) {
 #pragma unroll
@@ -403,7 +425,6 @@ __device__ __forceinline__ void moments(const T h[L::Q], const Phys& ph, Moments
             T v = M[k] - j[p] * j[q] * irho;
             if (p == q) v -= (T)(1.0 / 3.0) * drho;
             m.Pi[k] = v;
-            PP += (p == q ? (T)1 : (T)2) * v * v;
         }
     }
     m.drho = drho;
@@ -411,12 +432,39 @@ __device__ __forceinline__ void moments(const T h[L::Q], const Phys& ph, Moments
     m.irho = irho;
 #pragma unroll
     for (int p = 0; p < D; ++p) m.j[p] = j[p];
-    m.PP = PP;
-    m.norm = fsqrt((T)2 * PP);
-    const T tau = (T)ph.tau;
-    m.R = fsqrt(tau * tau + (T)(18.0 * ph.c2) * m.norm * irho);
-    m.te = (T)0.5 * (tau + m.R);
-    m.ite = rcp(m.te);
+    moments_finish<L, T>(ph, m);
+}
+
+// Moment record of a node state (the recompute of an adjoint segment keeps
+// one per node and step instead of the populations): drho, j, Pi, that is
+// 1 + D + K values in planes of N.
+template <class L>
+constexpr int record_size() {
+    return 1 + L::D + Sym<L::D>::K;
+}
+
+template <class L, class T>
+__device__ __forceinline__ void record_store(T* __restrict__ rec, int N, int n, const Moments<L, T>& m) {
+    rec[n] = m.drho;
+#pragma unroll
+    for (int p = 0; p < L::D; ++p) rec[(size_t)(1 + p) * N + n] = m.j[p];
+#pragma unroll
+    for (int k = 0; k < Sym<L::D>::K; ++k) rec[(size_t)(1 + L::D + k) * N + n] = m.Pi[k];
+}
+
+// The moments of a stored record, completed exactly as moments() completes
+// the sums of a state.
+template <class L, class T>
+__device__ __forceinline__ void record_load(const T* __restrict__ rec, int N, int n, const Phys& ph,
+                                            Moments<L, T>& m) {
+    m.drho = rec[n];
+#pragma unroll
+    for (int p = 0; p < L::D; ++p) m.j[p] = rec[(size_t)(1 + p) * N + n];
+#pragma unroll
+    for (int k = 0; k < Sym<L::D>::K; ++k) m.Pi[k] = rec[(size_t)(1 + L::D + k) * N + n];
+    m.rho = (T)1 + m.drho;
+    m.irho = rcp(m.rho);
+    moments_finish<L, T>(ph, m);
 }
 
 // Regularized collision (Eq. modified_collision) followed by the partial

@@ -93,7 +93,8 @@ __device__ __forceinline__ void node_samples(const Obj& ob, int x, int y, int z,
 
 // Forward step k: G_out = C(BC(S(G_in))). SAMPLE: write the block partials
 // of the sampled quantities of f^k. WPRE: also store f^k (pre-collision,
-// shifted) as a checkpoint.
+// shifted) as a checkpoint. REC: also store the moment record of f^k (the
+// recompute of an adjoint segment).
 // Zeroes the partial slots [gridDim.x, stride) that this launch does not
 // write, so that launches with different grids share one partials layout.
 template <int NT>
@@ -110,11 +111,11 @@ __device__ __forceinline__ void zero_unused_partials(double* partials, int strid
     zero_unused_partials_n<BLOCK>(partials, stride);
 }
 
-template <class L, class S, class T, bool SAMPLE, bool WPRE>
+template <class L, class S, class T, bool SAMPLE, bool WPRE, bool REC = false>
 __global__ __launch_bounds__(BLOCK) void k_step(const S* __restrict__ gin, S* __restrict__ gout,
                                                 S* __restrict__ pre, const T* __restrict__ sfield,
                                                 Geo g, Phys ph, Obj ob, double* __restrict__ partials,
-                                                int part_stride) {
+                                                int part_stride, T* __restrict__ rec = nullptr) {
     const int n = (int)(blockIdx.x * BLOCK + threadIdx.x);
     const bool active = n < g.N;
     double v[3] = {0.0, 0.0, 0.0};
@@ -131,6 +132,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const S* __restrict__ gin, S* __
         }
         Moments<L, T> m;
         moments<L, T>(h, ph, m);
+        if (REC) record_store<L, T>(rec, g.N, n, m);
         const T s = sfield[n];
         if (SAMPLE) node_samples<L, T>(ob, x, y, z, s, m, v);
         T out[L::Q];
@@ -391,9 +393,10 @@ struct TbLds<_Float16, float> {
     using type = _Float16;
 };
 
-// ALLOUT (recompute of an adjoint segment): every step t < nt also stores
-// the tile's post-collision state to allout + (t - 1) * slot (the step nt
-// state goes to gout as usual), so that each intermediate state is kept.
+// ALLOUT (recompute of an adjoint segment): every step t also stores the
+// moment record of the tile's pre-collision state f (drho, j, Pi, after the
+// boundary rules) to rec + (t - 1) * slot, which the adjoint reads instead
+// of pulling the populations again.
 // PS > 0: the planes of the LDS buffers are PS values apart (a compile-time
 // stride, so a node reaches its nine planes with immediate offsets); PS = 0:
 // they are LW * LH apart.
@@ -402,7 +405,7 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
                                                 S* __restrict__ pre, const T* __restrict__ sfield,
                                                 Geo g, Phys ph, Obj ob, double* __restrict__ partials,
                                                 int part_stride, int nt, int ox, int oy, int tiles_x,
-                                                S* __restrict__ allout, size_t slot) {
+                                                T* __restrict__ rec, size_t slot) {
     using L = D2Q9;
     using LT = typename TbLds<S, T>::type;
     extern __shared__ unsigned char lds_raw[];
@@ -448,16 +451,13 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
                 if (oc[u]) zou_he<L, T>(g, oc[u], c[u].y, h[u]);
                 Moments<L, T> mo;
                 moments<L, T>(h[u], ph, mo);
+                if (ALLOUT && tb_owned(g, c[u], H, ox, oy, x0, y0)) record_store<L, T>(rec, g.N, c[u].n, mo);
                 sbuf[c[u].cell] = sv[u];
                 T out[L::Q];
                 collide<L, T>(mo, sv[u], out);
 #pragma unroll
                 for (int a = 0; a < L::Q; ++a) dst[a * plane_sz + c[u].cell] = (LT)out[a];
                 if (face[u]) tb_ghosts<LT, T, 1>(g, dst, plane_sz, LW, LH, c[u], out);
-                if (ALLOUT && tb_owned(g, c[u], H, ox, oy, x0, y0)) {
-#pragma unroll
-                    for (int a = 0; a < L::Q; ++a) plane(allout, a, g.N)[(unsigned)c[u].n] = (S)out[a];
-                }
             }
         }
         __syncthreads();
@@ -474,16 +474,13 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
             tb_pull_lds<T, LT>(g, srcb, plane_sz, LW, rows, d0, c, face, h);
             Moments<L, T> mo;
             moments<L, T>(h, ph, mo);
+            if (ALLOUT && tb_owned(g, c, H, ox, oy, x0, y0))
+                record_store<L, T>(rec + (size_t)(t - 1) * slot, g.N, c.n, mo);
             T out[L::Q];
             collide<L, T>(mo, sbuf[c.cell], out);
 #pragma unroll
             for (int a = 0; a < L::Q; ++a) dst[a * plane_sz + c.cell] = (LT)out[a];
             if (face) tb_ghosts<LT, T, 1>(g, dst, plane_sz, LW, LH, c, out);
-            if (ALLOUT && tb_owned(g, c, H, ox, oy, x0, y0)) {
-                S* o = allout + (size_t)(t - 1) * slot;
-#pragma unroll
-                for (int a = 0; a < L::Q; ++a) plane(o, a, g.N)[(unsigned)c.n] = (S)out[a];
-            }
         }
         __syncthreads();
     }
@@ -503,6 +500,7 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
             }
             Moments<L, T> mo;
             moments<L, T>(h, ph, mo);
+            if (ALLOUT) record_store<L, T>(rec + (size_t)(nt - 1) * slot, g.N, c.n, mo);
             if (SAMPLE) {
                 double vv[3];
                 node_samples<L, T>(ob, c.x, c.y, 0, sbuf[c.cell], mo, vv);
@@ -972,10 +970,11 @@ __device__ __forceinline__ void adjoint_source(const Obj& ob, const Phys& ph, in
 //   sens(y) += d/ds <kappa, f**>  (FP64);
 //   mu = (d f** / d f^{k-1})^T kappa  (+ sampled objective source);
 //   nu_hat^{k-1} = BC^T mu on open nodes.
-// The pre-state f^{k-1}(y) comes from a stored checkpoint (DIRECT) or by
-// pulling the post-collision state G^{k-2} (recomputed segment). SEED only
+// The pre-state f^{k-1}(y) comes from a stored checkpoint (DIRECT), from
+// its moment record (REC: a recomputed D2Q9 segment) or by pulling the
+// post-collision state G^{k-2} (a recomputed D3Q19 segment). SEED only
 // evaluates the source (terminal condition at the window end).
-template <class L, class S, class T, class A, bool DIRECT, bool SEED>
+template <class L, class S, class T, class A, bool DIRECT, bool SEED, bool REC = false>
 __global__ __launch_bounds__(BLOCK) void k_adjoint(const A* __restrict__ nu_in, A* __restrict__ nu_out,
                                                    const S* __restrict__ state, const T* __restrict__ sfield,
                                                    double* __restrict__ sens, Geo g, Phys ph, Obj ob,
@@ -986,16 +985,20 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(const A* __restrict__ nu_in, 
     node_coords(g, n, x, y, z);
     const int oc = open_code<L>(g, x, y, z);
     // pre-state of the transition
-    T h[L::Q];
-    if (DIRECT) {
-#pragma unroll
-        for (int a = 0; a < L::Q; ++a) h[a] = (T)plane(state, a, g.N)[(unsigned)n];
-    } else {
-        pull<L, S, T>(state, g, n, x, y, z, h);
-        if (oc) zou_he<L, T>(g, oc, y, h);
-    }
     Moments<L, T> m;
-    moments<L, T>(h, ph, m);
+    if (REC) {
+        record_load<L, T>(reinterpret_cast<const T*>(state), g.N, n, ph, m);
+    } else {
+        T h[L::Q];
+        if (DIRECT) {
+#pragma unroll
+            for (int a = 0; a < L::Q; ++a) h[a] = (T)plane(state, a, g.N)[(unsigned)n];
+        } else {
+            pull<L, S, T>(state, g, n, x, y, z, h);
+            if (oc) zou_he<L, T>(g, oc, y, h);
+        }
+        moments<L, T>(h, ph, m);
+    }
     MomentGrad<L, T> gr;
     gr.gr = 0;
 #pragma unroll
@@ -1049,9 +1052,9 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(const A* __restrict__ nu_in, 
 
 // Temporally blocked adjoint steps (D2Q9) over a recomputed segment: one
 // launch takes nu_hat^{k_hi} to nu_hat^{k_hi - nt}. Step t (t = 1 .. nt) is
-// the transition k = k_hi - t + 1, whose pre-state f^{k-1} is pulled from
-// the post-collision state G^{k-2} = gseg + (k - 2 - kseg) * slot (global
-// memory; every step of a segment is stored by the blocked recompute). The
+// the transition k = k_hi - t + 1, whose pre-state enters through its
+// moment record R^{k-1} = rseg + (k - 2 - kseg) * slot (global memory; the
+// recompute stores one record per node and step of the segment). The
 // adjoint populations stay in LDS between steps, on tiles grown by nt - 1
 // nodes per side as in the forward blocked kernel. Adjoint streaming gathers
 // kappa_a(y) = nu_hat_a(y + c_a); for a direction leaving through a wall it
@@ -1063,7 +1066,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(const A* __restrict__ nu_in, 
 // an FP64 LDS plane and added to global memory once.
 template <class S, class T, class A, int TB, int PS>
 __global__ __launch_bounds__(TB) void k_adjoint_tb(const A* __restrict__ nu_in, A* __restrict__ nu_out,
-                                                   const S* __restrict__ gseg, size_t slot, long kseg,
+                                                   const T* __restrict__ rseg, size_t slot, long kseg,
                                                    const T* __restrict__ sfield, double* __restrict__ sens,
                                                    Geo g, Phys ph, Obj ob, long k_hi, long ns, long dW, double wgt,
                                                    int nt, int ox, int oy, int tiles_x) {
@@ -1085,7 +1088,7 @@ __global__ __launch_bounds__(TB) void k_adjoint_tb(const A* __restrict__ nu_in, 
     __syncthreads();
     for (int t = 1; t <= nt; ++t) {
         const long k = k_hi - t + 1;
-        const S* Gk2 = gseg + (size_t)(k - 2 - kseg) * slot;
+        const T* Rk1 = rseg + (size_t)(k - 2 - kseg) * slot;
         const double src_w = (k > ns && (k - ns) % dW == 0) ? wgt : 0.0;
         const bool last = t == nt;
         const TbPhase pt = tb_phase(g, t - 1, LW, LH, x0, y0, last);
@@ -1096,12 +1099,9 @@ __global__ __launch_bounds__(TB) void k_adjoint_tb(const A* __restrict__ nu_in, 
             const bool face = tb_cell(g, i, pt, LW, x0, y0, c);
             const int oc = face ? tb_open<T>(g, rows, c) : 0;
             const T u0 = rows.u[c.ly];
-            // pre-state f^{k-1}
-            T h[L::Q];
-            pull<L, S, T>(Gk2, g, c.n, c.x, c.y, 0, h);
-            if (oc) zou_he_rows<L, T>(oc, u0, d0, h);
+            // pre-state f^{k-1}: its moment record
             Moments<L, T> m;
-            moments<L, T>(h, ph, m);
+            record_load<L, T>(Rk1, g.N, c.n, ph, m);
             // adjoint streaming
             T kap[L::Q];
             if (t == 1) {
@@ -1544,8 +1544,8 @@ template <class S, class T, bool SAMPLE, bool WPRE, int TB, bool ALLOUT, int PS>
 static void launch_tb_ps(const StepLaunch& a, int tiles_x, int tiles_y, size_t lds) {
     hipLaunchKernelGGL((k_step_tb<S, T, SAMPLE, WPRE, TB, ALLOUT, PS>), dim3(tiles_x * tiles_y), dim3(TB), lds,
                        a.stream, (const S*)a.gin, (S*)a.gout, (S*)a.pre, (const T*)a.s, a.geo, a.ph, a.ob,
-                       a.partials, a.part_stride, a.nsteps, a.tile_x, a.tile_y, tiles_x, (S*)a.allout,
-                       a.allout_slot / sizeof(S));
+                       a.partials, a.part_stride, a.nsteps, a.tile_x, a.tile_y, tiles_x, (T*)a.rec,
+                       a.rec_slot / sizeof(T));
 }
 
 template <class S, class T, bool SAMPLE, bool WPRE, bool ALLOUT>
@@ -1604,7 +1604,7 @@ static hipError_t step_t(const StepLaunch& a) {
     S* pre = (S*)a.pre;
     const T* sf = (const T*)a.s;
     if (L::D == 3 && a.nsteps > 1) {
-        if (a.nsteps != 2 || a.allout) return hipErrorInvalidValue;
+        if (a.nsteps != 2 || a.rec) return hipErrorInvalidValue;
         if (a.sample) {
             if (pre) launch_tbz<S, T, true, true>(a);
             else launch_tbz<S, T, true, false>(a);
@@ -1616,7 +1616,7 @@ static hipError_t step_t(const StepLaunch& a) {
     }
     if (a.nsteps > 1) {
         if (L::D != 2) return hipErrorInvalidValue;
-        if (a.allout) {
+        if (a.rec) {
             if (a.sample || pre) return hipErrorInvalidValue;
             launch_tb<S, T, false, false, true>(a);
         } else if (a.sample) {
@@ -1630,7 +1630,11 @@ static hipError_t step_t(const StepLaunch& a) {
     }
     dim3 gr = grid_for(g.N);
     const int ps = a.part_stride;
-    if (a.sample) {
+    if (a.rec) {
+        if (a.sample || pre) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_step<L, S, T, false, false, true>), gr, dim3(BLOCK), 0, a.stream, gin, gout, pre, sf, g,
+                           a.ph, a.ob, a.partials, ps, (T*)a.rec);
+    } else if (a.sample) {
         if (pre) hipLaunchKernelGGL((k_step<L, S, T, true, true>), gr, dim3(BLOCK), 0, a.stream, gin, gout, pre, sf, g, a.ph, a.ob, a.partials, ps);
         else hipLaunchKernelGGL((k_step<L, S, T, true, false>), gr, dim3(BLOCK), 0, a.stream, gin, gout, pre, sf, g, a.ph, a.ob, a.partials, ps);
     } else {
@@ -1677,8 +1681,9 @@ static hipError_t adj_t(const AdjLaunch& a) {
         const int ps = tb_plane(a.nsteps, a.tile_x, a.tile_y, sizeof(T), sizeof(T), (size_t)a.tile_x * a.tile_y * 8);
         const int tb = tb_threads(a.nsteps, a.tile_x, a.tile_y);
         const dim3 grid(tiles_x * tiles_y);
-        const S* gs = (const S*)a.gseg;
-        const size_t slot = a.slot / sizeof(S);
+        if (!a.rec) return hipErrorInvalidValue;          // the D2Q9 segments are moment records
+        const T* gs = (const T*)a.gseg;
+        const size_t slot = a.slot / sizeof(T);
 #define LBM_ADJ_TB(TBV, PSV)                                                                                \
     hipLaunchKernelGGL((k_adjoint_tb<S, T, A, TBV, PSV>), grid, dim3(TBV), lds, a.stream, nin, nout, gs, slot, \
                        a.kseg, sf, a.sens, g, a.ph, a.ob, a.k_hi, a.ns, a.dW, a.wgt, a.nsteps, a.tile_x,       \
@@ -1707,6 +1712,8 @@ static hipError_t adj_t(const AdjLaunch& a) {
         hipLaunchKernelGGL((k_adjoint<L, S, T, A, false, true>), gr, dim3(BLOCK), 0, a.stream, nin, nout, st, sf, a.sens, g, a.ph, a.ob, a.src_w);
     } else if (a.direct) {
         hipLaunchKernelGGL((k_adjoint<L, S, T, A, true, false>), gr, dim3(BLOCK), 0, a.stream, nin, nout, st, sf, a.sens, g, a.ph, a.ob, a.src_w);
+    } else if (a.rec) {
+        hipLaunchKernelGGL((k_adjoint<L, S, T, A, false, false, true>), gr, dim3(BLOCK), 0, a.stream, nin, nout, st, sf, a.sens, g, a.ph, a.ob, a.src_w);
     } else {
         hipLaunchKernelGGL((k_adjoint<L, S, T, A, false, false>), gr, dim3(BLOCK), 0, a.stream, nin, nout, st, sf, a.sens, g, a.ph, a.ob, a.src_w);
     }

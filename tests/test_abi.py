@@ -71,9 +71,12 @@ def test_workspace_layout(B):
     assert st == B.LBM_OK
     N, Q = 40 * 16, 9
     state = -(-Q * N * 4 // 256) * 256
-    # two ping-pong states, two rings of |W|/K = 4 slots, K = 5 recompute slots
-    assert n >= (2 + 2 * 4 + 5) * state
-    assert n < (2 + 2 * 4 + 5) * state + 2 * 2 * Q * N * 4 + 64 * 1024 + 20 * 3 * 8 * 8
+    record = -(-6 * N * 4 // 256) * 256
+    # two ping-pong states, two rings of |W|/K = 4 slots, two recompute states
+    # and K - 1 = 4 moment records (drho, j, Pi) of the recomputed steps
+    fixed = (2 + 2 * 4 + 2) * state + 4 * record
+    assert n >= fixed
+    assert n < fixed + 2 * 2 * Q * N * 4 + 64 * 1024 + 20 * 3 * 8 * 8
 
 
 @pytest.mark.parametrize("field,value", [
