@@ -243,7 +243,11 @@ def precision_compare(w, ref_prec, res_ref, args, torch, Solver):
 # Algorithmic bytes per update on D3Q19 (FP32 storage): forward 19 * 4 * 2 + 4;
 # adjoint 19 * 4 * 2 + 19 * 4 + 4 + 16.
 FWD_BYTES_3D = {"f32": 19 * 4 * 2 + 4, "f64": 19 * 8 * 2 + 8, "f16s": 19 * 2 * 2 + 4}
-ADJ_BYTES_3D = {"f32": 19 * 4 * 3 + 4 + 16, "f64": 19 * 8 * 3 + 8 + 16, "f16s": 19 * 4 * 2 + 19 * 2 + 4 + 16}
+# the adjoint reads the moment record (10 values) of its pre-state; the
+# recompute writes it beside the state
+ADJ_BYTES_3D = {"f32": 19 * 4 * 2 + 10 * 4 + 4 + 16, "f64": 19 * 8 * 2 + 10 * 8 + 8 + 16,
+                "f16s": 19 * 4 * 2 + 10 * 4 + 4 + 16}
+REC_BYTES_3D = {p: FWD_BYTES_3D[p] + 10 * (8 if p == "f64" else 4) for p in FWD_BYTES_3D}
 
 
 def hbm_suite(args, torch):
@@ -277,7 +281,7 @@ def hbm_suite(args, torch):
                       REC_BYTES[prec]))
     w3 = W.cylinder_3d(window_len=100, sample_every=20, ckpt_every=20, n_windows=2)
     cases.append(("cylinder 3D 384x128x128 D3Q19", w3, "f32", FWD_BYTES_3D["f32"], ADJ_BYTES_3D["f32"],
-                  FWD_BYTES_3D["f32"]))
+                  REC_BYTES_3D["f32"]))
     for name, w, prec, fb, ab, rb in cases:
         sv = Solver(w, prec)
         sv.set_gamma(w.gamma)

@@ -155,8 +155,9 @@ typedef struct lbm_ctx lbm_ctx;
 
 /* Bytes of device workspace that lbm_init needs for this configuration
  * (state ping-pong, two checkpoint rings of |W|/K slots, the recompute
- * slots of a segment: for D2Q9 two states and K - 1 moment records of 6
- * values per node, for D3Q19 K states; adjoint buffers, sample partials;
+ * slots of a segment: two states and K - 1 moment records of 6 (D2Q9) or
+ * 10 (D3Q19) values per node in the compute precision (FP64 for LBM_F64,
+ * else FP32); adjoint buffers, sample partials;
  * with full_history also max_windows window-start states and a third
  * ring). Validates the configuration. */
 lbm_status lbm_workspace_bytes(const lbm_config* cfg, size_t* bytes);
@@ -273,9 +274,9 @@ lbm_status lbm_timing(lbm_ctx* ctx, int enable, double* out);
  * (FP32, FP16S) or 4 steps (FP64); larger grids 6 steps on 64 x 16 tiles
  * (FP32), 2 steps on 32 x 8 (FP64), and for FP16S (whose LDS holds FP16
  * states) 6 steps on 48 x 48 below 4M nodes, 5 steps on 64 x 40 above. The
- * recompute of the adjoint sweep uses the same blocking, storing every
- * intermediate state. The adjoint steps that pull their pre-state from a
- * recomputed segment run blocked too (see lbm_set_adjoint_blocking); this
+ * recompute of the adjoint sweep uses the same blocking, storing the moment
+ * record of every recomputed step. The adjoint steps that read their
+ * pre-state's record from a recomputed segment run blocked too (see lbm_set_adjoint_blocking); this
  * call sets their default: on grids of more than 400k nodes 4 steps on
  * 25 x 25 tiles (FP64) or 5 steps on 48 x 24 (FP32, FP16S), else the
  * forward's steps and tiles, falling back to the first of 48 x 24, 64 x 16,
@@ -284,8 +285,8 @@ lbm_status lbm_timing(lbm_ctx* ctx, int enable, double* out);
 lbm_status lbm_set_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y);
 
 /* Temporal blocking of D3Q19 forward launches: nsteps = 2 advances two
- * steps per launch (the recompute of the adjoint sweep takes single
- * steps). A workgroup owns tile_x x tile_y nodes in x and y and tile_z
+ * steps per launch (the recompute of the adjoint sweep too, storing the
+ * moment records of both steps). A workgroup owns tile_x x tile_y nodes in x and y and tile_z
  * consecutive z planes; it takes the first step plane by
  * plane over the tile grown by one node in x and y, keeping three planes of
  * that state in LDS (walls on x and y faces as ghost cells, as for D2Q9),
@@ -293,8 +294,8 @@ lbm_status lbm_set_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y);
  * nsteps = 1 turns it off. Requires at least 256 nodes per block,
  * (tile_x + 2) * (tile_y + 2) <= 1024 and 3 (tile_x + 2)(tile_y + 2) x
  * (19 state values in the storage-rounded LDS type + one compute-type
- * value) within 159 KB, and a state (19 x nodes x storage bytes) below
- * 4 GB. Samples, checkpoints and window ends fall on a launch's last step as
+ * value) within 159 KB, and a state (19 x nodes x storage bytes) and a
+ * moment record (10 x nodes x compute bytes) below 4 GB each. Samples, checkpoints and window ends fall on a launch's last step as
  * in 2D. Adjoint launches stay single-step. Default (set by lbm_init): FP32
  * grids of more than 2M nodes take 2 steps on 32 x 13 tiles, with the z run
  * that lets the blocks fill the compute units in nearly whole rounds with
@@ -303,8 +304,8 @@ lbm_status lbm_set_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y);
  * the LDS opt-in fails. */
 lbm_status lbm_set_blocking_3d(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y, int tile_z);
 
-/* Blocking of the adjoint launches that pull their pre-states from a
- * recomputed segment (D2Q9 only): up to nsteps reverse steps per launch on
+/* Blocking of the adjoint launches that read their pre-states' moment
+ * records from a recomputed segment (D2Q9 only): up to nsteps reverse steps per launch on
  * tile_x x tile_y output tiles, the adjoint populations (FP32, or FP64 for
  * LBM_F64) of the tile and its halo and an FP64 sensitivity plane of the
  * tile in LDS. nsteps = 1 turns it off. Requires tile_x * tile_y >= 256 and
@@ -314,19 +315,19 @@ lbm_status lbm_set_blocking_3d(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y,
  * out-of-range arguments, LBM_E_HIP if the LDS opt-in fails. */
 lbm_status lbm_set_adjoint_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y);
 
-/* Blocking of the D3Q19 adjoint launches that pull their pre-states from a
- * recomputed segment: nsteps = 2 takes two reverse steps per launch. A
+/* Blocking of the D3Q19 adjoint launches that read their pre-states' moment
+ * records from a recomputed segment: nsteps = 2 takes two reverse steps per launch. A
  * workgroup owns tile_x x tile_y nodes in x and y and tile_z consecutive z
  * planes; the first step runs plane by plane over the tile grown by one
  * node in x and y, keeping three planes of adjoint populations in LDS
  * (walls on x and y faces as ghost cells, 0 behind open faces), and the
- * second gathers from them; each step pulls its own pre-state from the
- * segment, and the tile's sensitivity takes one FP64 read-modify-write per
+ * second gathers from them; each step reads its own pre-state's record from
+ * the segment, and the tile's sensitivity takes one FP64 read-modify-write per
  * launch. nsteps = 1 turns it off. Requires at least 256 nodes per block,
  * (tile_x + 2) * (tile_y + 2) <= 512 (256 for LBM_F64), 3 (tile_x + 2) x
  * (tile_y + 2) x (8 + one compute-type value + 19 adjoint values) bytes
- * within 159 KB, and the state and the adjoint populations below 4 GB
- * each. Errors: LBM_E_INVALID for a D2Q9 context or out-of-range
+ * within 159 KB, and a moment record and the adjoint populations below
+ * 4 GB each. Errors: LBM_E_INVALID for a D2Q9 context or out-of-range
  * arguments, LBM_E_HIP if the LDS opt-in fails. */
 lbm_status lbm_set_adjoint_blocking_3d(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y, int tile_z);
 

@@ -139,12 +139,12 @@ void layout(const lbm_config* c, Layout& L) {
     L.as = L.cs;
     L.SB = align_up((size_t)L.Q * L.N * L.ss);
     L.R = c->window_len / c->ckpt_every;
-    // D2Q9 segments keep moment records of every recomputed step and two
-    // states for the recompute's ping-pong; D3Q19 segments keep every state
-    const bool d2 = c->lattice == LBM_D2Q9;
-    L.nseg = d2 ? 2 : (c->ckpt_every < 2 ? 2 : c->ckpt_every);
-    L.nrec = d2 ? (c->ckpt_every < 2 ? 1 : c->ckpt_every - 1) : 0;
-    L.RB = align_up((size_t)(d2 ? 6 : 10) * L.N * L.cs);
+    // a segment keeps the moment record (drho, j, Pi: 1 + D + D(D+1)/2
+    // values per node) of every recomputed step and two states for the
+    // recompute's ping-pong
+    L.nseg = 2;
+    L.nrec = c->ckpt_every < 2 ? 1 : c->ckpt_every - 1;
+    L.RB = align_up((size_t)(c->lattice == LBM_D2Q9 ? 6 : 10) * L.N * L.cs);
     L.nblocks = blocks_for(L.N);
     L.pstride = 2 * L.nblocks + 64;      // partial slots per sample, for any launch grid
     L.nsamp = c->window_len / c->sample_every;
@@ -492,8 +492,9 @@ lbm_status set_blocking_3d(lbm_ctx* c, int nsteps, int tile_x, int tile_y, int t
             return fail(LBM_E_INVALID, "(tile_x + 2) * (tile_y + 2) must be at most 1024");
         if (tbz_lds_bytes_prec(tile_x, tile_y, c->cfg.prec) > TB_LDS_MAX)
             return fail(LBM_E_INVALID, "tile needs more than 159 KB of LDS");
-        // the blocked kernel addresses a state with 32-bit byte offsets
-        if ((size_t)c->L.Q * c->L.N * c->L.ss > TBZ_STATE_MAX)
+        // the blocked kernel addresses a state and a moment record with
+        // 32-bit byte offsets
+        if ((size_t)c->L.Q * c->L.N * c->L.ss > TBZ_STATE_MAX || (size_t)10 * c->L.N * c->L.cs > TBZ_STATE_MAX)
             return fail(LBM_E_INVALID, "state too large for D3Q19 blocking (limit 4 GB)");
         const long tiles = (long)((c->cfg.nx + tile_x - 1) / tile_x) * ((c->cfg.ny + tile_y - 1) / tile_y) *
                            ((c->cfg.nz + tile_z - 1) / tile_z);
@@ -518,7 +519,7 @@ lbm_status set_adj_blocking_3d(lbm_ctx* c, int nsteps, int tile_x, int tile_y, i
             return fail(LBM_E_INVALID, "(tile_x + 2) * (tile_y + 2) too large (512, FP64 256)");
         if (adj_tbz_lds_bytes(tile_x, tile_y, c->L.as, c->L.cs) > TB_LDS_MAX)
             return fail(LBM_E_INVALID, "tile needs more than 159 KB of LDS");
-        if ((size_t)c->L.Q * c->L.N * c->L.ss > TBZ_STATE_MAX || (size_t)c->L.Q * c->L.N * c->L.as > TBZ_STATE_MAX)
+        if ((size_t)10 * c->L.N * c->L.cs > TBZ_STATE_MAX || (size_t)c->L.Q * c->L.N * c->L.as > TBZ_STATE_MAX)
             return fail(LBM_E_INVALID, "state too large for D3Q19 blocking (limit 4 GB)");
         HIPCHK(tb_prepare(c->cfg.prec));
         c->adj_tile_x = tile_x;
@@ -614,106 +615,41 @@ lbm_status adjoint_window(lbm_ctx* c, const std::vector<void*>& ring, long ns, b
         aa.kseg = c0;
         const bool last = seg == L.R - 1;
         const bool seed = last && objective_window;
-        if (c->cfg.lattice == LBM_D2Q9) {
-            // recompute G^{c0+1} .. G^{c0+K-1} through two state slots, keeping
-            // the moment record R^m of every pre-collision state f^m,
-            // m = c0+1 .. c0+K-1, in recs[m - c0 - 1]: the pre-states of
-            // transitions c0+2 .. c0+K
-            int gc = 0;
-            if (seed || K >= 2) {
-                AuxLaunch ca = aux_args(c, AUX_COLLIDE);
-                ca.src = ring[seg];
-                ca.dst = c->seg[0];
-                HIPCHK(launch_aux(ca));
-                const long nrec = K - 1;
-                for (long j = 1; j <= nrec;) {
-                    long n = nrec - j + 1;
-                    if (n > c->tb_steps) n = c->tb_steps;
-                    sa.nsteps = (int)n;
-                    sa.gin = c->seg[gc];
-                    sa.gout = c->seg[gc ^ 1];
-                    sa.rec = c->recs[j - 1];
-                    sa.rec_slot = L.RB;
-                    if ((st = t_launch(c, 2, n)) != LBM_OK) return st;
-                    HIPCHK(launch_step(sa));
-                    gc ^= 1;
-                    j += n;
-                }
-                sa.rec = nullptr;
-                sa.nsteps = 1;
-                if ((st = t_close(c)) != LBM_OK) return st;
-            }
-            if (seed) {
-                // terminal condition: nu_hat^{n_e} = BC^T (dJ/df^{n_e}), f^{n_e} = BC(S(G^{n_e - 1}))
-                aa.nu_in = nullptr;
-                aa.nu_out = c->nu[cur];
-                aa.state = c->seg[gc];
-                aa.direct = 0;
-                aa.rec = 0;
-                aa.seed = 1;
-                aa.src_w = wgt;
-                HIPCHK(launch_adjoint(aa));
-            }
-            for (long k = c0 + K; k >= c0 + 1;) {
-                aa.nu_in = c->nu[cur];
-                aa.nu_out = c->nu[cur ^ 1];
-                aa.seed = 0;
-                aa.nsteps = 1;
-                long n = 1;
-                if (k - 1 == c0) {
-                    aa.direct = 1;
-                    aa.rec = 0;
-                    aa.state = ring[seg];
-                } else {
-                    // transitions k .. c0 + 2 read the records of their pre-states
-                    aa.direct = 0;
-                    aa.rec = 1;
-                    aa.state = c->recs[k - 2 - c0];
-                    aa.gseg = c->recs[0];
-                    aa.slot = L.RB;
-                    n = k - (c0 + 1);
-                    if (n > c->adj_steps) n = c->adj_steps;
-                    if (n > 1) {
-                        aa.nsteps = (int)n;
-                        aa.k_hi = k;
-                    }
-                }
-                aa.src_w = (k > ns && (k - ns) % dW == 0) ? wgt : 0.0;
-                if ((st = t_launch(c, 1, n)) != LBM_OK) return st;
-                HIPCHK(launch_adjoint(aa));
-                cur ^= 1;
-                k -= n;
-            }
-            aa.rec = 0;
-            if ((st = t_close(c)) != LBM_OK) return st;
-            continue;
-        }
-        aa.gseg = c->seg[0];
-        aa.slot = L.SB;
-        const long nrec = seed ? K - 1 : K - 2;       // step launches after the restart
+        // recompute G^{c0+1} .. G^{c0+K-1} through two state slots, keeping
+        // the moment record R^m of every pre-collision state f^m,
+        // m = c0+1 .. c0+K-1, in recs[m - c0 - 1]: the pre-states of
+        // transitions c0+2 .. c0+K
+        int gc = 0;
         if (seed || K >= 2) {
             AuxLaunch ca = aux_args(c, AUX_COLLIDE);
             ca.src = ring[seg];
             ca.dst = c->seg[0];
             HIPCHK(launch_aux(ca));
-            // D3Q19: recompute G^{c0+1} .. G^{c0+nrec} into seg[1 .. nrec] in
-            // single steps (a two-step launch, which would also have to store
-            // the first step's state, measured slower)
-            for (long j = 1; j <= nrec; ++j) {
-                sa.nsteps = 1;
-                sa.gin = c->seg[j - 1];
-                sa.gout = c->seg[j];
-                if ((st = t_launch(c, 2, 1)) != LBM_OK) return st;
+            const long nrec = K - 1;
+            for (long j = 1; j <= nrec;) {
+                long n = nrec - j + 1;
+                if (n > c->tb_steps) n = c->tb_steps;
+                sa.nsteps = (int)n;
+                sa.gin = c->seg[gc];
+                sa.gout = c->seg[gc ^ 1];
+                sa.rec = c->recs[j - 1];
+                sa.rec_slot = L.RB;
+                if ((st = t_launch(c, 2, n)) != LBM_OK) return st;
                 HIPCHK(launch_step(sa));
+                gc ^= 1;
+                j += n;
             }
+            sa.rec = nullptr;
+            sa.nsteps = 1;
             if ((st = t_close(c)) != LBM_OK) return st;
         }
         if (seed) {
             // terminal condition: nu_hat^{n_e} = BC^T (dJ/df^{n_e}), f^{n_e} = BC(S(G^{n_e - 1}))
             aa.nu_in = nullptr;
             aa.nu_out = c->nu[cur];
-            aa.state = c->seg[K - 1];
+            aa.state = c->seg[gc];
             aa.direct = 0;
+            aa.rec = 0;
             aa.seed = 1;
             aa.src_w = wgt;
             HIPCHK(launch_adjoint(aa));
@@ -726,11 +662,15 @@ lbm_status adjoint_window(lbm_ctx* c, const std::vector<void*>& ring, long ns, b
             long n = 1;
             if (k - 1 == c0) {
                 aa.direct = 1;
+                aa.rec = 0;
                 aa.state = ring[seg];
             } else {
-                // steps k .. c0 + 2 pull their pre-state from the segment
+                // transitions k .. c0 + 2 read the records of their pre-states
                 aa.direct = 0;
-                aa.state = c->seg[k - 2 - c0];
+                aa.rec = 1;
+                aa.state = c->recs[k - 2 - c0];
+                aa.gseg = c->recs[0];
+                aa.slot = L.RB;
                 n = k - (c0 + 1);
                 if (n > c->adj_steps) n = c->adj_steps;
                 if (n > 1) {
@@ -744,6 +684,7 @@ lbm_status adjoint_window(lbm_ctx* c, const std::vector<void*>& ring, long ns, b
             cur ^= 1;
             k -= n;
         }
+        aa.rec = 0;
         if ((st = t_close(c)) != LBM_OK) return st;
     }
     return LBM_OK;

@@ -452,19 +452,37 @@ __device__ __forceinline__ void record_store(T* __restrict__ rec, int N, int n, 
     for (int k = 0; k < Sym<L::D>::K; ++k) rec[(size_t)(1 + L::D + k) * N + n] = m.Pi[k];
 }
 
-// The moments of a stored record, completed exactly as moments() completes
-// the sums of a state.
+// The moments of a record's values r (drho, j, Pi), completed exactly as
+// moments() completes the sums of a state.
 template <class L, class T>
-__device__ __forceinline__ void record_load(const T* __restrict__ rec, int N, int n, const Phys& ph,
-                                            Moments<L, T>& m) {
-    m.drho = rec[n];
+__device__ __forceinline__ void record_moments(const T (&r)[record_size<L>()], const Phys& ph, Moments<L, T>& m) {
+    m.drho = r[0];
 #pragma unroll
-    for (int p = 0; p < L::D; ++p) m.j[p] = rec[(size_t)(1 + p) * N + n];
+    for (int p = 0; p < L::D; ++p) m.j[p] = r[1 + p];
 #pragma unroll
-    for (int k = 0; k < Sym<L::D>::K; ++k) m.Pi[k] = rec[(size_t)(1 + L::D + k) * N + n];
+    for (int k = 0; k < Sym<L::D>::K; ++k) m.Pi[k] = r[1 + L::D + k];
     m.rho = (T)1 + m.drho;
     m.irho = rcp(m.rho);
     moments_finish<L, T>(ph, m);
+}
+
+template <class L, class T>
+__device__ __forceinline__ void record_load(const T* __restrict__ rec, int N, int n, const Phys& ph,
+                                            Moments<L, T>& m) {
+    T r[record_size<L>()];
+#pragma unroll
+    for (int c = 0; c < record_size<L>(); ++c) r[c] = rec[(size_t)c * N + n];
+    record_moments<L, T>(r, ph, m);
+}
+
+// The values of a record, in the order record_moments() takes them.
+template <class L, class T>
+__device__ __forceinline__ void record_values(const Moments<L, T>& m, T (&r)[record_size<L>()]) {
+    r[0] = m.drho;
+#pragma unroll
+    for (int p = 0; p < L::D; ++p) r[1 + p] = m.j[p];
+#pragma unroll
+    for (int k = 0; k < Sym<L::D>::K; ++k) r[1 + L::D + k] = m.Pi[k];
 }
 
 // Regularized collision (Eq. modified_collision) followed by the partial

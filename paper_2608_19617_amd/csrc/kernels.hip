@@ -652,12 +652,14 @@ __device__ __forceinline__ void buf_st(BufRsrc r, unsigned off, _Float16 v) {
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)buf_off(off), 0, 0);
 }
 
-template <class S, class T, bool SAMPLE, bool WPRE, int TB, int U>
+template <class S, class T, bool SAMPLE, bool WPRE, int TB, int U, bool REC = false>
 __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* __restrict__ gout,
                                                  S* __restrict__ pre, const T* __restrict__ sfield, Geo g, Phys ph,
                                                  Obj ob, double* __restrict__ partials, int part_stride, int ox,
-                                                 int oy, int oz, int tiles_x, int tiles_y) {
+                                                 int oy, int oz, int tiles_x, int tiles_y, T* __restrict__ rec,
+                                                 size_t rslot) {
     using L = D3Q19;
+    constexpr int RS = record_size<L>();
     using LT = typename TbLds<S, T>::type;
     extern __shared__ unsigned char lds_raw[];
     const int LW = ox + 2, LH = oy + 2, psz = LW * LH;
@@ -677,6 +679,11 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
     const BufRsrc rs = buf_rsrc(sfield, (size_t)N * sizeof(T));
     const BufRsrc rout = buf_rsrc(gout, state_bytes);
     const BufRsrc rpre = buf_rsrc(WPRE ? pre : gout, state_bytes);
+    // REC: the moment records of f^{k+1} (step 1, owned cells) and f^{k+2}
+    // (step 2), in two record slots rslot values apart
+    const size_t rec_bytes = (size_t)RS * N * sizeof(T);
+    const BufRsrc rrec1 = buf_rsrc(rec, REC ? rec_bytes : 0);
+    const BufRsrc rrec2 = buf_rsrc(REC ? rec + rslot : rec, REC ? rec_bytes : 0);
 
     // this thread's cells of a plane, the same on every plane: up to U of
     // the step-1 region and U of the output tile; a lane without a cell
@@ -684,7 +691,7 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
     const TbPhase p1 = tb_phase(g, 0, LW, LH, x0, y0, false);
     const TbPhase p2 = tb_phase(g, 1, LW, LH, x0, y0, true);
     TbCell c1[U], c2[U];
-    bool v1[U], v2[U], f1[U], f2[U];
+    bool v1[U], v2[U], f1[U], f2[U], own1[U];
     int o1[U], o2[U];
     T u1[U], u2[U];
 #pragma unroll
@@ -697,6 +704,7 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
         f1[u] = v1[u] && tb_cell(g, i, p1, LW, x0, y0, c1[u]);
         o1[u] = f1[u] ? open_code_xy(g, c1[u].x, c1[u].y) : 0;
         u1[u] = o1[u] ? (T)g.u_in[c1[u].y] : (T)0;
+        own1[u] = v1[u] && tb_owned(g, c1[u], 1, ox, oy, x0, y0);
         v2[u] = i < p2.count;
         f2[u] = v2[u] && tb_cell(g, i, p2, LW, x0, y0, c2[u]);
         o2[u] = f2[u] ? open_code_xy(g, c2[u].x, c2[u].y) : 0;
@@ -732,10 +740,17 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
         }
     };
     // step 1 of level j into its ring slot (a uniform branch around LDS and
-    // arithmetic only)
+    // arithmetic), then REC's record stores
     auto step1 = [&](int j, const R (&h)[U][L::Q], const T (&s)[U]) {
         int z;
         const bool ok = level_z(j, z);
+        T r1[U][RS];
+        if (REC) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int q = 0; q < RS; ++q) r1[u][q] = (T)0;
+        }
         if (ok) {
             const bool zf = !g.per_z && (z == 0 || z == g.nz - 1);
             const int slot[3] = {(j + 2) % 3, j % 3, (j + 1) % 3};
@@ -750,12 +765,27 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
                 if (o1[u] && !zf) zou_he_rows<L, T>(o1[u], u1[u], d0, hh);
                 Moments<L, T> mo;
                 moments<L, T>(hh, ph, mo);
+                if (REC) record_values<L, T>(mo, r1[u]);
                 sdst[c1[u].cell] = s[u];
                 T out[L::Q];
                 collide<L, T>(mo, s[u], out);
 #pragma unroll
                 for (int a = 0; a < L::Q; ++a) dst[a * psz + c1[u].cell] = (LT)out[a];
                 if (f1[u]) tbz_ghosts<LT, T, 1>(g, ring, psz, LW, LH, slot, c1[u], out);
+            }
+        }
+        if (REC) {
+            // records of the owned cells of an output plane (level 1 .. nzc),
+            // stored by every lane on every level (out-of-range offsets
+            // elsewhere)
+            const int zc = ok ? z : 0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool live = ok && own1[u] && j >= 1 && j <= nzc;
+                const unsigned n = (unsigned)(zc * nxy + c1[u].n);
+#pragma unroll
+                for (int q = 0; q < RS; ++q)
+                    buf_st(rrec1, live ? ((unsigned)q * N + n) * (unsigned)sizeof(T) : BUF_OOB, r1[u][q]);
             }
         }
     };
@@ -766,11 +796,14 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
         const int k = j - 1;
         const bool ok = k >= 1 && k <= nzc;
         const int z = ok ? zs + k - 1 : 0;
-        T out[U][L::Q], hp[U][L::Q];
+        T out[U][L::Q], hp[U][L::Q], rv[U][RS];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int u = 0; u < U; ++u) {
 #pragma unroll
             for (int a = 0; a < L::Q; ++a) out[u][a] = hp[u][a] = (T)0;
+#pragma unroll
+            for (int q = 0; q < RS; ++q) rv[u][q] = (T)0;
+        }
         if (ok) {
             const bool zlo = !g.per_z && z == 0, zhi = !g.per_z && z == g.nz - 1;
             const bool zf = zlo || zhi;
@@ -800,6 +833,7 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
                 }
                 Moments<L, T> mo;
                 moments<L, T>(h, ph, mo);
+                if (REC) record_values<L, T>(mo, rv[u]);
                 const T sc = sring[s0 * psz + c.cell];
                 if (SAMPLE && v2[u]) {
                     double vv[3];
@@ -820,6 +854,11 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
                 const unsigned o = live ? ((unsigned)a * N + n) * (unsigned)sizeof(S) : BUF_OOB;
                 buf_st(rout, o, (S)out[u][a]);
                 if (WPRE) buf_st(rpre, o, (S)hp[u][a]);
+            }
+            if (REC) {
+#pragma unroll
+                for (int q = 0; q < RS; ++q)
+                    buf_st(rrec2, live ? ((unsigned)q * N + n) * (unsigned)sizeof(T) : BUF_OOB, rv[u][q]);
             }
         }
     };
@@ -971,7 +1010,7 @@ __device__ __forceinline__ void adjoint_source(const Obj& ob, const Phys& ph, in
 //   mu = (d f** / d f^{k-1})^T kappa  (+ sampled objective source);
 //   nu_hat^{k-1} = BC^T mu on open nodes.
 // The pre-state f^{k-1}(y) comes from a stored checkpoint (DIRECT), from
-// its moment record (REC: a recomputed D2Q9 segment) or by pulling the
+// its moment record (REC: a recomputed segment) or by pulling the
 // post-collision state G^{k-2} (a recomputed D3Q19 segment). SEED only
 // evaluates the source (terminal condition at the window end).
 template <class L, class S, class T, class A, bool DIRECT, bool SEED, bool REC = false>
@@ -1225,7 +1264,8 @@ __device__ __forceinline__ void gather_index(const Geo& g, int n, int x, int y, 
 // nu_hat^{k_hi - 1} plane by plane over the xy tile grown by one node,
 // into a three-slot LDS ring; step 2 of plane z gathers its kappa from the
 // ring (planes z - 1, z, z + 1) and writes nu_hat^{k_hi - 2} for the tile.
-// Each step pulls its own pre-state f^{k-1} from G^{k-2} in the segment.
+// Each step reads the moments of its own pre-state f^{k-1} from the
+// segment's record of that step (record k - 2 - kseg).
 // Walls on x and y faces are ghost cells written by step 1 (nu_hat_b, or 0
 // on an open node, at y - c_b in plane opp(b) of the slot of plane
 // z - c_bz); a wall on a z face is taken in the step-2 gather itself
@@ -1242,12 +1282,12 @@ __device__ __forceinline__ void gather_index(const Geo& g, int n, int x, int y, 
 // plane.
 template <class S, class T, class A, int TB>
 __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in, A* __restrict__ nu_out,
-                                                    const S* __restrict__ gseg, size_t slot, long kseg,
+                                                    const T* __restrict__ rseg, size_t slot, long kseg,
                                                     const T* __restrict__ sfield, double* __restrict__ sens, Geo g,
                                                     Phys ph, Obj ob, long k_hi, long ns, long dW, double wgt, int ox,
                                                     int oy, int oz, int tiles_x, int tiles_y) {
     using L = D3Q19;
-    using R = typename BufReg<S>::type;
+    constexpr int RS = record_size<L>();
     extern __shared__ unsigned char lds_raw[];
     const int LW = ox + 2, LH = oy + 2, psz = LW * LH;
     double* dsring = reinterpret_cast<double*>(lds_raw);
@@ -1258,10 +1298,9 @@ __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in,
     const int x0 = tx * ox - 1, y0 = ty * oy - 1;
     const int zs = tz * oz, nzc = min(oz, g.nz - zs);
     const int N = g.N, nxy = g.nx * g.ny;
-    const T d0 = (T)g.drho_out;
-    const size_t sbytes = (size_t)L::Q * N * sizeof(S), abytes = (size_t)L::Q * N * sizeof(A);
-    const BufRsrc rG1 = buf_rsrc(gseg + (size_t)(k_hi - 2 - kseg) * slot, sbytes);   // G^{k_hi - 2}
-    const BufRsrc rG2 = buf_rsrc(gseg + (size_t)(k_hi - 3 - kseg) * slot, sbytes);   // G^{k_hi - 3}
+    const size_t rbytes = (size_t)RS * N * sizeof(T), abytes = (size_t)L::Q * N * sizeof(A);
+    const BufRsrc rR1 = buf_rsrc(rseg + (size_t)(k_hi - 2 - kseg) * slot, rbytes);   // record of f^{k_hi - 1}
+    const BufRsrc rR2 = buf_rsrc(rseg + (size_t)(k_hi - 3 - kseg) * slot, rbytes);   // record of f^{k_hi - 2}
     const BufRsrc rnu = buf_rsrc(nu_in, abytes);
     const BufRsrc rout = buf_rsrc(nu_out, abytes);
     const BufRsrc rs = buf_rsrc(sfield, (size_t)N * sizeof(T));
@@ -1293,8 +1332,8 @@ __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in,
         }
         return z >= 0 && z < g.nz;
     };
-    // step-1 inputs of level j: pre-state, nu_hat gather, s
-    R hp1[L::Q];
+    // step-1 inputs of level j: pre-state record, nu_hat gather, s
+    T r1[RS];
     A nk[L::Q];
     T s1 = (T)0;
     auto load1 = [&](int j) {
@@ -1302,37 +1341,37 @@ __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in,
         const bool ok = level_z(j, z);
         const int zc = ok ? z : 0;
         const bool live = ok && v1;
-        const int n = zc * nxy + c1.n;
+        const unsigned n = (unsigned)(zc * nxy + c1.n);
         const bool zf = !g.per_z && (zc == 0 || zc == g.nz - 1);
-        unsigned e[L::Q];
-        pull_index<L>(g, n, c1.x, c1.y, zc, e);
 #pragma unroll
-        for (int a = 0; a < L::Q; ++a) buf_ld(rG1, live ? e[a] * (unsigned)sizeof(S) : BUF_OOB, hp1[a]);
-        gather_index<L>(g, n, c1.x, c1.y, zc, o1 != 0 && !zf, e);
+        for (int q = 0; q < RS; ++q)
+            buf_ld(rR1, live ? ((unsigned)q * N + n) * (unsigned)sizeof(T) : BUF_OOB, r1[q]);
+        unsigned e[L::Q];
+        gather_index<L>(g, (int)n, c1.x, c1.y, zc, o1 != 0 && !zf, e);
 #pragma unroll
         for (int a = 0; a < L::Q; ++a)
             buf_ld(rnu, live && e[a] != GATHER_ZERO ? e[a] * (unsigned)sizeof(A) : BUF_OOB, nk[a]);
         buf_ld(rs, live ? (unsigned)n * (unsigned)sizeof(T) : BUF_OOB, s1);
     };
-    // step-2 inputs of level k: pre-state and the old sensitivity
-    R hp2[L::Q];
+    // step-2 inputs of level k: pre-state record and the old sensitivity
+    T r2[RS];
     double sold = 0.0;
     auto load2 = [&](int k) {
         const bool ok = k >= 1 && k <= nzc;
         const int z = ok ? zs + k - 1 : 0;
         const bool live = ok && v2;
-        const int n = z * nxy + c2.n;
-        unsigned e[L::Q];
-        pull_index<L>(g, n, c2.x, c2.y, z, e);
+        const unsigned n = (unsigned)(z * nxy + c2.n);
 #pragma unroll
-        for (int a = 0; a < L::Q; ++a) buf_ld(rG2, live ? e[a] * (unsigned)sizeof(S) : BUF_OOB, hp2[a]);
-        buf_ld(rsens, live ? (unsigned)n * 8u : BUF_OOB, sold);
+        for (int q = 0; q < RS; ++q)
+            buf_ld(rR2, live ? ((unsigned)q * N + n) * (unsigned)sizeof(T) : BUF_OOB, r2[q]);
+        buf_ld(rsens, live ? n * 8u : BUF_OOB, sold);
     };
-    // one adjoint node update: pre-state h (post-boundary), kappa -> mu, ds
-    auto update = [&](T (&h)[L::Q], const T (&kap)[L::Q], T s, int oc, T u0, int x, int y, int z, double w,
+    // one adjoint node update: moments of the pre-state (post-boundary),
+    // kappa -> mu, ds
+    auto update = [&](const T (&r)[RS], const T (&kap)[L::Q], T s, int oc, T u0, int x, int y, int z, double w,
                       T (&mu)[L::Q]) {
         Moments<L, T> m;
-        moments<L, T>(h, ph, m);
+        record_moments<L, T>(r, ph, m);
         MomentGrad<L, T> gr;
         gr.gr = 0;
 #pragma unroll
@@ -1352,14 +1391,10 @@ __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in,
         const int oc = zf ? 0 : o1;
         const int slots[3] = {(j + 2) % 3, j % 3, (j + 1) % 3};   // planes z - 1, z, z + 1
         if (!v1) return;
-        T h[L::Q], kap[L::Q], mu[L::Q];
+        T kap[L::Q], mu[L::Q];
 #pragma unroll
-        for (int a = 0; a < L::Q; ++a) {
-            h[a] = from_reg<T>(hp1[a]);
-            kap[a] = (T)nk[a];
-        }
-        if (oc) zou_he_rows<L, T>(oc, u1, d0, h);
-        const T ds = update(h, kap, s1, oc, u1, c1.x, c1.y, z, w1, mu);
+        for (int a = 0; a < L::Q; ++a) kap[a] = (T)nk[a];
+        const T ds = update(r1, kap, s1, oc, u1, c1.x, c1.y, z, w1, mu);
         A* dst = ring + slots[1] * L::Q * psz;
 #pragma unroll
         for (int a = 0; a < L::Q; ++a) dst[a * psz + c1.cell] = (A)mu[a];
@@ -1398,14 +1433,10 @@ __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in,
                     off[a] = refl ? (s0 * L::Q + L::opp[a]) * psz : (sl * L::Q + a) * psz + shift;
                 }
             }
-            T h[L::Q], kap[L::Q];
+            T kap[L::Q];
 #pragma unroll
-            for (int a = 0; a < L::Q; ++a) {
-                h[a] = from_reg<T>(hp2[a]);
-                kap[a] = (T)ring[off[a] + c2.cell];
-            }
-            if (oc) zou_he_rows<L, T>(oc, u2, d0, h);
-            const T ds = update(h, kap, sring[s0 * psz + c2.cell], oc, u2, c2.x, c2.y, z, w2, mu);
+            for (int a = 0; a < L::Q; ++a) kap[a] = (T)ring[off[a] + c2.cell];
+            const T ds = update(r2, kap, sring[s0 * psz + c2.cell], oc, u2, c2.x, c2.y, z, w2, mu);
             snew = (sold + dsring[s0 * psz + c2.cell]) + (double)ds;
         }
         const bool live = ok && v2;
@@ -1419,10 +1450,9 @@ __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in,
     // at level -1 (only loads) so that every pass issues the same memory
     // operations.
 #pragma unroll
-    for (int a = 0; a < L::Q; ++a) {
-        hp1[a] = hp2[a] = (R)0;
-        nk[a] = (A)0;
-    }
+    for (int q = 0; q < RS; ++q) r1[q] = r2[q] = (T)0;
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) nk[a] = (A)0;
     for (int j = -1; j <= nzc + 1; ++j) {
         step1(j);
         load1(j + 1);
@@ -1572,7 +1602,7 @@ static void launch_tb(const StepLaunch& a) {
     launch_tb_ps<S, T, SAMPLE, WPRE, 1024, ALLOUT, 0>(a, tiles_x, tiles_y, lds);
 }
 
-template <class S, class T, bool SAMPLE, bool WPRE>
+template <class S, class T, bool SAMPLE, bool WPRE, bool REC = false>
 static void launch_tbz(const StepLaunch& a) {
     using LT = typename TbLds<S, T>::type;
     const Geo& g = a.geo;
@@ -1583,9 +1613,10 @@ static void launch_tbz(const StepLaunch& a) {
     const dim3 grid(tiles_x * tiles_y * tiles_z);
     const int nt = tbz_threads(a.tile_x, a.tile_y), u = tbz_cells(a.tile_x, a.tile_y);
 #define LBM_TBZ(TB, U)                                                                                          \
-    hipLaunchKernelGGL((k_step_tbz<S, T, SAMPLE, WPRE, TB, U>), grid, dim3(TB), lds, a.stream,                  \
+    hipLaunchKernelGGL((k_step_tbz<S, T, SAMPLE, WPRE, TB, U, REC>), grid, dim3(TB), lds, a.stream,             \
                        (const S*)a.gin, (S*)a.gout, (S*)a.pre, (const T*)a.s, g, a.ph, a.ob, a.partials,        \
-                       a.part_stride, a.tile_x, a.tile_y, a.tile_z, tiles_x, tiles_y)
+                       a.part_stride, a.tile_x, a.tile_y, a.tile_z, tiles_x, tiles_y, (T*)a.rec,                \
+                       a.rec_slot / sizeof(T))
     if (nt == 256) {
         LBM_TBZ(256, 1);
     } else if (u == 1) {
@@ -1604,8 +1635,11 @@ static hipError_t step_t(const StepLaunch& a) {
     S* pre = (S*)a.pre;
     const T* sf = (const T*)a.s;
     if (L::D == 3 && a.nsteps > 1) {
-        if (a.nsteps != 2 || a.rec) return hipErrorInvalidValue;
-        if (a.sample) {
+        if (a.nsteps != 2) return hipErrorInvalidValue;
+        if (a.rec) {
+            if (a.sample || pre) return hipErrorInvalidValue;
+            launch_tbz<S, T, false, false, true>(a);
+        } else if (a.sample) {
             if (pre) launch_tbz<S, T, true, true>(a);
             else launch_tbz<S, T, true, false>(a);
         } else {
@@ -1659,8 +1693,9 @@ static hipError_t adj_t(const AdjLaunch& a) {
         const int tiles_z = (g.nz + a.tile_z - 1) / a.tile_z;
         const size_t lds = adj_tbz_lds_bytes(a.tile_x, a.tile_y, sizeof(A), sizeof(T));
         const dim3 grid(tiles_x * tiles_y * tiles_z);
-        const S* gs = (const S*)a.gseg;
-        const size_t slot = a.slot / sizeof(S);
+        if (!a.rec) return hipErrorInvalidValue;          // the segments are moment records
+        const T* gs = (const T*)a.gseg;
+        const size_t slot = a.slot / sizeof(T);
 #define LBM_ADJ_TBZ(TBV)                                                                                      \
     hipLaunchKernelGGL((k_adjoint_tbz<S, T, A, TBV>), grid, dim3(TBV), lds, a.stream, nin, nout, gs, slot,      \
                        a.kseg, sf, a.sens, g, a.ph, a.ob, a.k_hi, a.ns, a.dW, a.wgt, a.tile_x, a.tile_y,        \
@@ -1681,7 +1716,7 @@ static hipError_t adj_t(const AdjLaunch& a) {
         const int ps = tb_plane(a.nsteps, a.tile_x, a.tile_y, sizeof(T), sizeof(T), (size_t)a.tile_x * a.tile_y * 8);
         const int tb = tb_threads(a.nsteps, a.tile_x, a.tile_y);
         const dim3 grid(tiles_x * tiles_y);
-        if (!a.rec) return hipErrorInvalidValue;          // the D2Q9 segments are moment records
+        if (!a.rec) return hipErrorInvalidValue;          // the segments are moment records
         const T* gs = (const T*)a.gseg;
         const size_t slot = a.slot / sizeof(T);
 #define LBM_ADJ_TB(TBV, PSV)                                                                                \
@@ -1928,6 +1963,7 @@ static hipError_t tbz_attr(int b) {
     if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tbz<S, T, true, false, NT, U>, at, b);
     if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tbz<S, T, false, true, NT, U>, at, b);
     if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tbz<S, T, true, true, NT, U>, at, b);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_step_tbz<S, T, false, false, NT, U, true>, at, b);
     return e;
 }
 

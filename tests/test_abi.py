@@ -79,6 +79,25 @@ def test_workspace_layout(B):
     assert n < fixed + 2 * 2 * Q * N * 4 + 64 * 1024 + 20 * 3 * 8 * 8
 
 
+@pytest.mark.parametrize("prec,ss,cs", [(0, 8, 8), (1, 4, 4), (2, 2, 4)])
+def test_workspace_layout_3d(B, prec, ss, cs):
+    """D3Q19: the records hold 10 values per node (drho, j, Pi) in the
+    compute precision, whatever the storage precision."""
+    from paper_2608_19617_amd import workloads as W
+    from paper_2608_19617_amd.solver import make_config
+    w = W.cylinder_3d(nx=24, ny=12, nz=6, radius=3, center=(8, 6), window_len=20, sample_every=5,
+                      ckpt_every=5, n_windows=2)
+    cfg, keep = make_config(w, ("f64", "f32", "f16s")[prec])
+    st, n = _bytes(B, cfg)
+    assert st == B.LBM_OK
+    N, Q = 24 * 12 * 6, 19
+    state = -(-Q * N * ss // 256) * 256
+    record = -(-10 * N * cs // 256) * 256
+    fixed = (2 + 2 * 4 + 2) * state + 4 * record
+    assert n >= fixed
+    assert n < fixed + 2 * 2 * Q * N * 8 + 64 * 1024 + 20 * 3 * 8 * 8 + 4 * N * 8
+
+
 @pytest.mark.parametrize("field,value", [
     ("tau", 0.5), ("tau", float("nan")), ("c_smag", -0.1), ("window_len", 0),
     ("sample_every", 3), ("ckpt_every", 3), ("max_windows", 0), ("eps", float("nan")),
