@@ -286,8 +286,8 @@ lbm_status lbm_set_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y);
 
 /* Temporal blocking of D3Q19 forward launches: nsteps = 2 advances two
  * steps per launch (the recompute of the adjoint sweep too, storing the
- * moment records of both steps). A workgroup owns tile_x x tile_y nodes in x and y and tile_z
- * consecutive z planes; it takes the first step plane by
+ * moment records of both steps). A workgroup owns tile_x x tile_y nodes in
+ * x and y and tile_z consecutive z planes; it takes the first step plane by
  * plane over the tile grown by one node in x and y, keeping three planes of
  * that state in LDS (walls on x and y faces as ghost cells, as for D2Q9),
  * and the second step of each plane as soon as the plane above is ready.
@@ -295,18 +295,18 @@ lbm_status lbm_set_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y);
  * (tile_x + 2) * (tile_y + 2) <= 1024 and 3 (tile_x + 2)(tile_y + 2) x
  * (19 state values in the storage-rounded LDS type + one compute-type
  * value) within 159 KB, and a state (19 x nodes x storage bytes) and a
- * moment record (10 x nodes x compute bytes) below 4 GB each. Samples, checkpoints and window ends fall on a launch's last step as
- * in 2D. Adjoint launches stay single-step. Default (set by lbm_init): FP32
- * grids of more than 2M nodes take 2 steps on 32 x 13 tiles, with the z run
- * that lets the blocks fill the compute units in nearly whole rounds with
- * the fewest halo planes; other D3Q19 contexts take single steps. Errors:
- * LBM_E_INVALID for a D2Q9 context or out-of-range arguments, LBM_E_HIP if
- * the LDS opt-in fails. */
+ * moment record (10 x nodes x compute bytes) below 4 GB each. Samples,
+ * checkpoints and window ends fall on a launch's last step as in 2D.
+ * Default (set by lbm_init): FP32 grids of more than 2M nodes take 2 steps
+ * on 32 x 13 tiles, with the z run that lets the blocks fill the compute
+ * units in nearly whole rounds with the fewest halo planes; other D3Q19
+ * contexts take single steps. Errors: LBM_E_INVALID for a D2Q9 context or
+ * out-of-range arguments, LBM_E_HIP if the LDS opt-in fails. */
 lbm_status lbm_set_blocking_3d(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y, int tile_z);
 
 /* Blocking of the adjoint launches that read their pre-states' moment
- * records from a recomputed segment (D2Q9 only): up to nsteps reverse steps per launch on
- * tile_x x tile_y output tiles, the adjoint populations (FP32, or FP64 for
+ * records from a recomputed segment (D2Q9 only): up to nsteps reverse
+ * steps per launch on tile_x x tile_y output tiles, the adjoint populations (FP32, or FP64 for
  * LBM_F64) of the tile and its halo and an FP64 sensitivity plane of the
  * tile in LDS. nsteps = 1 turns it off. Requires tile_x * tile_y >= 256 and
  * tile_x * tile_y * 8 bytes plus 19 R values of the adjoint type plus the
@@ -315,19 +315,22 @@ lbm_status lbm_set_blocking_3d(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y,
  * out-of-range arguments, LBM_E_HIP if the LDS opt-in fails. */
 lbm_status lbm_set_adjoint_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y);
 
-/* Blocking of the D3Q19 adjoint launches that read their pre-states' moment
- * records from a recomputed segment: nsteps = 2 takes two reverse steps per launch. A
- * workgroup owns tile_x x tile_y nodes in x and y and tile_z consecutive z
- * planes; the first step runs plane by plane over the tile grown by one
- * node in x and y, keeping three planes of adjoint populations in LDS
- * (walls on x and y faces as ghost cells, 0 behind open faces), and the
- * second gathers from them; each step reads its own pre-state's record from
- * the segment, and the tile's sensitivity takes one FP64 read-modify-write per
- * launch. nsteps = 1 turns it off. Requires at least 256 nodes per block,
- * (tile_x + 2) * (tile_y + 2) <= 512 (256 for LBM_F64), 3 (tile_x + 2) x
- * (tile_y + 2) x (8 + one compute-type value + 19 adjoint values) bytes
- * within 159 KB, and a moment record and the adjoint populations below
- * 4 GB each. Errors: LBM_E_INVALID for a D2Q9 context or out-of-range
+/* Blocking of the D3Q19 adjoint launches that read their pre-states'
+ * moment records from a recomputed segment: nsteps = 2 takes two reverse
+ * steps per launch. A workgroup owns tile_x x tile_y nodes in x and y and
+ * tile_z consecutive z planes; the first step runs plane by plane over the
+ * tile grown by one node in x and y, keeping three planes of adjoint
+ * populations in LDS (walls on x and y faces as ghost cells, 0 behind open
+ * faces), and the second gathers from them; each step reads its own
+ * pre-state's record from the segment, and the tile's sensitivity takes
+ * one FP64 read-modify-write per launch. nsteps = 1 turns it off. Requires
+ * at least 256 nodes per block, (tile_x + 2) * (tile_y + 2) <= 512 (256
+ * for LBM_F64), 3 (tile_x + 2) x (tile_y + 2) x (8 + one compute-type
+ * value + 19 adjoint values) bytes within 159 KB, and a moment record and
+ * the adjoint populations below 4 GB each. Default (set by lbm_init): FP32
+ * and FP16S grids of more than 2M nodes take 2 steps on the forward
+ * default's 32 x 13 tiles and z runs; FP64 and smaller grids take single
+ * steps. Errors: LBM_E_INVALID for a D2Q9 context or out-of-range
  * arguments, LBM_E_HIP if the LDS opt-in fails. */
 lbm_status lbm_set_adjoint_blocking_3d(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y, int tile_z);
 

@@ -1332,11 +1332,18 @@ __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in,
         }
         return z >= 0 && z < g.nz;
     };
-    // step-1 inputs of level j: pre-state record, nu_hat gather, s
-    T r1[RS];
-    A nk[L::Q];
-    T s1 = (T)0;
-    auto load1 = [&](int j) {
+    // step-1 inputs of a level: pre-state record, nu_hat gather, s
+    struct In1 {
+        T r[RS];
+        A nk[L::Q];
+        T s;
+    };
+    // step-2 inputs of a level: pre-state record and the old sensitivity
+    struct In2 {
+        T r[RS];
+        double sold;
+    };
+    auto load1 = [&](int j, In1& in) {
         int z;
         const bool ok = level_z(j, z);
         const int zc = ok ? z : 0;
@@ -1345,26 +1352,23 @@ __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in,
         const bool zf = !g.per_z && (zc == 0 || zc == g.nz - 1);
 #pragma unroll
         for (int q = 0; q < RS; ++q)
-            buf_ld(rR1, live ? ((unsigned)q * N + n) * (unsigned)sizeof(T) : BUF_OOB, r1[q]);
+            buf_ld(rR1, live ? ((unsigned)q * N + n) * (unsigned)sizeof(T) : BUF_OOB, in.r[q]);
         unsigned e[L::Q];
         gather_index<L>(g, (int)n, c1.x, c1.y, zc, o1 != 0 && !zf, e);
 #pragma unroll
         for (int a = 0; a < L::Q; ++a)
-            buf_ld(rnu, live && e[a] != GATHER_ZERO ? e[a] * (unsigned)sizeof(A) : BUF_OOB, nk[a]);
-        buf_ld(rs, live ? (unsigned)n * (unsigned)sizeof(T) : BUF_OOB, s1);
+            buf_ld(rnu, live && e[a] != GATHER_ZERO ? e[a] * (unsigned)sizeof(A) : BUF_OOB, in.nk[a]);
+        buf_ld(rs, live ? (unsigned)n * (unsigned)sizeof(T) : BUF_OOB, in.s);
     };
-    // step-2 inputs of level k: pre-state record and the old sensitivity
-    T r2[RS];
-    double sold = 0.0;
-    auto load2 = [&](int k) {
+    auto load2 = [&](int k, In2& in) {
         const bool ok = k >= 1 && k <= nzc;
         const int z = ok ? zs + k - 1 : 0;
         const bool live = ok && v2;
         const unsigned n = (unsigned)(z * nxy + c2.n);
 #pragma unroll
         for (int q = 0; q < RS; ++q)
-            buf_ld(rR2, live ? ((unsigned)q * N + n) * (unsigned)sizeof(T) : BUF_OOB, r2[q]);
-        buf_ld(rsens, live ? n * 8u : BUF_OOB, sold);
+            buf_ld(rR2, live ? ((unsigned)q * N + n) * (unsigned)sizeof(T) : BUF_OOB, in.r[q]);
+        buf_ld(rsens, live ? n * 8u : BUF_OOB, in.sold);
     };
     // one adjoint node update: moments of the pre-state (post-boundary),
     // kappa -> mu, ds
@@ -1384,7 +1388,7 @@ __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in,
         if (oc) zou_he_adjoint_rows<L, T>(oc, u0, mu);
         return ds;
     };
-    auto step1 = [&](int j) {
+    auto step1 = [&](int j, const In1& in) {
         int z;
         if (!level_z(j, z)) return;
         const bool zf = !g.per_z && (z == 0 || z == g.nz - 1);
@@ -1393,12 +1397,12 @@ __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in,
         if (!v1) return;
         T kap[L::Q], mu[L::Q];
 #pragma unroll
-        for (int a = 0; a < L::Q; ++a) kap[a] = (T)nk[a];
-        const T ds = update(r1, kap, s1, oc, u1, c1.x, c1.y, z, w1, mu);
+        for (int a = 0; a < L::Q; ++a) kap[a] = (T)in.nk[a];
+        const T ds = update(in.r, kap, in.s, oc, u1, c1.x, c1.y, z, w1, mu);
         A* dst = ring + slots[1] * L::Q * psz;
 #pragma unroll
         for (int a = 0; a < L::Q; ++a) dst[a * psz + c1.cell] = (A)mu[a];
-        sring[slots[1] * psz + c1.cell] = s1;
+        sring[slots[1] * psz + c1.cell] = in.s;
         if (own1) dsring[slots[1] * psz + c1.cell] = (double)ds;
         if (f1) {
             // ghost cells of the adjoint wall rule (0 on an open node)
@@ -1409,7 +1413,7 @@ __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in,
             tbz_ghosts<A, T, -1>(g, ring, psz, LW, LH, slots, c1, mu);
         }
     };
-    auto step2 = [&](int k) {
+    auto step2 = [&](int k, const In2& in) {
         const bool ok = k >= 1 && k <= nzc;
         const int z = ok ? zs + k - 1 : 0;
         const int n = z * nxy + c2.n;
@@ -1436,8 +1440,8 @@ __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in,
             T kap[L::Q];
 #pragma unroll
             for (int a = 0; a < L::Q; ++a) kap[a] = (T)ring[off[a] + c2.cell];
-            const T ds = update(r2, kap, sring[s0 * psz + c2.cell], oc, u2, c2.x, c2.y, z, w2, mu);
-            snew = (sold + dsring[s0 * psz + c2.cell]) + (double)ds;
+            const T ds = update(in.r, kap, sring[s0 * psz + c2.cell], oc, u2, c2.x, c2.y, z, w2, mu);
+            snew = (in.sold + dsring[s0 * psz + c2.cell]) + (double)ds;
         }
         const bool live = ok && v2;
 #pragma unroll
@@ -1445,21 +1449,43 @@ __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in,
             buf_st(rout, live ? ((unsigned)a * N + (unsigned)n) * (unsigned)sizeof(A) : BUF_OOB, (A)mu[a]);
         buf_st(rsens, live ? (unsigned)n * 8u : BUF_OOB, snew);
     };
-    // ring level j: step 1 of level j, the step-1 loads of level j + 1, then
-    // step 2 of level j - 1 and the step-2 loads of level j. The loop starts
-    // at level -1 (only loads) so that every pass issues the same memory
-    // operations.
+    In1 a1, b1;
+    In2 a2, b2;
 #pragma unroll
-    for (int q = 0; q < RS; ++q) r1[q] = r2[q] = (T)0;
+    for (int q = 0; q < RS; ++q) a1.r[q] = b1.r[q] = a2.r[q] = b2.r[q] = (T)0;
 #pragma unroll
-    for (int a = 0; a < L::Q; ++a) nk[a] = (A)0;
-    for (int j = -1; j <= nzc + 1; ++j) {
-        step1(j);
-        load1(j + 1);
-        lds_barrier();
-        step2(j - 1);
-        load2(j);
-        lds_barrier();
+    for (int a = 0; a < L::Q; ++a) a1.nk[a] = b1.nk[a] = (A)0;
+    a1.s = b1.s = (T)0;
+    a2.sold = b2.sold = 0.0;
+    if constexpr (sizeof(A) == 4) {
+        // ring level j: step 1 of level j from its input set, the step-1
+        // loads of level j + 2 into that set, then step 2 of level j - 1
+        // and the step-2 loads of level j + 1 into its set. Two sets of each
+        // keep the loads of two levels in flight; the loop is unrolled by
+        // two so that each set has fixed registers, and starts at level -2
+        // (only loads) so that every pass issues the same memory operations.
+        auto pass = [&](int j, In1& i1, In2& i2) {
+            step1(j, i1);
+            load1(j + 2, i1);
+            lds_barrier();
+            step2(j - 1, i2);
+            load2(j + 1, i2);
+            lds_barrier();
+        };
+        for (int j = -2; j <= nzc + 1; j += 2) {
+            pass(j, a1, b2);
+            pass(j + 1, b1, a2);
+        }
+    } else {
+        // FP64 (no registers for a second set): one level ahead, from -1
+        for (int j = -1; j <= nzc + 1; ++j) {
+            step1(j, a1);
+            load1(j + 1, a1);
+            lds_barrier();
+            step2(j - 1, a2);
+            load2(j, a2);
+            lds_barrier();
+        }
     }
 }
 
