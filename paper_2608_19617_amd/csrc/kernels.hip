@@ -1010,9 +1010,9 @@ __device__ __forceinline__ void adjoint_source(const Obj& ob, const Phys& ph, in
 //   mu = (d f** / d f^{k-1})^T kappa  (+ sampled objective source);
 //   nu_hat^{k-1} = BC^T mu on open nodes.
 // The pre-state f^{k-1}(y) comes from a stored checkpoint (DIRECT), from
-// its moment record (REC: a recomputed segment) or by pulling the
-// post-collision state G^{k-2} (a recomputed D3Q19 segment). SEED only
-// evaluates the source (terminal condition at the window end).
+// its moment record (REC: a recomputed segment) or, for SEED, by pulling
+// the post-collision state G^{k-2}; SEED only evaluates the source
+// (terminal condition at the window end).
 template <class L, class S, class T, class A, bool DIRECT, bool SEED, bool REC = false>
 __global__ __launch_bounds__(BLOCK) void k_adjoint(const A* __restrict__ nu_in, A* __restrict__ nu_out,
                                                    const S* __restrict__ state, const T* __restrict__ sfield,
@@ -1776,7 +1776,7 @@ static hipError_t adj_t(const AdjLaunch& a) {
     } else if (a.rec) {
         hipLaunchKernelGGL((k_adjoint<L, S, T, A, false, false, true>), gr, dim3(BLOCK), 0, a.stream, nin, nout, st, sf, a.sens, g, a.ph, a.ob, a.src_w);
     } else {
-        hipLaunchKernelGGL((k_adjoint<L, S, T, A, false, false>), gr, dim3(BLOCK), 0, a.stream, nin, nout, st, sf, a.sens, g, a.ph, a.ob, a.src_w);
+        return hipErrorInvalidValue;   // a transition reads a checkpoint or a moment record
     }
     return hipGetLastError();
 }

@@ -20,7 +20,7 @@ struct StepLaunch {
     int nsteps;            // 1: single step; > 1: temporally blocked launch (D2Q9; 2 for D3Q19)
     int tile_x, tile_y;    // output tile of a blocked launch
     int tile_z;            // D3Q19: two steps on tile_x x tile_y tiles, tile_z planes per workgroup
-    void* rec;             // recompute (D2Q9): the moment record of step t's pre-collision state goes
+    void* rec;             // recompute: the moment record of step t's pre-collision state goes
     size_t rec_slot;       // to rec + (t-1) * rec_slot bytes (compute type, record_size planes of N)
     Geo geo;
     Phys ph;
@@ -32,15 +32,15 @@ struct AdjLaunch {
     int lattice, prec;
     const void* nu_in;     // nu_hat^k
     void* nu_out;          // nu_hat^{k-1}
-    const void* state;     // f^{k-1} (direct), its moment record (rec) or G^{k-2} (pull)
+    const void* state;     // f^{k-1} (direct), its moment record (rec) or the G it is pulled from (seed)
     const void* s;
     double* sens;
     int direct, seed;
-    int rec;               // D2Q9 segments: state / gseg hold moment records, slot bytes apart
+    int rec;               // state / gseg hold moment records, slot bytes apart
     double src_w;          // weight of the objective source on f^{k-1} (0: none)
     // blocked launch (nsteps > 1; D3Q19: 2): steps k_hi .. k_hi - nsteps + 1, each
-    // reading its pre-state at gseg + (k - 2 - kseg) * slot bytes (D2Q9: the record
-    // R^{k-1}; D3Q19: G^{k-2}, pulled)
+    // reading the moment record of its pre-state f^{k-1} at gseg + (k - 2 - kseg) * slot
+    // bytes
     int nsteps, tile_x, tile_y;
     int tile_z;            // D3Q19 (nsteps = 2): z planes per workgroup
     const void* gseg;
