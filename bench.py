@@ -240,11 +240,12 @@ def precision_compare(w, ref_prec, res_ref, args, torch, Solver):
     return out
 
 
-# Algorithmic bytes per update on D3Q19 (FP32 storage): forward 19 * 4 * 2 + 4;
-# adjoint 19 * 4 * 2 + 19 * 4 + 4 + 16.
+# Algorithmic bytes per update on D3Q19: the forward reads and writes the 19
+# populations and reads s; the adjoint reads and writes the 19 adjoint
+# populations, reads the moment record (10 values of the compute type) of its
+# pre-state and s, and read-modify-writes the FP64 sensitivity; the recompute
+# is a forward step that also writes the record.
 FWD_BYTES_3D = {"f32": 19 * 4 * 2 + 4, "f64": 19 * 8 * 2 + 8, "f16s": 19 * 2 * 2 + 4}
-# the adjoint reads the moment record (10 values) of its pre-state; the
-# recompute writes it beside the state
 ADJ_BYTES_3D = {"f32": 19 * 4 * 2 + 10 * 4 + 4 + 16, "f64": 19 * 8 * 2 + 10 * 8 + 8 + 16,
                 "f16s": 19 * 4 * 2 + 10 * 4 + 4 + 16}
 REC_BYTES_3D = {p: FWD_BYTES_3D[p] + 10 * (8 if p == "f64" else 4) for p in FWD_BYTES_3D}
