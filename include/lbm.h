@@ -328,9 +328,10 @@ lbm_status lbm_set_adjoint_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int ti
  * for LBM_F64), 3 (tile_x + 2) x (tile_y + 2) x (8 + one compute-type
  * value + 19 adjoint values) bytes within 159 KB, and a moment record and
  * the adjoint populations below 4 GB each. Default (set by lbm_init): FP32
- * and FP16S grids of more than 2M nodes take 2 steps on the forward
- * default's 32 x 13 tiles and z runs; FP64 and smaller grids take single
- * steps. Errors: LBM_E_INVALID for a D2Q9 context or out-of-range
+ * and FP16S grids of more than 2M nodes take 2 steps on 32 x 13 or 48 x 8
+ * tiles, whichever has the shorter path per compute unit (rounds of
+ * workgroups times the step-1 region of a block) with its z run chosen as
+ * for the forward; FP64 and smaller grids take single steps. Errors: LBM_E_INVALID for a D2Q9 context or out-of-range
  * arguments, LBM_E_HIP if the LDS opt-in fails. */
 lbm_status lbm_set_adjoint_blocking_3d(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y, int tile_z);
 

@@ -535,11 +535,16 @@ lbm_status set_adj_blocking_3d(lbm_ctx* c, int nsteps, int tile_x, int tile_y, i
 // compute units' rounds that the tiles x c blocks fill (one block per
 // compute unit) and (oz + 1) / oz the extra work of the two halo planes
 // per run of oz planes.
-static int default_z_run(lbm_ctx* c, int tile_x, int tile_y) {
+static int compute_units() {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
         cus = 256;
+    return cus;
+}
+
+static int default_z_run(lbm_ctx* c, int tile_x, int tile_y) {
+    const int cus = compute_units();
     const long tiles = (long)((c->cfg.nx + tile_x - 1) / tile_x) * ((c->cfg.ny + tile_y - 1) / tile_y);
     const int nz = c->cfg.nz;
     int best = nz;
@@ -557,6 +562,18 @@ static int default_z_run(lbm_ctx* c, int tile_x, int tile_y) {
         }
     }
     return best;
+}
+
+// Critical path of a two-step z-marching launch per compute unit, in cell
+// updates of one step: rounds of workgroups times the step-1 region of a
+// block (the tile grown by one node in x and y, its run grown by one plane
+// on each side).
+static double tbz_cost(lbm_ctx* c, int tile_x, int tile_y, int oz) {
+    const int cus = compute_units();
+    const long tiles = (long)((c->cfg.nx + tile_x - 1) / tile_x) * ((c->cfg.ny + tile_y - 1) / tile_y);
+    const long blocks = tiles * ((c->cfg.nz + oz - 1) / oz);
+    const long rounds = (blocks + cus - 1) / cus;
+    return (double)rounds * (tile_x + 2.0) * (tile_y + 2.0) * (oz + 2.0);
 }
 
 lbm_status set_adj_blocking(lbm_ctx* c, int nsteps, int tile_x, int tile_y) {
@@ -924,11 +941,22 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
     if (cfg->lattice == LBM_D3Q19 && cfg->prec != LBM_F64 && L.N > 2000000 && cfg->nx >= 32 && cfg->ny >= 13 &&
         (size_t)10 * L.N * L.cs <= TBZ_STATE_MAX && (size_t)L.Q * L.N * L.as <= TBZ_STATE_MAX) {
         // D3Q19 adjoint with FP32 adjoint populations on large grids: two
-        // reverse steps per launch on the same tiles and z runs (measured on
-        // MI355X on the 384 x 128 x 128 channel: 247 us per reverse step
-        // against 265 for single steps, FP32; 243 against 260, FP16S). FP64
-        // stays single-step (its blocked launches measured slower).
-        if ((st = set_adj_blocking_3d(c, 2, 32, 13, default_z_run(c, 32, 13))) != LBM_OK) return bail(st);
+        // reverse steps per launch, on 32 x 13 tiles or, where its blocks fill
+        // the compute units better for less halo work, 48 x 8 (measured on
+        // MI355X on the 384 x 128 x 128 channel, FP32: 236 us per reverse
+        // step on 48 x 8 tiles in z runs of 64, 256 workgroups, against 245
+        // on 32 x 13, 240 workgroups, and 265 for single steps). FP64 stays
+        // single-step (its blocked launches measured slower).
+        int atx = 32, aty = 13, aoz = default_z_run(c, 32, 13);
+        if (cfg->nx >= 48) {
+            const int oz = default_z_run(c, 48, 8);
+            if (tbz_cost(c, 48, 8, oz) < tbz_cost(c, atx, aty, aoz)) {
+                atx = 48;
+                aty = 8;
+                aoz = oz;
+            }
+        }
+        if ((st = set_adj_blocking_3d(c, 2, atx, aty, aoz)) != LBM_OK) return bail(st);
     }
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
