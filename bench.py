@@ -280,9 +280,10 @@ def hbm_suite(args, torch):
                             max_windows=2)
         cases.append(("cylinder wake 8192x2048 (C3 x4 per axis)", w, prec, FWD_BYTES[prec], ADJ_BYTES[prec],
                       REC_BYTES[prec]))
-    w3 = W.cylinder_3d(window_len=100, sample_every=20, ckpt_every=20, n_windows=2)
-    cases.append(("cylinder 3D 384x128x128 D3Q19", w3, "f32", FWD_BYTES_3D["f32"], ADJ_BYTES_3D["f32"],
-                  REC_BYTES_3D["f32"]))
+    for prec in ("f32", "f16s", "f64"):
+        w3 = W.cylinder_3d(window_len=100, sample_every=20, ckpt_every=20, n_windows=2)
+        cases.append(("cylinder 3D 384x128x128 D3Q19", w3, prec, FWD_BYTES_3D[prec], ADJ_BYTES_3D[prec],
+                      REC_BYTES_3D[prec]))
     for name, w, prec, fb, ab, rb in cases:
         sv = Solver(w, prec)
         sv.set_gamma(w.gamma)
