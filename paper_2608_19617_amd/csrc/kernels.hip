@@ -61,6 +61,105 @@ __device__ __forceinline__ void block_sum(double v[NC], double* out) {
 // term removes 2 s j from the fluid) over the force box. The window field
 // accumulator receives dW/|W| times 2 j_x (drag: the explicit dD/ds) or u
 // (wake) on its box.
+// Raw buffer access (the range check of a buffer resource): a byte offset
+// of BUF_OOB lies beyond every array, so a store there is dropped and a load
+// returns 0. The z-marching kernel issues all of its global loads and stores
+// this way and unconditionally, so that every plane issues the same sequence
+// of vector memory operations whatever the lane, plane or face; the
+// compiler's count of the loads still in flight is then exact across its
+// branches, and the loads of two planes stay in flight behind the current
+// one. The arrays must be smaller than BUF_OOB bytes (checked by the host).
+constexpr unsigned BUF_OOB = 0xFFFFFFF0u;
+using BufRsrc = __amdgpu_buffer_rsrc_t;
+using BufU2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(BufRsrc(), 0, 0, 0));
+
+// The offset passes through an empty asm statement, so that the compiler
+// cannot see its out-of-range value and split one access into branches.
+__device__ __forceinline__ unsigned buf_off(unsigned off) {
+    asm("" : "+v"(off));
+    return off;
+}
+
+__device__ __forceinline__ BufRsrc buf_rsrc(const void* p, size_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)(unsigned)bytes, 0x00020000);
+}
+__device__ __forceinline__ void buf_ld(BufRsrc r, unsigned off, float& v) {
+    v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)buf_off(off), 0, 0));
+}
+__device__ __forceinline__ void buf_ld(BufRsrc r, unsigned off, double& v) {
+    v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)buf_off(off), 0, 0));
+}
+__device__ __forceinline__ void buf_ld(BufRsrc r, unsigned off, _Float16& v) {
+    v = __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)buf_off(off), 0, 0));
+}
+// FP16 storage is loaded into a full 32-bit register (zero-extended), so
+// that two values in flight never share one register.
+__device__ __forceinline__ void buf_ld(BufRsrc r, unsigned off, unsigned& v) {
+    v = (unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, (int)buf_off(off), 0, 0);
+}
+template <class S>
+struct BufReg {
+    using type = S;
+};
+template <>
+struct BufReg<_Float16> {
+    using type = unsigned;
+};
+template <class T, class R>
+__device__ __forceinline__ T from_reg(R v) {
+    if constexpr (sizeof(R) == 4 && !std::is_floating_point<R>::value)
+        return (T)__builtin_bit_cast(_Float16, (unsigned short)v);
+    else
+        return (T)v;
+}
+
+__device__ __forceinline__ void buf_st(BufRsrc r, unsigned off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)buf_off(off), 0, 0);
+}
+__device__ __forceinline__ void buf_st(BufRsrc r, unsigned off, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(BufU2, v), r, (int)buf_off(off), 0, 0);
+}
+__device__ __forceinline__ void buf_st(BufRsrc r, unsigned off, _Float16 v) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)buf_off(off), 0, 0);
+}
+
+// Pull of a node for the single-step kernels. An interior node reads its Q
+// populations through one buffer resource per plane whose base already
+// holds that plane's uniform source shift (plane a starts at
+// G + a N - off_a), so every load takes the same byte offset n sizeof(S):
+// one vector instruction for all Q addresses instead of the 64-bit address
+// arithmetic of each plain load. n - off_a lies in [0, N) for an interior
+// node, so every access stays inside plane a. Boundary nodes take pull().
+template <class L, class S, class T>
+__device__ __forceinline__ void pull_buf(const S* __restrict__ G, const Geo& g, int n, int x, int y, int z,
+                                         T h[L::Q]) {
+    const bool interior = x > 0 && x < g.nx - 1 && y > 0 && y < g.ny - 1 &&
+                          (L::D == 2 || (z > 0 && z < g.nz - 1));
+    if (interior) {
+        const unsigned vo = (unsigned)n * (unsigned)sizeof(S);
+        const size_t pb = (size_t)g.N * sizeof(S);
+#pragma unroll
+        for (int a = 0; a < L::Q; ++a) {
+            const long off = L::cx[a] + (long)L::cy[a] * g.nx + (long)L::cz[a] * g.nx * g.ny;
+            typename BufReg<S>::type v;
+            buf_ld(buf_rsrc(G + ((long)a * g.N - off), pb), vo, v);
+            h[a] = from_reg<T>(v);
+        }
+        return;
+    }
+    pull<L, S, T>(G, g, n, x, y, z, h);
+}
+
+// Store of a node's Q post-collision populations through one buffer
+// resource per plane (the same byte offset n sizeof(S) for every plane).
+template <class L, class S, class T>
+__device__ __forceinline__ void store_buf(S* __restrict__ G, int N, int n, const T out[L::Q]) {
+    const unsigned vo = (unsigned)n * (unsigned)sizeof(S);
+    const size_t pb = (size_t)N * sizeof(S);
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) buf_st(buf_rsrc(G + (size_t)a * N, pb), vo, (S)out[a]);
+}
+
 template <class L, class T>
 __device__ __forceinline__ void node_samples(const Obj& ob, int x, int y, int z, T s, const Moments<L, T>& m,
                                              double v[3]) {
@@ -124,7 +223,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const S* __restrict__ gin, S* __
         node_coords(g, n, x, y, z);
         const int oc = open_code<L>(g, x, y, z);
         T h[L::Q];
-        pull<L, S, T>(gin, g, n, x, y, z, h);
+        pull_buf<L, S, T>(gin, g, n, x, y, z, h);
         if (oc) zou_he<L, T>(g, oc, y, h);
         if (WPRE) {
 #pragma unroll
@@ -137,8 +236,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const S* __restrict__ gin, S* __
         if (SAMPLE) node_samples<L, T>(ob, x, y, z, s, m, v);
         T out[L::Q];
         collide<L, T>(m, s, out);
-#pragma unroll
-        for (int a = 0; a < L::Q; ++a) plane(gout, a, g.N)[(unsigned)n] = (S)out[a];
+        store_buf<L, S, T>(gout, g.N, n, out);
     }
     if (SAMPLE) {
         block_sum<3>(v, partials + 3 * (size_t)blockIdx.x);
@@ -590,67 +688,6 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Raw buffer access (the range check of a buffer resource): a byte offset
-// of BUF_OOB lies beyond every array, so a store there is dropped and a load
-// returns 0. The z-marching kernel issues all of its global loads and stores
-// this way and unconditionally, so that every plane issues the same sequence
-// of vector memory operations whatever the lane, plane or face; the
-// compiler's count of the loads still in flight is then exact across its
-// branches, and the loads of two planes stay in flight behind the current
-// one. The arrays must be smaller than BUF_OOB bytes (checked by the host).
-constexpr unsigned BUF_OOB = 0xFFFFFFF0u;
-using BufRsrc = __amdgpu_buffer_rsrc_t;
-using BufU2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(BufRsrc(), 0, 0, 0));
-
-// The offset passes through an empty asm statement, so that the compiler
-// cannot see its out-of-range value and split one access into branches.
-__device__ __forceinline__ unsigned buf_off(unsigned off) {
-    asm("" : "+v"(off));
-    return off;
-}
-
-__device__ __forceinline__ BufRsrc buf_rsrc(const void* p, size_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)(unsigned)bytes, 0x00020000);
-}
-__device__ __forceinline__ void buf_ld(BufRsrc r, unsigned off, float& v) {
-    v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)buf_off(off), 0, 0));
-}
-__device__ __forceinline__ void buf_ld(BufRsrc r, unsigned off, double& v) {
-    v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)buf_off(off), 0, 0));
-}
-__device__ __forceinline__ void buf_ld(BufRsrc r, unsigned off, _Float16& v) {
-    v = __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)buf_off(off), 0, 0));
-}
-// FP16 storage is loaded into a full 32-bit register (zero-extended), so
-// that two values in flight never share one register.
-__device__ __forceinline__ void buf_ld(BufRsrc r, unsigned off, unsigned& v) {
-    v = (unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, (int)buf_off(off), 0, 0);
-}
-template <class S>
-struct BufReg {
-    using type = S;
-};
-template <>
-struct BufReg<_Float16> {
-    using type = unsigned;
-};
-template <class T, class R>
-__device__ __forceinline__ T from_reg(R v) {
-    if constexpr (sizeof(R) == 4 && !std::is_floating_point<R>::value)
-        return (T)__builtin_bit_cast(_Float16, (unsigned short)v);
-    else
-        return (T)v;
-}
-
-__device__ __forceinline__ void buf_st(BufRsrc r, unsigned off, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)buf_off(off), 0, 0);
-}
-__device__ __forceinline__ void buf_st(BufRsrc r, unsigned off, double v) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(BufU2, v), r, (int)buf_off(off), 0, 0);
-}
-__device__ __forceinline__ void buf_st(BufRsrc r, unsigned off, _Float16 v) {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)buf_off(off), 0, 0);
-}
 
 template <class S, class T, bool SAMPLE, bool WPRE, int TB, int U, bool REC = false>
 __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* __restrict__ gout,
