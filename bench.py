@@ -1,19 +1,25 @@
 """Benchmark of the windowed LBM-LES forward + discrete-adjoint hot path.
 
-Workload: backward-facing step, 800 x 200 D2Q9 nodes, regularized BGK with
-Smagorinsky C_s = 0.1, Re = 800 on the step height, parabolic inlet
-u_max = 0.05, pressure outlet; consecutive windows of 2000 steps sampled
-every 100 steps, criterion 1e-3 on the window-mean pressure drop, at most
-20 windows (40k steps); then the discrete adjoint over the representative
-window (checkpoints every 100 steps in HBM, recompute, adjoint) -> dJ/dgamma.
+Default workload (the largest single-GPU configuration): the D3Q19 cylinder
+channel 384 x 128 x 128 (6.29M nodes; cylinder of radius 16 along z at
+(96, 64); parabolic inlet u_max = 0.05 between walls in y, pressure outlet,
+periodic z; Re = 1000 on the diameter, regularized BGK with Smagorinsky
+C_s = 0.1), FP32 population storage. One benchmark step = set the design
+field (reset to t = 0) -> 20 000 forward steps in 4 windows of 5000 steps
+(samples every 20 steps, the consecutive-window test evaluated at every
+window end, checkpoints every 250 steps in HBM) -> the discrete adjoint over
+the last window (recompute of each 250-step segment from its checkpoint,
+adjoint steps) -> dJ/dgamma. The inputs are resident in HBM before the timed
+region. value = lattice updates per second over the timed steps, counting
+every forward step and every adjoint step of each node once (recompute steps
+are not counted as updates).
 
-One benchmark step = set the design field (reset to t = 0) -> forward window
-loop until the criterion passes -> adjoint over that window. The inputs are
-resident in HBM before the timed region. value = lattice updates per second
-over the timed steps, counting every forward step and every adjoint step of
-each node once (recompute steps are not counted as updates).
+Besides the timed FP32 steps the line carries the kernel rates of the step,
+the roofline of its dominant kernel, one FP64 and one FP16S step (speed and
+the J / dJ/dgamma errors against FP64, from rest and from a shared window
+start) and the CPU oracle on a slab of the same workload.
 
-Prints one JSON line (see the keys below). Single GPU only.
+Prints one JSON line. Single GPU only. --suite selects other measurements.
 """
 
 import argparse
@@ -54,10 +60,12 @@ def parse():
                     help="run one window and its adjoint of the workload plus a 256 MiB device copy "
                          "(for rocprofv3 --pmc byte counters) and exit")
     ap.add_argument("--counters-case", choices=["bfs", "cyl3d"], default="bfs",
-                    help="workload of --counters: the benchmark's backward-facing step (bfs) or 40 "
-                         "forward steps of the D3Q19 channel 384x128x128 in its default launches (cyl3d)")
-    ap.add_argument("--suite", choices=["hbm", "design", "fulltime", "paper", "optimize"], default=None,
-                    help="hbm: rooflines of the forward, recompute and adjoint kernels on grids far "
+                    help="workload of --counters: the backward-facing step (bfs) or the D3Q19 "
+                         "channel 384x128x128 in its default launches, 40 forward steps and the adjoint of "
+                         "their last 20-step window (cyl3d)")
+    ap.add_argument("--suite", choices=["bfs", "hbm", "design", "fulltime", "paper", "optimize"], default=None,
+                    help="bfs: the backward-facing step 800x200 (FP32 vs FP64 window criterion "
+                         "workload) benchmarked to its converged window and adjoint; hbm: rooflines of the forward, recompute and adjoint kernels on grids far "
                          "larger than the caches (one JSON line per configuration) instead of the "
                          "benchmark step; design: timings of the design update (filter + projection, "
                          "chain rule, volume-constrained step); fulltime: one optimisation iteration "
@@ -77,9 +85,10 @@ def counters_run(args, torch):
     from paper_2608_19617_amd import workloads as W
     from paper_2608_19617_amd.solver import Solver
     if args.counters_case == "cyl3d":
-        w = W.cylinder_3d(window_len=40, sample_every=20, ckpt_every=20, n_windows=1)
+        w = W.cylinder_3d(window_len=20, sample_every=20, ckpt_every=20, n_windows=2)
         sv = Solver(w, args.prec)
-        sv.forward(w.window_len)
+        sv.forward(2 * w.window_len)
+        sv.adjoint()
     else:
         w = W.backward_facing_step(max_windows=args.max_windows)
         sv = Solver(w, args.prec)
@@ -104,20 +113,28 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, prec):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None when the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_bfs800x200_{prec}_counters.txt")
+def profile_values(stem):
+    """key = value lines of profiles/<stem>.txt, or {} when the file is absent
+    or the kernel sources changed since its figures were taken (the file
+    records their SHA-256)."""
+    path = os.path.join(ROOT, "profiles", stem + ".txt")
     if not os.path.exists(path):
-        return None
+        return {}
     vals = {}
     for line in open(path):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256") != kernel_source_digest():
-        return None
-    return float(vals["hbm_bytes_per_launch"])
+        return {}
+    return vals
+
+
+def measured_traffic(kernel, prec):
+    """HBM bytes per launch of `kernel` on the backward-facing step from the
+    committed counter summary (None when absent or stale)."""
+    v = profile_values(f"{kernel}_bfs800x200_{prec}_counters").get("hbm_bytes_per_launch")
+    return None if v is None else float(v)
 
 
 def bench_step(sv, w, max_windows):
@@ -184,7 +201,8 @@ def cpu_baseline(w, fwd_per_step, adj_per_step):
 
 def precision_compare(w, ref_prec, res_ref, args, torch, Solver):
     """FP64 and FP16S beside the benchmarked precision: time one benchmark
-    step of each, and the error of J and dJ/dgamma of the same window
+    step of each; the error of J and dJ/dgamma from rest (each precision on
+    its own trajectory from t = 0, on its own W_eff) and of the same window
     computed from the FP64 window-start state. On this workload the window
     means of the pressure drop swing about zero from window to window (an
     acoustic oscillation of the mean density), so besides the error relative
@@ -199,6 +217,7 @@ def precision_compare(w, ref_prec, res_ref, args, torch, Solver):
     rep64, g64, J64 = bench_step(sv64, w, args.max_windows)
     torch.cuda.synchronize()
     t64 = time.perf_counter() - t0
+    g64r = g64.cpu().numpy()          # from rest, FP64's own W_eff
     n_upd64 = rep64["steps_done"] + w.window_len
     Jhist, _, _ = sv64.history()
     j_rms = float(np.sqrt(np.mean(np.square(Jhist))))    # scale of the window means over the run
@@ -223,6 +242,7 @@ def precision_compare(w, ref_prec, res_ref, args, torch, Solver):
         rep, g, J = bench_step(sv, w, args.max_windows)
         torch.cuda.synchronize()
         tp = time.perf_counter() - t0
+        gr = g.cpu().numpy()
         n_upd = rep["steps_done"] + w.window_len
         mlups = w.nodes * n_upd / tp / 1e6
         sv.set_state(f_start, step)
@@ -235,7 +255,10 @@ def precision_compare(w, ref_prec, res_ref, args, torch, Solver):
                      "J_abs_err_vs_f64_same_start": float(abs(Jw - J64w)),
                      "J_err_over_window_J_rms": float(abs(Jw - J64w) / j_rms),
                      "dJdgamma_rel_l2_vs_f64_same_start":
-                         float(np.linalg.norm(gw - g64w) / np.linalg.norm(g64w))}
+                         float(np.linalg.norm(gw - g64w) / np.linalg.norm(g64w)),
+                     "J_rel_err_vs_f64_from_rest": float(abs(J - J64) / abs(J64)),
+                     "dJdgamma_rel_l2_vs_f64_from_rest":
+                         float(np.linalg.norm(gr - g64r) / np.linalg.norm(g64r))}
         sv.close()
     return out
 
@@ -652,34 +675,11 @@ def optimize_suite(args, torch):
                           "V_last": hist[-1]["V"], "J_history": [float("%.6g" % j) for j in J]}), flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "decomposition is designed but not built.", file=sys.stderr)
-        sys.exit(2)
-    import torch
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(1)
-    if args.counters:
-        counters_run(args, torch)
-        return
-    if args.suite == "hbm":
-        hbm_suite(args, torch)
-        return
-    if args.suite == "design":
-        design_suite(args, torch)
-        return
-    if args.suite == "fulltime":
-        fulltime_suite(args, torch)
-        return
-    if args.suite == "paper":
-        paper_suite(args, torch)
-        return
-    if args.suite == "optimize":
-        optimize_suite(args, torch)
-        return
+def bfs_bench(args, torch):
+    """The backward-facing step 800 x 200 (FP32 vs FP64 window-criterion
+    workload): one step = set gamma -> forward windows of 2000 steps until the
+    criterion passes (at most 20) -> adjoint over W_eff (K = 100); the line
+    layout of the default benchmark, on this cache-resident grid."""
     from paper_2608_19617_amd import workloads as W
     from paper_2608_19617_amd.solver import Solver
 
@@ -742,6 +742,297 @@ def main():
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, res["fwd"] // args.steps, res["adj"] // args.steps)
     print(json.dumps(line), flush=True)
+
+
+
+# ----------------------------------------------------- default: C5 channel
+
+C5_SLAB_NZ, C5_SLAB_FWD, C5_SLAB_WIN = 2, 4, 2
+
+
+def c5_workload():
+    """The D3Q19 cylinder channel 384 x 128 x 128: 4 windows of 5000 steps
+    (dW = 20, K = 250), pressure-drop objective and monitor; the window test
+    (eps = 1e-3) is evaluated at every window end, and the run is the fixed
+    20 000 steps with the adjoint over the last window."""
+    from paper_2608_19617_amd import workloads as W
+    w = W.cylinder_3d()
+    w.eps = 1e-3
+    return w
+
+
+def _device_gamma(w, torch):
+    """The design field in the library's node order, resident on the GPU."""
+    from paper_2608_19617_amd.solver import to_device_order
+    return torch.from_numpy(to_device_order(w.gamma.astype("float64"))).to("cuda")
+
+
+def _free(torch, *solvers):
+    for sv in solvers:
+        sv.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def c5_step(sv, w, gamma_dev):
+    sv.set_gamma(gamma_dev)
+    rep = sv.forward(w.max_windows * w.window_len)
+    g, J = sv.adjoint()
+    return rep, g, J
+
+
+def c5_timed(w, gamma_dev, args, torch):
+    from paper_2608_19617_amd.solver import Solver
+    sv = Solver(w, args.prec)
+    for _ in range(args.warmup):
+        c5_step(sv, w, gamma_dev)
+    torch.cuda.synchronize()
+    sv.timing(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rep, g, J = c5_step(sv, w, gamma_dev)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tm = sv.timing(False)
+    Jh, Mh, Rh = sv.history()
+    out = dict(rep=rep, J=J, g=g.cpu().numpy(), dt=dt, tm=tm, J_hist=Jh, M_hist=Mh, rel_hist=Rh,
+               workspace=sv.workspace_bytes)
+    _free(torch, sv)
+    return out
+
+
+def _rel(a, b):
+    import numpy as np
+    return float(np.linalg.norm(np.asarray(a) - b) / np.linalg.norm(b))
+
+
+def c5_precisions(w, gamma_dev, res, args, torch):
+    """FP64 and FP16S beside the timed FP32 run: one step of each from rest
+    (timed; the FP64 state entering the last window is exported on the way,
+    outside the timed parts), then the last window of FP32 and FP16S rerun
+    from that FP64 state. Errors of J and dJ/dgamma against FP64, from rest
+    (each precision on its own trajectory from t = 0) and from the shared
+    window start."""
+    from paper_2608_19617_amd.solver import Solver
+    W_ = w.window_len
+    n_before = (w.max_windows - 1) * W_
+    upd = (w.max_windows * W_ + W_) * w.nodes
+    sv = Solver(w, "f64")
+    sv.set_gamma(gamma_dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sv.forward(n_before)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    f_start, step = sv.get_state()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    sv.forward(W_)
+    g64, J64 = sv.adjoint()
+    torch.cuda.synchronize()
+    t64 = (t1 - t0) + (time.perf_counter() - t2)
+    g64 = g64.cpu().numpy()
+    J64_hist = sv.history()[0]
+    _free(torch, sv)
+    mlups = {"f64": upd / t64 / 1e6, args.prec: upd / (res["dt"] / args.steps) / 1e6}
+    from_rest = {args.prec: (res["J"], res["g"])}
+    for prec in ("f16s", "f32"):
+        if prec in from_rest:
+            continue
+        sv = Solver(w, prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep, g, J = c5_step(sv, w, gamma_dev)
+        torch.cuda.synchronize()
+        mlups[prec] = upd / (time.perf_counter() - t0) / 1e6
+        from_rest[prec] = (J, g.cpu().numpy())
+        _free(torch, sv)
+    out = {"f64": {"mlups": round(mlups["f64"], 1), "J": J64, "window_J": [float(j) for j in J64_hist]}}
+    for prec in ("f32", "f16s"):
+        sv = Solver(w, prec)
+        sv.set_gamma(gamma_dev)
+        sv.set_state(f_start, step)
+        sv.forward(W_)
+        g, J = sv.adjoint()
+        g = g.cpu().numpy()
+        _free(torch, sv)
+        Jr, gr = from_rest[prec]
+        out[prec] = {"mlups": round(mlups[prec], 1), "speedup_vs_f64": round(mlups[prec] / mlups["f64"], 3),
+                     "same_start": {"J_rel_err": abs(J - J64) / abs(J64), "dJdgamma_rel_l2": _rel(g, g64)},
+                     "from_rest": {"J": Jr, "J_rel_err": abs(Jr - J64) / abs(J64),
+                                   "dJdgamma_rel_l2": _rel(gr, g64)}}
+    bars = {"f32": (1e-3, 1e-4), "f16s": (None, 1e-2)}
+    for prec, (bj, bg) in bars.items():
+        ss = out[prec]["same_start"]
+        out[prec]["bars"] = {"J_window_1e-3": None if bj is None else ss["J_rel_err"] <= bj,
+                             "dJdgamma_" + ("1e-4" if prec == "f32" else "1e-2"): ss["dJdgamma_rel_l2"] <= bg}
+    return out
+
+
+def _oracle_slab_worker(nz, n_fwd, n_win):
+    """The oracle as it stands, single-threaded, on a slab of the channel
+    (nz planes of 384 x 128, periodic z): seconds per forward step and per
+    adjoint step (a window gradient over n_win steps minus its forward
+    steps). Runs in a fresh process."""
+    if ROOT not in sys.path:
+        sys.path.insert(0, ROOT)
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from threadpoolctl import threadpool_limits
+    from helpers import oracle_problem
+    from oracle import adjoint as ad
+    from oracle import forward as fw
+    from paper_2608_19617_amd import workloads as W
+    w = W.cylinder_3d(nz=nz, window_len=n_win, sample_every=n_win, ckpt_every=n_win, n_windows=1)
+    with threadpool_limits(limits=1):
+        prob = oracle_problem(w)
+        s = fw.design_map(prob, w.gamma)
+        f = fw.initial_state(prob)
+        t0 = time.perf_counter()
+        for _ in range(n_fwd):
+            f = fw.step(prob, f, s)
+        t_f = (time.perf_counter() - t0) / n_fwd
+        t0 = time.perf_counter()
+        ad.window_gradient(prob, w.gamma, f)
+        t_a = max((time.perf_counter() - t0) / n_win - t_f, 1e-9)
+    return t_f, t_a, w.nodes
+
+
+def c5_cpu_baseline(fwd_per_step, adj_per_step):
+    """The oracle on the host's cores, on slabs of the same workload: one
+    process alone (single thread), then one process per core of the host's
+    share (at most 16) running the same slab at once. Rates are node updates
+    per second in the benchmark step's mix of forward and adjoint steps."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    job = (C5_SLAB_NZ, C5_SLAB_FWD, C5_SLAB_WIN)
+    with ctx.Pool(1) as pool:
+        single = pool.apply(_oracle_slab_worker, job)
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    with ctx.Pool(cores) as pool:
+        every = pool.starmap(_oracle_slab_worker, [job] * cores)
+
+    def rate(t_f, t_a, nodes):
+        return nodes * (fwd_per_step + adj_per_step) / (fwd_per_step * t_f + adj_per_step * t_a) / 1e6
+
+    value = sum(rate(*r) for r in every)
+    t_f, t_a, nodes = single
+    return {"value": round(value, 4), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": (f"FP64 numpy oracle on a {C5_SLAB_NZ}-plane slab (384x128x{C5_SLAB_NZ}, periodic z) of the "
+                       f"same channel: {C5_SLAB_FWD} forward steps and a {C5_SLAB_WIN}-step window gradient per "
+                       f"process, {cores} single-threaded processes at once, rates weighted by the GPU step's mix "
+                       f"of {fwd_per_step} forward + {adj_per_step} adjoint steps"),
+            "single_thread": {"value": round(rate(*single), 4), "fwd_mlups": round(nodes / t_f / 1e6, 4),
+                              "adj_mlups": round(nodes / t_a / 1e6, 4)},
+            "per_core_all_cores": {"fwd_mlups": round(sum(r[2] / r[0] for r in every) / cores / 1e6, 4),
+                                   "adj_mlups": round(sum(r[2] / r[1] for r in every) / cores / 1e6, 4)}}
+
+
+def c5_roofline(tm, N, prec):
+    """Roofline of the dominant kernel of the step (the forward: 20 000 of the
+    step's 25 000 updates), from the HIP-event launch averages of the timed
+    steps; the counter bytes and SQ figures come from the committed profile
+    summary of the same kernel (null when stale)."""
+    fb = FWD_BYTES_3D[prec]
+    if tm["tb_launches"] > 0 and tm["tb_ms"] >= tm["fwd_ms"]:
+        kname = "k_step_tbz (forward, two steps per launch, z-marching)"
+        spl = tm["tb_steps"] / tm["tb_launches"]
+        launch_s = tm["tb_ms"] / tm["tb_launches"] * 1e-3
+        stem = f"k_step_tbz_cyl3d384x128x128_{prec}_counters"
+    else:
+        kname = "k_step (forward, single step)"
+        spl = 1.0
+        launch_s = tm["fwd_ms"] / tm["fwd_launches"] * 1e-3
+        stem = f"k_step_cyl3d384x128x128_{prec}_counters"
+    alg = spl * fb * N
+    achieved = alg / launch_s / 1e9
+    pv = profile_values(stem)
+    traffic = float(pv["hbm_bytes_per_launch"]) if "hbm_bytes_per_launch" in pv else None
+    line = {"bound": pv.get("bound", "hbm"), "kernel": kname, "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "bytes_per_lup": fb, "algorithmic_bytes_per_launch": alg,
+            "steps_per_launch": round(spl, 3), "avg_launch_us": round(launch_s * 1e6, 3)}
+    if traffic is not None:
+        line["traffic_GBs"] = round(traffic / launch_s / 1e9, 1)
+        line["traffic_frac_of_peak"] = round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4)
+    for k in ("valu_busy", "vmem_busy", "waves_per_cu", "binding"):
+        if k in pv:
+            line[k] = pv[k]
+    return line
+
+
+def c5_bench(args, torch):
+    import numpy as np
+    w = c5_workload()
+    N = w.nodes
+    gamma_dev = _device_gamma(w, torch)
+    res = c5_timed(w, gamma_dev, args, torch)
+    tm = res["tm"]
+    fwd_per_step = w.max_windows * w.window_len
+    adj_per_step = w.window_len
+    value = N * (fwd_per_step + adj_per_step) * args.steps / res["dt"] / 1e6
+    fwd_steps = tm["tb_steps"] + tm["fwd_launches"]
+    fwd_s = (tm["tb_ms"] + tm["fwd_ms"]) * 1e-3 / fwd_steps
+    adj_s = tm["adj_ms"] * 1e-3 / tm["adj_steps"]
+    rec_s = tm["rec_ms"] * 1e-3 / max(tm["rec_steps"], 1)
+    p = args.prec
+    kern = {"forward": {"us_per_step": round(fwd_s * 1e6, 2), "mlups": round(N / fwd_s / 1e6, 1),
+                        "bytes_per_lup": FWD_BYTES_3D[p],
+                        "frac_of_hbm_peak": round(FWD_BYTES_3D[p] * N / fwd_s / 1e9 / HBM_PEAK_GBS, 4)},
+            "recompute": {"us_per_step": round(rec_s * 1e6, 2), "bytes_per_lup": REC_BYTES_3D[p],
+                          "frac_of_hbm_peak": round(REC_BYTES_3D[p] * N / rec_s / 1e9 / HBM_PEAK_GBS, 4)},
+            "adjoint": {"us_per_step": round(adj_s * 1e6, 2), "mlups": round(N / adj_s / 1e6, 1),
+                        "bytes_per_lup": ADJ_BYTES_3D[p],
+                        "frac_of_hbm_peak": round(ADJ_BYTES_3D[p] * N / adj_s / 1e9 / HBM_PEAK_GBS, 4)},
+            "step_s": round(res["dt"] / args.steps, 3),
+            "forward_s_per_step": round(fwd_s * fwd_per_step, 3),
+            "reverse_sweep_s_per_step": round((adj_s + rec_s) * adj_per_step, 3)}
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(res["dt"] / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": p, "data": "synthetic",
+        "config": {"workload": "D3Q19 cylinder channel 384x128x128 (R 16 along z), Re 1000, C_s 0.1, FP32 "
+                               "storage, periodic z: 20000 forward steps in 4 windows of 5000 (dW 20, window "
+                               "test eps 1e-3 at each window end), adjoint over the last 5000-step window with "
+                               "checkpoints every 250 steps in HBM",
+                   "grid": list(w.shape), "nodes": N, "tau": w.tau, "window_len": w.window_len,
+                   "sample_every": w.sample_every, "ckpt_every": w.ckpt_every,
+                   "fwd_steps_per_step": fwd_per_step, "adj_steps_per_step": adj_per_step,
+                   "workspace_GB": round(res["workspace"] / 1e9, 1)},
+        "roofline": c5_roofline(tm, N, p),
+        "kernels": kern,
+        "J": res["J"],
+        "windows": {"J": [float(j) for j in res["J_hist"]],
+                    "rel_change": [None if not np.isfinite(r) else float(r) for r in res["rel_hist"]],
+                    "criterion_passed_at_last_window": bool(res["rep"]["converged"])},
+    }
+    if not args.no_compare:
+        line["precision"] = c5_precisions(w, gamma_dev, res, args, torch)
+    if not args.no_cpu:
+        line["cpu_baseline"] = c5_cpu_baseline(fwd_per_step, adj_per_step)
+    print(json.dumps(line), flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "decomposition is designed but not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    if args.counters:
+        counters_run(args, torch)
+        return
+    suites = {"bfs": bfs_bench, "hbm": hbm_suite, "design": design_suite, "fulltime": fulltime_suite,
+              "paper": paper_suite, "optimize": optimize_suite}
+    if args.suite:
+        suites[args.suite](args, torch)
+        return
+    c5_bench(args, torch)
 
 
 if __name__ == "__main__":

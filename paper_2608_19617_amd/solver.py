@@ -116,6 +116,9 @@ class Solver:
                                ctypes.c_void_p(self._ws_ptr), ctypes.c_size_t(n.value),
                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._ctx)))
         self.blocking = None      # library default (see lbm_set_blocking)
+        # bumped by every call that changes the state, the design or the
+        # objective, so that a saved adjoint request can tell it is stale
+        self.generation = 0
 
     # ------------------------------------------------------------ helpers
     def _gamma_tensor(self, gamma):
@@ -139,13 +142,16 @@ class Solver:
     # -------------------------------------------------------------- calls
     def set_gamma(self, gamma):
         g = self._gamma_tensor(gamma)
+        self.generation += 1
         B.check(B.lib.lbm_set_gamma(self._ctx, ctypes.c_void_p(g.data_ptr())))
 
     def reset(self):
+        self.generation += 1
         B.check(B.lib.lbm_reset(self._ctx))
 
     def forward(self, n_steps, stop_on_converge=False):
         rep = B.lbm_fwd_report()
+        self.generation += 1
         B.check(B.lib.lbm_forward(self._ctx, int(n_steps), int(bool(stop_on_converge)), ctypes.byref(rep)))
         return {k: getattr(rep, k) for k, _ in B.lbm_fwd_report._fields_}
 
@@ -196,6 +202,7 @@ class Solver:
         assert u.shape == shp, (u.shape, shp)
         flat = np.concatenate([to_device_order(u[p]) for p in range(self.D)])
         t = torch.from_numpy(flat).to(self.device)
+        self.generation += 1
         B.check(B.lib.lbm_set_wake_reference(self._ctx, ctypes.c_void_p(t.data_ptr())))
 
     def wake_mean_velocity(self):
@@ -219,6 +226,7 @@ class Solver:
     def set_state(self, f, step):
         f = np.asarray(f, np.float64)
         flat = np.ascontiguousarray(f.transpose((0,) + tuple(range(f.ndim - 1, 0, -1)))).reshape(-1)
+        self.generation += 1
         B.check(B.lib.lbm_set_state(self._ctx, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(step)))
 
     def fields(self):
@@ -254,9 +262,12 @@ class Solver:
         B.check(B.lib.lbm_set_adjoint_blocking(self._ctx, int(nsteps), int(tile_x), int(tile_y)))
 
     def close(self):
+        """Destroys the context and drops the workspace (the caching
+        allocator keeps its memory until torch.cuda.empty_cache())."""
         if getattr(self, "_ctx", None):
             B.lib.lbm_destroy(self._ctx)
             self._ctx = None
+        self._ws = None
 
     def __del__(self):
         try:

@@ -107,6 +107,7 @@ def test_small_window_reduced(Solver, prec, tol_f, tol_g):
     sv.set_state(f0, 0)
     sv.forward(w.window_len)
     g, J = sv.adjoint()
+    print(f"small window {prec}: J {abs(J - J_o) / abs(J_o):.2e}, dJ/dgamma {rel_l2(g.cpu().numpy(), g_o):.2e}")
     assert abs(J - J_o) <= tol_f * abs(J_o) + 1e-9
     assert rel_l2(g.cpu().numpy(), g_o) <= tol_g
     sv.close()
@@ -168,7 +169,11 @@ def test_c1_fp64_fields(c1, c1_gpu64):
     print(f"C1 FP64 fields: step 300 {e300:.2e}; step 1000 vs oracle {e1000:.2e}, vs extended "
           f"precision {e1000_ld:.2e} (FP64 oracle vs extended {c1['drift1000']:.2e})")
     assert e300 <= 1e-12
-    assert e1000_ld <= max(1e-12, 3 * c1["drift1000"])
+    # the 1e-12 bar at step 1000 is missed: the outlet amplifies round-off
+    # (measured 1.15e-12 against the extended-precision solution, about
+    # 1e-11 against the FP64 oracle, which is itself 9.8e-12 from it)
+    assert e1000_ld <= 2e-12
+    assert e1000 <= 2.5e-11
 
 
 @pytest.fixture(scope="module")
@@ -202,7 +207,7 @@ def test_c1_fp64_windows_and_adjoint(c1_gpu64, c1_window4):
     assert eg <= 1e-10
 
 
-@pytest.mark.parametrize("prec,tol_J,tol_g", [("f32", 1e-3, 1e-4), ("f16s", 1e-1, 1e-2)])
+@pytest.mark.parametrize("prec,tol_J,tol_g", [("f32", 1e-4, 1e-4), ("f16s", 1e-3, 1e-2)])
 def test_c1_reduced_precision(Solver, c1, c1_gpu64, c1_window4, prec, tol_J, tol_g):
     """FP32 / FP16-shifted storage: laminar fields from t = 0 (step 300), and
     J and dJ/dgamma of window 4 from the shared FP64 window-start state."""
@@ -245,6 +250,7 @@ def test_d2q9_record_sweep_blocked_matches_oracle(Solver, prec, K):
     sv.set_state(f0, 0)
     sv.forward(w.window_len)
     g, J = sv.adjoint()
+    print(f"record sweep {prec} K={K}: J {abs(J - J_o) / abs(J_o):.2e}, dJ/dgamma {rel_l2(g.cpu().numpy(), g_o):.2e}")
     assert abs(J - J_o) <= tol_J * abs(J_o)
     assert rel_l2(g.cpu().numpy(), g_o) <= tol_g, rel_l2(g.cpu().numpy(), g_o)
     sv.close()
@@ -407,6 +413,7 @@ def test_d3q19_record_sweep_blocked_matches_oracle(Solver, prec, K):
     sv.set_state(f0, 0)
     sv.forward(w.window_len)
     g, J = sv.adjoint()
+    print(f"record sweep {prec} K={K}: J {abs(J - J_o) / abs(J_o):.2e}, dJ/dgamma {rel_l2(g.cpu().numpy(), g_o):.2e}")
     assert abs(J - J_o) <= tol_J * abs(J_o)
     assert rel_l2(g.cpu().numpy(), g_o) <= tol_g, rel_l2(g.cpu().numpy(), g_o)
     sv.close()
@@ -760,7 +767,78 @@ def test_cylinder_wake_fd_check(Solver):
     errs = np.array(errs)
     print(f"cylinder wake FD check: max rel err {errs.max():.2e}, median {np.median(errs):.2e}, "
           f"|dJ/dgamma| of the entries {np.abs(g[tuple(pick.T)]).min():.2e}..{np.abs(g[tuple(pick.T)]).max():.2e}")
-    assert np.median(errs) <= 1e-2
+    assert errs.max() <= 1e-3
+    sv.close()
+
+
+@pytest.fixture(scope="module")
+def wake_window_oracle(Solver):
+    """Cylinder wake 2048 x 512: the GPU FP64 state after 1000 steps, and the
+    oracle's J and window gradient of a 10-step window from it (samples at
+    steps 5 and 10) with the pressure sections across the cylinder
+    (x = 505 and 520, every open row), so the adjoint reaches the disk, its
+    ramp and the flow around it."""
+    w = W.cylinder_wake(window_len=1000, ckpt_every=100, sample_every=20, max_windows=1)
+    f0 = _share_state(Solver, w, 1000)
+    w1 = W.cylinder_wake(window_len=10, ckpt_every=10, sample_every=5, max_windows=1)
+    w1.sec_in, w1.sec_out = (505, 1, 511), (520, 1, 511)
+    J_o, g_o, _ = ad.window_gradient(oracle_problem(w1), w1.gamma, f0)
+    return w1, f0, J_o, g_o
+
+
+@pytest.mark.parametrize("prec,tol_J,tol_g", [("f64", 1e-12, 1e-10), ("f32", 1e-5, 1e-4), ("f16s", 1e-2, 1e-2)])
+def test_cylinder_wake_full_size_adjoint_vs_oracle(Solver, wake_window_oracle, prec, tol_J, tol_g):
+    """The library's default launches at 2048 x 512 (temporally blocked
+    forward, recompute and adjoint) over a 10-step window from a shared
+    state: J and dJ/dgamma on the whole grid against the oracle (Sec. 3.2,
+    Eqs. adjoint_collision, adjoint_streaming, sensitivity)."""
+    w1, f0, J_o, g_o = wake_window_oracle
+    sv = Solver(w1, prec)
+    sv.set_state(f0, 0)
+    sv.forward(w1.window_len)
+    g, J = sv.adjoint()
+    g = g.cpu().numpy()
+    eJ = abs(J - J_o) / abs(J_o)
+    eg = rel_l2(g, g_o)
+    print(f"cylinder wake 2048x512 {prec}: 10-step window J {eJ:.2e} (J = {J_o:.3e}), dJ/dgamma {eg:.2e}, "
+          f"nonzero entries {np.count_nonzero(g_o)}")
+    assert np.count_nonzero(g_o) > 40000
+    assert eJ <= tol_J
+    assert eg <= tol_g
+    sv.close()
+
+
+@pytest.fixture(scope="module")
+def u_bend_window_oracle(Solver):
+    """U-bend 1024 x 1024: the GPU FP64 state after 1000 steps and the
+    oracle's J and window gradient of a 4-step window from it (dissipation
+    plus pressure drop, samples at steps 2 and 4): the dissipation sums over
+    every node, so the gradient is nonzero on the whole grid."""
+    w = W.u_bend(window_len=200, sample_every=20, ckpt_every=20, max_windows=1)
+    f0 = _share_state(Solver, w, 1000)
+    w1 = W.u_bend(window_len=4, sample_every=2, ckpt_every=4, max_windows=1)
+    J_o, g_o, _ = ad.window_gradient(oracle_problem(w1), w1.gamma, f0)
+    return w1, f0, J_o, g_o
+
+
+@pytest.mark.parametrize("prec,tol_J,tol_g", [("f64", 1e-12, 1e-10), ("f32", 1e-5, 1e-4), ("f16s", 1e-2, 1e-2)])
+def test_u_bend_full_size_adjoint_vs_oracle(Solver, u_bend_window_oracle, prec, tol_J, tol_g):
+    """The U-bend in the default launches of each precision (west inlet and
+    west outlet rows, dissipation objective), 4-step window from a shared
+    state: J and dJ/dgamma on all 1M nodes against the oracle."""
+    w1, f0, J_o, g_o = u_bend_window_oracle
+    sv = Solver(w1, prec)
+    sv.set_state(f0, 0)
+    sv.forward(w1.window_len)
+    g, J = sv.adjoint()
+    g = g.cpu().numpy()
+    eJ = abs(J - J_o) / abs(J_o)
+    eg = rel_l2(g, g_o)
+    print(f"U-bend 1024x1024 {prec}: 4-step window J {eJ:.2e} (J = {J_o:.3e}), dJ/dgamma {eg:.2e}, "
+          f"nonzero entries {np.count_nonzero(g_o)}")
+    assert np.count_nonzero(g_o) > 900000
+    assert eJ <= tol_J
+    assert eg <= tol_g
     sv.close()
 
 
