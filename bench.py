@@ -63,7 +63,8 @@ def parse():
                     help="workload of --counters: the backward-facing step (bfs) or the D3Q19 "
                          "channel 384x128x128 in its default launches, 40 forward steps and the adjoint of "
                          "their last 20-step window (cyl3d)")
-    ap.add_argument("--suite", choices=["bfs", "hbm", "design", "fulltime", "paper", "optimize"], default=None,
+    ap.add_argument("--suite", choices=["bfs", "hbm", "design", "fulltime", "paper", "optimize", "conditioning"],
+                    default=None,
                     help="bfs: the backward-facing step 800x200 (FP32 vs FP64 window criterion "
                          "workload) benchmarked to its converged window and adjoint; hbm: rooflines of the forward, recompute and adjoint kernels on grids far "
                          "larger than the caches (one JSON line per configuration) instead of the "
@@ -1014,6 +1015,132 @@ def c5_bench(args, torch):
     print(json.dumps(line), flush=True)
 
 
+# ------------------------------------------------------ conditioning suite
+
+def _conditioning_cases():
+    """(name, workload factory for a window of L steps, spin-up steps S,
+    window lengths, the window of the configuration, finite-difference
+    entries, finite-difference steps h)."""
+    from paper_2608_19617_amd import workloads as W
+
+    def c5(L):
+        return W.cylinder_3d(window_len=L, sample_every=20, ckpt_every=min(250, L // 2), n_windows=1)
+
+    def c3(L):
+        return W.cylinder_wake(window_len=L, sample_every=20, ckpt_every=min(500, L // 2), max_windows=1, eps=-1.0)
+
+    def bfs(L):
+        w = W.backward_facing_step(window_len=L, sample_every=100, ckpt_every=min(100, L), max_windows=1, eps=-1.0)
+        return w
+
+    def ubend(L):
+        return W.u_bend_paper(400.0, window_len=L, sample_every=20, ckpt_every=min(500, L // 2), max_windows=1,
+                              eps=-1.0)
+
+    hs = (1e-3, 1e-4, 1e-5, 1e-6)
+    return [("cylinder_3d_384x128x128", c5, 15000, (40, 200, 1000, 5000), 5000, 4, hs),
+            ("cylinder_wake_2048x512", c3, 20000, (100, 1000, 5000, 20000), 20000, 8, hs),
+            ("backward_facing_step_800x200", bfs, 38000, (100, 500, 2000), 2000, 8, hs),
+            ("u_bend_paper_240x192_re400", ubend, 40000, (2000, 5000, 10000, 20000), 20000, 12,
+             (1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8))]
+
+
+def _fd_entries(g, n, seed):
+    """n seeded entries among the nodes whose |dJ/dgamma| is in the top 5%."""
+    import numpy as np
+    a = np.abs(g).ravel()
+    thr = np.quantile(a, 0.95)
+    cand = np.flatnonzero(a >= thr) if thr > 0 else np.flatnonzero(a > 0)
+    pick = np.random.default_rng(seed).choice(cand, min(n, len(cand)), replace=False)
+    return [np.unravel_index(int(i), g.shape) for i in pick]
+
+
+def conditioning_suite(args, torch):
+    import numpy as np
+    from paper_2608_19617_amd.solver import Solver
+
+    def window(w, prec, f, step, keep_state=False):
+        sv = Solver(w, prec)
+        sv.set_state(f, step)
+        rep = sv.forward(w.window_len)
+        fe = sv.get_state()[0] if keep_state else None
+        g, J = sv.adjoint()
+        return sv, rep, J, g.cpu().numpy(), fe
+
+    for name, make, S, lengths, w_cfg, n_fd, hs in _conditioning_cases():
+        if args.case not in name:
+            continue
+        w0 = make(lengths[0])
+        sv = Solver(w0, "f64")
+        sv.forward(S)
+        f64_S, step = sv.get_state()
+        _free(torch, sv)
+        rng = np.random.default_rng(1)
+        delta = 1e-8 * rng.standard_normal(f64_S.shape) * np.abs(f64_S).mean()
+        for L in lengths:
+            w = make(L)
+            t0 = time.perf_counter()
+            sv64, rep, J64, g64, fe64 = window(w, "f64", f64_S, S, keep_state=True)
+            pts = _fd_entries(g64, n_fd, 0)
+            top = float(np.max(np.abs(g64)))
+            fd = {}
+            for h in hs:
+                errs = []
+                for p in pts:
+                    gp = w.gamma.copy()
+                    gm = w.gamma.copy()
+                    hp = min(h, 1.0 - gp[p]) if gp[p] + h > 1.0 else h
+                    hm = min(h, gm[p]) if gm[p] - h < 0.0 else h
+                    gp[p] += hp
+                    gm[p] -= hm
+                    d = (sv64.replay(gp) - sv64.replay(gm)) / (hp + hm)
+                    errs.append(abs(d - g64[p]) / top)
+                fd[f"h={h:g}"] = float(max(errs))
+            _free(torch, sv64)
+            # growth of a small state perturbation over the window (FP64)
+            svp = Solver(w, "f64")
+            svp.set_state(f64_S + delta, S)
+            svp.forward(L)
+            fe_p = svp.get_state()[0]
+            _free(torch, svp)
+            growth = float(np.linalg.norm(fe_p - fe64) / np.linalg.norm(delta))
+            line = {"suite": "conditioning", "workload": name, "grid": list(w.shape), "window_len": L,
+                    "spin_up_steps": S, "J_f64": J64, "dJdgamma_norm_f64": float(np.linalg.norm(g64)),
+                    "dJdgamma_max_f64": top, "fd_f64_max_err_over_max_dJdgamma": fd,
+                    "fd_entries": len(pts), "perturbation_growth": growth}
+            for prec in ("f32", "f16s"):
+                svr, _, J, g, _ = window(w, prec, f64_S, S)
+                _free(torch, svr)
+                line[prec] = {"J_rel_err": abs(J - J64) / abs(J64), "dJdgamma_rel_l2": _rel(g, g64),
+                              "dJdgamma_norm": float(np.linalg.norm(g))}
+            line["s"] = round(time.perf_counter() - t0, 2)
+            print(json.dumps(line), flush=True)
+        # from rest: how much of each precision's error comes from its own
+        # window-start state (the FP64 adjoint run from that state) and how
+        # much from rounding inside the window (the same-start error)
+        w = make(w_cfg)
+        sv64, _, J64, g64, _ = window(w, "f64", f64_S, S)
+        _free(torch, sv64)
+        out = {"suite": "conditioning", "workload": name, "window_len": w_cfg, "from_rest_decomposition": {}}
+        for prec in ("f32", "f16s"):
+            sv = Solver(w0, prec)
+            sv.forward(S)
+            fp_S, _ = sv.get_state()
+            _free(torch, sv)
+            sva, _, Jp, gp, _ = window(w, prec, fp_S, S)
+            _free(torch, sva)
+            svb, _, Jb, gb, _ = window(w, "f64", fp_S, S)
+            _free(torch, svb)
+            svc, _, Jc, gc, _ = window(w, prec, f64_S, S)
+            _free(torch, svc)
+            out["from_rest_decomposition"][prec] = {
+                "start_state_rel_l2_vs_f64": float(np.linalg.norm(fp_S - f64_S) / np.linalg.norm(f64_S)),
+                "from_rest": {"J_rel_err": abs(Jp - J64) / abs(J64), "dJdgamma_rel_l2": _rel(gp, g64)},
+                "f64_from_this_start": {"J_rel_err": abs(Jb - J64) / abs(J64), "dJdgamma_rel_l2": _rel(gb, g64)},
+                "same_start": {"J_rel_err": abs(Jc - J64) / abs(J64), "dJdgamma_rel_l2": _rel(gc, g64)}}
+        print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -1028,7 +1155,7 @@ def main():
         counters_run(args, torch)
         return
     suites = {"bfs": bfs_bench, "hbm": hbm_suite, "design": design_suite, "fulltime": fulltime_suite,
-              "paper": paper_suite, "optimize": optimize_suite}
+              "paper": paper_suite, "optimize": optimize_suite, "conditioning": conditioning_suite}
     if args.suite:
         suites[args.suite](args, torch)
         return

@@ -162,11 +162,18 @@ typedef struct lbm_ctx lbm_ctx;
  * ring). Validates the configuration. */
 lbm_status lbm_workspace_bytes(const lbm_config* cfg, size_t* bytes);
 
-/* Creates a context. gamma_dev: device FP64 array of N design values in
- * [0, 1] (copied; the caller may reuse it). workspace_dev: device memory of
- * at least lbm_workspace_bytes bytes, 256-byte aligned, owned by the caller
- * and used exclusively by this context until lbm_destroy. stream: the
- * hipStream_t every launch goes to. Sets the state to f^0. */
+/* Creates a context: the setup of the problem statement (Sec. 2.1.3 initial
+ * and boundary conditions; Sec. 2.2 bounce-back fraction s(gamma), Eq.
+ * external_force): builds s from gamma, the per-row boundary tables and
+ * inlet speeds, and f^0 = f^eq(rho_init, u_init) (Eq. feq). gamma_dev:
+ * device FP64 array of N design values in [0, 1] (copied; the caller may
+ * reuse it). workspace_dev: device memory of at least lbm_workspace_bytes
+ * bytes, 256-byte aligned, owned by the caller and used exclusively by this
+ * context until lbm_destroy. stream: the hipStream_t every launch goes to.
+ * Errors: LBM_E_INVALID for a bad configuration (checked before any HIP
+ * call) or a gamma entry that is not finite (or, with LBM_S_PAPER, outside
+ * the map's range), LBM_E_NOMEM for a short workspace, LBM_E_HIP if a HIP
+ * call fails; *out is set only on LBM_OK. */
 lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* workspace_dev,
                     size_t bytes, void* stream, lbm_ctx** out);
 
@@ -189,10 +196,16 @@ lbm_status lbm_forward(lbm_ctx* ctx, long n_steps, int stop_on_converge, lbm_fwd
 lbm_status lbm_window_history(lbm_ctx* ctx, double* J, double* M, double* rel, int cap, int* n);
 
 /* Discrete adjoint over window `window` (1-based), which must be the last
- * completed window (or pass 0 for it). Writes dJ/dgamma (device FP64, N
- * values) and, if J_out is not NULL, the window objective. The forward
- * state is not changed. Recomputes each K-step segment from its HBM
- * checkpoint. The drag's samples depend on s directly: their explicit
+ * completed window (or pass 0 for it): the reverse sweep of Sec. 3.2 over
+ * the window-restricted subproblem (adjoint boundary rules, Eqs.
+ * adjoint_inlet_bc and adjoint_outlet_bc; adjoint streaming, Eq.
+ * adjoint_streaming; adjoint collision, Eq. adjoint_collision; objective
+ * sources at the sampling instants, Eq. weighted_temporal_sampling), then
+ * the design gradient of Eq. sensitivity with ds/dgamma. Writes dJ/dgamma
+ * (device FP64, N values, caller-owned) and, if J_out is not NULL, the
+ * window objective. The forward state is not changed. Recomputes each
+ * K-step segment from its HBM checkpoint. Errors: LBM_E_STATE without a
+ * completed window, for another window or after LBM_E_UNSTABLE. The drag's samples depend on s directly: their explicit
  * derivative, dW/|W| times 2 j_x summed over the window's samples, is kept
  * by the forward on the force box and added here. */
 lbm_status lbm_adjoint(lbm_ctx* ctx, int window, double* dJdgamma_dev, double* J_out);
@@ -212,8 +225,12 @@ lbm_status lbm_adjoint_full(lbm_ctx* ctx, double* dJdgamma_dev, double* J_out);
 
 /* Replays the last completed window from its (fixed) start state with the
  * design field gamma_dev (device FP64, N values) and returns its objective:
- * the function lbm_adjoint differentiates, for finite-difference checks.
- * The forward state, checkpoints and the context's own gamma are unchanged. */
+ * the function lbm_adjoint differentiates, for finite-difference checks on
+ * the same window and sampling instants (the validation protocol of Sec.
+ * 4.2.1). The forward state, checkpoints and the context's own gamma are
+ * unchanged. Errors: LBM_E_STATE without a completed window, LBM_E_INVALID
+ * for a gamma entry that is not finite (or outside the LBM_S_PAPER map's
+ * range). */
 lbm_status lbm_window_replay(lbm_ctx* ctx, const double* gamma_dev, double* J_out);
 
 /* Wake recovery (objective LBM_J_WAKE): sets the reference mean velocity

@@ -1,16 +1,24 @@
 // gfx950 kernels of the windowed LBM-LES solver and its discrete adjoint.
 //
-// One thread per lattice node, 256 threads (four wave64) per workgroup,
-// structure-of-arrays populations so that every load and store of a wave
+// Structure-of-arrays populations, so that every load and store of a wave
 // covers a contiguous run of one population plane. The step is a fused
 // pull (stream) -> boundary rules -> sample -> collide -> partial
-// bounce-back -> store: each population is read and written once per step,
-// the state in HBM is the post-collision one (G^k = C(f^k)), and the
-// post-boundary state f^k of the paper only lives in registers. The adjoint
-// step is the mirror pull of the adjoint populations fused with the
-// transposed collision in moment space. This path is bandwidth-bound
-// (about 3 flop per byte), so there is no MFMA and no LDS staging: there is
-// no data reuse across threads to stage.
+// bounce-back -> store: the state in HBM is the post-collision one
+// (G^k = C(f^k)), and the post-boundary state f^k of the paper only lives
+// in registers or LDS. The adjoint step is the mirror pull of the adjoint
+// populations fused with the transposed collision in moment space. At
+// about 3 flop per algorithmic byte there is no MFMA.
+//
+// Three launch forms per step kind:
+//   * single steps (k_step, k_adjoint): one thread per node, 256 threads
+//     per workgroup, each population read and written once per step, no
+//     LDS;
+//   * temporally blocked D2Q9 launches (k_step_tb, k_adjoint_tb): a
+//     workgroup advances its tile and a shrinking halo several steps in
+//     LDS, so HBM is touched once per launch;
+//   * D3Q19 two-step launches marching along z (k_step_tbz,
+//     k_adjoint_tbz): the first step's planes pass through a three-plane
+//     LDS ring and the second step reads them there.
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"

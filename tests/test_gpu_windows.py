@@ -186,13 +186,14 @@ def test_windowed_j_refuses_a_solver_that_ran_again(Solver):
     sv.close()
 
 
-@pytest.mark.parametrize("prec,h,tol", [("f64", 1e-4, 1e-6), ("f32", 1e-3, 3e-2)])
+@pytest.mark.parametrize("prec,h,tol", [("f64", 1e-4, 1e-6), ("f32", 1e-3, 2e-4)])
 def test_windowed_j_central_differences(Solver, prec, h, tol):
     """Central differences through WindowedJ's fixed-start form (one window
     from the state entering W_eff) on 8 seed-chosen entries (the disk ramp,
     the disk and the near wake) against the backward of the from-rest
     objective. FP32 takes h = 1e-3: J changes by about 1e-7 per 1e-4 of one
-    entry, near the FP32 rounding of the replayed window."""
+    entry, near the FP32 rounding of the replayed window. Measured: FP64
+    2.8e-8, FP32 2.0e-5 of the largest |dJ/dgamma|."""
     from paper_2608_19617_amd.autograd import windowed_objective
     w = _channel(0.3)
     sv = Solver(w, prec)
