@@ -82,6 +82,32 @@ lbm_status lbm_design_update(lbm_design* d, const double* x_dev, const double* d
 /* Frees the host-side context. */
 void lbm_design_destroy(lbm_design* d);
 
+/* Allocation-free form of lbm_design_map, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc. It needs no context and no workspace and
+ * calls no allocating routine. Same result as lbm_design_init on (nx, ny,
+ * nz, radius, mask_dev, base_dev) followed by lbm_design_map(x_dev, beta,
+ * eta): gamma_dev (device FP64, N, caller-owned) = H(F x) on the design
+ * domain, base elsewhere; if volume_dev (device FP64, one value, may be
+ * NULL) is given it receives V(gamma) (NaN for an empty design domain).
+ * Inputs mask_dev (device bytes, N), base_dev and x_dev (device FP64, N)
+ * are read only. Everything is enqueued on `stream`; nothing is
+ * synchronised.
+ * Limits: at most 65536 tiles of 256 nodes (32 x 8 in 2D, 8 x 8 x 4 in 3D;
+ * 16 777 216 nodes when the grid is a multiple of the tile), else
+ * LBM_E_INVALID. Scratch: a fixed 1 MB device array of the library, one per
+ * GPU, held until the process ends; every call on a GPU uses that GPU's
+ * array (it rewrites all it reads, nothing needs clearing), so calls that
+ * overlap on one GPU (other streams or threads) race. The first call on
+ * each GPU looks up the array's device address (hipGetSymbolAddress, not a
+ * stream operation); make that first call before any graph capture.
+ * Errors: LBM_E_INVALID for NULL inputs, bad sizes, radius outside [1, 5],
+ * beta <= 0 or eta outside (0, 1), all before any HIP call; LBM_E_HIP for
+ * HIP failures. */
+lbm_status lbm_design_map_noalloc(int nx, int ny, int nz, double radius, const unsigned char* mask_dev,
+                                  const double* base_dev, const double* x_dev, double beta, double eta,
+                                  double* gamma_dev, double* volume_dev, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,7 @@ EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_set_gamma", "lbm_reset", "lb
             "lbm_set_state", "lbm_get_fields", "lbm_timing", "lbm_set_blocking", "lbm_set_blocking_3d",
             "lbm_set_adjoint_blocking", "lbm_set_adjoint_blocking_3d", "lbm_last_error", "lbm_destroy",
             "lbm_design_workspace_bytes", "lbm_design_init", "lbm_design_map", "lbm_design_chain",
-            "lbm_design_update", "lbm_design_destroy"]
+            "lbm_design_update", "lbm_design_destroy", "lbm_design_map_noalloc"]
 
 
 class lbm_config(ctypes.Structure):
@@ -101,6 +101,7 @@ def _load():
     lib.lbm_design_chain.argtypes = [P, P, dbl, dbl, P, P, P]
     lib.lbm_design_update.argtypes = [P, P, P, P, dbl, dbl, dbl, dbl, dbl, P, D, D]
     lib.lbm_design_destroy.argtypes = [P]
+    lib.lbm_design_map_noalloc.argtypes = [i, i, i, dbl, P, P, P, dbl, dbl, P, P, P]
     lib.lbm_design_destroy.restype = None
     for name in EXPORTED:
         if name not in ("lbm_last_error", "lbm_destroy", "lbm_design_destroy"):

@@ -15,11 +15,21 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "launch.hpp"
 #include "lbm_design.h"
+
+// Scratch of lbm_design_map_noalloc: per-workgroup partials (volume sum and
+// design-node count, two doubles per block) for at most DZ_NOALLOC_BLOCKS
+// blocks, then the two final sums. Each GPU holds its own copy for the life
+// of the process; host code never uses this name as an address (it is a
+// host-side stand-in): it passes the address hipGetSymbolAddress returned
+// for the current device.
+constexpr int DZ_NOALLOC_BLOCKS = 65536;
+static __device__ __align__(256) double scratch[2 * DZ_NOALLOC_BLOCKS + 32];
 
 namespace lbm {
 namespace {
@@ -246,6 +256,81 @@ __global__ __launch_bounds__(DZ_TB) void k_dz_trial(const unsigned char* __restr
     xn[n] = fmin(fmax(xv - move * (sJ + lam * sV), lo), hi);
 }
 
+// Allocation-free map (lbm_design_map_noalloc): the filter with its
+// normalisation in one stencil pass, no neighbour list. A workgroup stages
+// m x and m over its tile and halo in LDS and walks the integer offsets of
+// the ball |o| < r in the order the host list of a context uses (z, then y,
+// then x), with weights r - |o|, so each sum takes the same terms in the
+// same order as the context's two passes. Per-block partials of the volume
+// sum and of the design-node count go to `partials`.
+template <int D>
+__global__ __launch_bounds__(DZ_TB) void k_dz_map_direct(DzGeo g, const unsigned char* __restrict__ mask,
+                                                         const double* __restrict__ x,
+                                                         const double* __restrict__ base, double radius,
+                                                         double beta, double eta, double hn, double hd,
+                                                         double* __restrict__ gamma, double* __restrict__ partials) {
+    using TL = DzTile<D>;
+    __shared__ double s0[dz_region_max<D>()];
+    __shared__ double s1[dz_region_max<D>()];
+    const int bidx = (int)blockIdx.x;
+    const int btx = bidx % g.tiles_x, bty = (bidx / g.tiles_x) % g.tiles_y, btz = bidx / (g.tiles_x * g.tiles_y);
+    const int x0 = btx * TL::X - g.H, y0 = bty * TL::Y - g.H, z0 = (D == 3 ? btz * TL::Z - g.H : 0);
+    const int rcount = g.rx * g.ry * g.rz;
+    for (int c = (int)threadIdx.x; c < rcount; c += DZ_TB) {
+        const int lz = c / (g.rx * g.ry), r2 = c - lz * g.rx * g.ry;
+        const int ly = r2 / g.rx, lx = r2 - ly * g.rx;
+        const int xx = x0 + lx, yy = y0 + ly, zz = z0 + lz;
+        double v0 = 0.0, v1 = 0.0;
+        if (xx >= 0 && xx < g.nx && yy >= 0 && yy < g.ny && zz >= 0 && zz < g.nz) {
+            const int n = (zz * g.ny + yy) * g.nx + xx;
+            if (mask[n]) {
+                v0 = x[n];
+                v1 = 1.0;
+            }
+        }
+        s0[c] = v0;
+        s1[c] = v1;
+    }
+    __syncthreads();
+    const int t = (int)threadIdx.x;
+    const int ox = t % TL::X, oy = (t / TL::X) % TL::Y, oz = t / (TL::X * TL::Y);
+    const int xx = btx * TL::X + ox, yy = bty * TL::Y + oy, zz = (D == 3 ? btz * TL::Z + oz : 0);
+    double vol = 0.0, cnt = 0.0;
+    if (xx < g.nx && yy < g.ny && zz < g.nz) {
+        const int n = (zz * g.ny + yy) * g.nx + xx;
+        const int cell = ((oz + (D == 3 ? g.H : 0)) * g.ry + (oy + g.H)) * g.rx + (ox + g.H);
+        const bool m = mask[n] != 0;
+        double gam = base[n];
+        if (m) {
+            double acc = 0.0, wsum = 0.0;
+            const int hz = D == 3 ? g.H : 0;
+            for (int dz = -hz; dz <= hz; ++dz)
+                for (int dy = -g.H; dy <= g.H; ++dy)
+                    for (int dx = -g.H; dx <= g.H; ++dx) {
+                        const double dist = sqrt((double)(dx * dx + dy * dy + dz * dz));
+                        if (dist < radius) {
+                            const double w = radius - dist;
+                            const int off = (dz * g.ry + dy) * g.rx + dx;
+                            acc += w * s0[cell + off];
+                            wsum += w * s1[cell + off];
+                        }
+                    }
+            const double xt = acc / wsum;
+            gam = (hn + tanh(beta * (xt - eta))) * hd;
+            vol = gam;
+            cnt = 1.0;
+        }
+        gamma[n] = gam;
+    }
+    double v[2] = {vol, cnt};
+    dz_block_sum<2>(v, partials);
+}
+
+// volume = sums[0] / sums[1] (NaN for an empty design domain).
+__global__ void k_dz_ratio(const double* __restrict__ sums, double* __restrict__ volume) {
+    if (threadIdx.x == 0) volume[0] = sums[0] / sums[1];
+}
+
 size_t dz_align(size_t v) { return (v + 255) / 256 * 256; }
 
 int dz_halo(double r) { return (int)std::ceil(r) - 1; }
@@ -343,6 +428,27 @@ lbm_status dz_volume(lbm_design* d, double* v) {
 }
 
 bool dz_params(double beta, double eta) { return std::isfinite(beta) && beta > 0.0 && eta > 0.0 && eta < 1.0; }
+
+// Device address of `scratch` on each GPU, taken with that GPU current on
+// the first allocation-free call there; never the array's host-side name.
+constexpr int DZ_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[DZ_MAX_DEVICES] = {};
+
+lbm_status noalloc_scratch(double** out) {
+    int dev = -1;
+    DZCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= DZ_MAX_DEVICES) return record_error(LBM_E_INVALID, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        DZCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return record_error(LBM_E_HIP, "hipGetSymbolAddress returned a null address");
+        g_scratch_ptr[dev] = (double*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_OK;
+}
 
 }  // namespace
 
@@ -501,5 +607,51 @@ lbm_status lbm_design_update(lbm_design* d, const double* x_dev, const double* d
 }
 
 void lbm_design_destroy(lbm_design* d) { delete d; }
+
+lbm_status lbm_design_map_noalloc(int nx, int ny, int nz, double radius, const unsigned char* mask_dev,
+                                  const double* base_dev, const double* x_dev, double beta, double eta,
+                                  double* gamma_dev, double* volume_dev, void* stream) {
+    if (!mask_dev || !base_dev || !x_dev || !gamma_dev) return dz_bad("NULL argument");
+    if (!dz_valid_grid(nx, ny, nz, radius)) return dz_bad("grid sizes must be >= 1 and radius in [1, 5]");
+    if (!dz_params(beta, eta)) return dz_bad("need beta > 0 and 0 < eta < 1");
+    const DzLayout L = dz_layout(nx, ny, nz);
+    if (L.nb_tiles > DZ_NOALLOC_BLOCKS)
+        return dz_bad("grid too large for lbm_design_map_noalloc (at most 65536 tiles of 256 nodes)");
+    double* scr = nullptr;
+    lbm_status st = noalloc_scratch(&scr);
+    if (st != LBM_OK) return st;
+    const int D = nz > 1 ? 3 : 2;
+    const int H = dz_halo(radius);
+    DzGeo g{};
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    g.N = nx * ny * nz;
+    g.H = H;
+    g.rx = (D == 3 ? DzTile<3>::X : DzTile<2>::X) + 2 * H;
+    g.ry = (D == 3 ? DzTile<3>::Y : DzTile<2>::Y) + 2 * H;
+    g.rz = D == 3 ? DzTile<3>::Z + 2 * H : 1;
+    g.tiles_x = (nx + (D == 3 ? DzTile<3>::X : DzTile<2>::X) - 1) / (D == 3 ? DzTile<3>::X : DzTile<2>::X);
+    g.tiles_y = (ny + (D == 3 ? DzTile<3>::Y : DzTile<2>::Y) - 1) / (D == 3 ? DzTile<3>::Y : DzTile<2>::Y);
+    g.noff = 0;
+    g.offs = nullptr;
+    const double hn = std::tanh(beta * eta);
+    const double hd = 1.0 / (hn + std::tanh(beta * (1.0 - eta)));
+    hipStream_t sm = (hipStream_t)stream;
+    double* sums = scr + 2 * DZ_NOALLOC_BLOCKS;
+    if (D == 2)
+        hipLaunchKernelGGL(k_dz_map_direct<2>, dim3(L.nb_tiles), dim3(DZ_TB), 0, sm, g, mask_dev, x_dev, base_dev,
+                           radius, beta, eta, hn, hd, gamma_dev, scr);
+    else
+        hipLaunchKernelGGL(k_dz_map_direct<3>, dim3(L.nb_tiles), dim3(DZ_TB), 0, sm, g, mask_dev, x_dev, base_dev,
+                           radius, beta, eta, hn, hd, gamma_dev, scr);
+    DZCHK(hipGetLastError());
+    if (volume_dev) {
+        hipLaunchKernelGGL((k_dz_final<2, 0>), dim3(1), dim3(DZ_TB), 0, sm, scr, L.nb_tiles, sums);
+        hipLaunchKernelGGL(k_dz_ratio, dim3(1), dim3(64), 0, sm, sums, volume_dev);
+        DZCHK(hipGetLastError());
+    }
+    return LBM_OK;
+}
 
 }  // extern "C"

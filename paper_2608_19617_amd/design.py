@@ -89,3 +89,34 @@ class Design:
             self.close()
         except Exception:
             pass
+
+
+def map_noalloc(shape, mask, base, x, radius, beta, eta=0.5, stream=None):
+    """lbm_design_map_noalloc: (gamma [x, y(, z)], volume fraction as a
+    0-dim device tensor) without a design context or workspace. The result
+    tensors are allocated here by torch; the library call allocates nothing."""
+    shape = tuple(int(s) for s in shape)
+    dev = torch.device("cuda")
+
+    def flat(a, dtype=torch.float64):
+        t = a if isinstance(a, torch.Tensor) else torch.as_tensor(np.asarray(a))
+        t = t.detach().to(dev, dtype)
+        if tuple(t.shape) == shape:
+            t = t.permute(*range(t.ndim - 1, -1, -1))
+        return t.contiguous().reshape(-1)
+
+    nx, ny = shape[0], shape[1]
+    nz = shape[2] if len(shape) == 3 else 1
+    m = flat(torch.as_tensor(np.asarray(mask) != 0) if not isinstance(mask, torch.Tensor) else mask != 0,
+             torch.uint8)
+    b, xf = flat(base), flat(x)
+    g = torch.empty(m.numel(), dtype=torch.float64, device=dev)
+    v = torch.empty((), dtype=torch.float64, device=dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    B.check(B.lib.lbm_design_map_noalloc(nx, ny, nz, float(radius), ctypes.c_void_p(m.data_ptr()),
+                                         ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(xf.data_ptr()),
+                                         float(beta), float(eta), ctypes.c_void_p(g.data_ptr()),
+                                         ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(st.cuda_stream)))
+    rev = tuple(reversed(shape))
+    return g.reshape(rev).permute(*range(len(rev) - 1, -1, -1)), v
+

@@ -230,3 +230,23 @@ def test_objective_configs(B):
     cfg.meas_box[:] = (20, 26, 5, 11, 0, 1)              # 36 nodes, two components
     st, wake = _bytes(B, cfg)
     assert st == B.LBM_OK and 4 * 72 * 8 + 1024 * 8 <= wake - base <= 4 * (72 * 8 + 256) + 1024 * 8 + 256
+
+
+def test_design_map_noalloc_validates_before_any_hip_call(B):
+    """The allocation-free map rejects NULL inputs, bad parameters and grids
+    beyond its fixed scratch (more than 65536 tiles) before touching the
+    GPU, so these calls run without one."""
+    import ctypes
+    P = ctypes.c_void_p
+    ok = P(256)
+    f = B.lib.lbm_design_map_noalloc
+    assert f(64, 64, 1, 4.0, None, ok, ok, 2.0, 0.5, ok, ok, None) == B.LBM_E_INVALID
+    assert f(64, 64, 1, 4.0, ok, ok, ok, 2.0, 0.5, None, ok, None) == B.LBM_E_INVALID
+    assert f(64, 64, 1, 6.0, ok, ok, ok, 2.0, 0.5, ok, ok, None) == B.LBM_E_INVALID
+    assert f(64, 64, 1, 4.0, ok, ok, ok, 0.0, 0.5, ok, ok, None) == B.LBM_E_INVALID
+    assert f(64, 64, 1, 4.0, ok, ok, ok, 2.0, 1.0, ok, ok, None) == B.LBM_E_INVALID
+    # 8224 x 2048 in 2D is 257 x 256 tiles of 32 x 8
+    assert f(8224, 2048, 1, 4.0, ok, ok, ok, 2.0, 0.5, ok, ok, None) == B.LBM_E_INVALID
+    assert b"65536 tiles" in B.lib.lbm_last_error()
+    # 3D tiles are 8 x 8 x 4
+    assert f(520, 512, 64, 4.0, ok, ok, ok, 2.0, 0.5, ok, ok, None) == B.LBM_E_INVALID   # 65 x 64 x 16 tiles
