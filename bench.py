@@ -59,11 +59,12 @@ def parse():
     ap.add_argument("--counters", action="store_true",
                     help="run one window and its adjoint of the workload plus a 256 MiB device copy "
                          "(for rocprofv3 --pmc byte counters) and exit")
-    ap.add_argument("--counters-case", choices=["bfs", "cyl3d"], default="bfs",
-                    help="workload of --counters: the backward-facing step (bfs) or the D3Q19 "
-                         "channel 384x128x128 in its default launches, 40 forward steps and the adjoint of "
-                         "their last 20-step window (cyl3d)")
-    ap.add_argument("--suite", choices=["bfs", "hbm", "design", "fulltime", "paper", "optimize", "conditioning"],
+    ap.add_argument("--counters-case", choices=["bfs", "cyl3d", "wake8192"], default="bfs",
+                    help="workload of --counters: the backward-facing step (bfs), the D3Q19 "
+                         "channel 384x128x128 (cyl3d) or the cylinder wake 8192x2048 (wake8192) in their "
+                         "default launches: 40 forward steps and the adjoint of their last 20-step window")
+    ap.add_argument("--suite", choices=["bfs", "hbm", "design", "fulltime", "paper", "optimize", "conditioning",
+                                        "c3", "c4"],
                     default=None,
                     help="bfs: the backward-facing step 800x200 (FP32 vs FP64 window criterion "
                          "workload) benchmarked to its converged window and adjoint; hbm: rooflines of the forward, recompute and adjoint kernels on grids far "
@@ -85,8 +86,12 @@ def counters_run(args, torch):
     FETCH_SIZE / WRITE_SIZE."""
     from paper_2608_19617_amd import workloads as W
     from paper_2608_19617_amd.solver import Solver
-    if args.counters_case == "cyl3d":
-        w = W.cylinder_3d(window_len=20, sample_every=20, ckpt_every=20, n_windows=2)
+    if args.counters_case in ("cyl3d", "wake8192"):
+        if args.counters_case == "cyl3d":
+            w = W.cylinder_3d(window_len=20, sample_every=20, ckpt_every=20, n_windows=2)
+        else:
+            w = W.cylinder_wake(nx=8192, ny=2048, radius=128, window_len=20, sample_every=20, ckpt_every=20,
+                                max_windows=2)
         sv = Solver(w, args.prec)
         sv.forward(2 * w.window_len)
         sv.adjoint()
@@ -1015,6 +1020,141 @@ def c5_bench(args, torch):
     print(json.dumps(line), flush=True)
 
 
+# ------------------------------------------------------------ C3 and C4
+
+def c3_suite(args, torch):
+    """The cylinder wake 2048 x 512 (disk R = 32, Re 1000, u_max = 0.04,
+    C_s = 0.1) in FP32 through WindowedJ: windows of 20 000 steps (dW = 20,
+    K = 500) from rest until the criterion (eps = 1e-3) passes or 5 windows
+    ran, backward = the adjoint over W_eff; then central differences
+    (h = 1e-4) of the window objective through WindowedJ's fixed-start form
+    on 16 seed-chosen entries (the disk ramp and the near wake, numpy
+    default_rng(0)), in FP32 and in FP64 from the same window-start state."""
+    import numpy as np
+    from paper_2608_19617_amd import workloads as W
+    from paper_2608_19617_amd.autograd import windowed_objective
+    from paper_2608_19617_amd.solver import Solver
+    w = W.cylinder_wake(window_len=20000, sample_every=20, ckpt_every=500, max_windows=5, eps=1e-3)
+    line = {"suite": "c3", "workload": "cylinder wake 2048x512 Re 1000, windows of 20000, K 500", "dtype": "f32"}
+    sv = Solver(w, "f32")
+    gamma = torch.tensor(w.gamma, dtype=torch.float64, device="cuda", requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = windowed_objective(gamma, sv, w.max_windows * w.window_len)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    g = gamma.grad.cpu().numpy()
+    Jh, Mh, Rh = sv.history()
+    w_eff = len(Jh)
+    line.update({"w_eff": w_eff, "J": float(J), "window_J": [float(v) for v in Jh],
+                 "rel_change": [None if not np.isfinite(r) else float(r) for r in Rh],
+                 "forward_s": round(t1 - t0, 3), "adjoint_s": round(t2 - t1, 3),
+                 "forward_mlups": round(w_eff * w.window_len * w.nodes / (t1 - t0) / 1e6, 1),
+                 "reverse_sweep_mlups": round(w.window_len * w.nodes / (t2 - t1) / 1e6, 1),
+                 "workspace_GB": round(sv.workspace_bytes / 1e9, 2)})
+    sv.set_gamma(w.gamma)
+    sv.forward((w_eff - 1) * w.window_len)
+    start = sv.get_state()
+    rng = np.random.default_rng(0)
+    X, Y = np.meshgrid(np.arange(2048), np.arange(512), indexing="ij")
+    cand = np.argwhere(((w.gamma > 0) & (w.gamma < 1)) | ((X >= 544) & (X < 704) & (np.abs(Y - 256) <= 64)))
+    pick = [tuple(int(v) for v in cand[i]) for i in rng.choice(len(cand), 16, replace=False)]
+    h = 1e-4
+    fd = {}
+    sv64 = Solver(w, "f64")
+    g64_t = torch.tensor(w.gamma, dtype=torch.float64, device="cuda", requires_grad=True)
+    J64 = windowed_objective(g64_t, sv64, 0, start=start)
+    J64.backward()
+    g64 = g64_t.grad.cpu().numpy()
+    for name, s_, gref in (("f32", sv, g), ("f64", sv64, g64)):
+        errs, errs_top = [], []
+        top = float(np.max(np.abs(gref)))
+        for p in pick:
+            gp = torch.tensor(w.gamma, dtype=torch.float64, device="cuda")
+            gm = gp.clone()
+            gp[p] += h
+            gm[p] -= h
+            d = (float(windowed_objective(gp, s_, 0, start=start)) -
+                 float(windowed_objective(gm, s_, 0, start=start))) / (2 * h)
+            errs.append(abs(d - gref[p]) / max(abs(gref[p]), 1e-300))
+            errs_top.append(abs(d - gref[p]) / top)
+        fd[name] = {"max_rel_err": float(max(errs)), "median_rel_err": float(np.median(errs)),
+                    "max_err_over_max_dJdgamma": float(max(errs_top))}
+    _free(torch, sv, sv64)
+    line["fd_h=1e-4_16_entries"] = fd
+    line["dJdgamma_f32_vs_f64_same_start"] = _rel(g, g64)
+    line["fd_entries"] = [list(p) for p in pick]
+    print(json.dumps(line), flush=True)
+
+
+def c4_suite(args, torch):
+    """The U-bend 1024 x 1024 (legs of width 128 on the west face, Re 2000,
+    uniform inlet 0.03, C_s = 0.1; J = window mean of dissipation plus the
+    pressure drop, dW = 20, K = 500): a spin-up window of 10 000 steps, then
+    the adjoint over the second 10 000-step window, in FP64, FP32 and FP16S
+    from rest (timed) and in FP32 and FP16S from the FP64 state entering the
+    second window. J and dJ/dgamma errors against FP64 and FP16S against
+    FP32."""
+    from paper_2608_19617_amd import workloads as W
+    from paper_2608_19617_amd.solver import Solver
+    w = W.u_bend(window_len=10000, sample_every=20, ckpt_every=500, max_windows=2)
+    w.eps = -1.0
+    gamma_dev = _device_gamma(w, torch)
+    res = {}
+    f_start = None
+    for prec in ("f64", "f32", "f16s"):
+        sv = Solver(w, prec)
+        sv.set_gamma(gamma_dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sv.forward(w.window_len)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if prec == "f64":
+            f_start = sv.get_state()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        sv.forward(w.window_len)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        g, J = sv.adjoint()
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        res[prec] = {"J": J, "g": g.cpu().numpy(), "forward_s": (t1 - t0) + (t3 - t2), "adjoint_s": t4 - t3}
+        _free(torch, sv)
+    same = {}
+    for prec in ("f32", "f16s"):
+        sv = Solver(w, prec)
+        sv.set_gamma(gamma_dev)
+        sv.set_state(*f_start)
+        sv.forward(w.window_len)
+        g, J = sv.adjoint()
+        same[prec] = (J, g.cpu().numpy())
+        _free(torch, sv)
+    N = w.nodes
+    line = {"suite": "c4", "workload": "U-bend 1024x1024 Re 2000, spin-up window + 10000-step window", "precisions": {}}
+    for prec, r in res.items():
+        e = {"J": r["J"], "forward_mlups": round(2 * w.window_len * N / r["forward_s"] / 1e6, 1),
+             "reverse_sweep_mlups": round(w.window_len * N / r["adjoint_s"] / 1e6, 1),
+             "step_s": round(r["forward_s"] + r["adjoint_s"], 3)}
+        if prec != "f64":
+            J64, g64 = res["f64"]["J"], res["f64"]["g"]
+            Js, gs = same[prec]
+            e["speedup_vs_f64"] = round((res["f64"]["forward_s"] + res["f64"]["adjoint_s"]) / e["step_s"], 3)
+            e["vs_f64_from_rest"] = {"J_rel_err": abs(r["J"] - J64) / abs(J64), "dJdgamma_rel_l2": _rel(r["g"], g64)}
+            e["vs_f64_same_start"] = {"J_rel_err": abs(Js - J64) / abs(J64), "dJdgamma_rel_l2": _rel(gs, g64)}
+        line["precisions"][prec] = e
+    J32, g32 = same["f32"]
+    J16, g16 = same["f16s"]
+    line["f16s_vs_f32_same_start"] = {"J_rel_err": abs(J16 - J32) / abs(J32), "dJdgamma_rel_l2": _rel(g16, g32)}
+    line["f16s_vs_f32_from_rest"] = {"J_rel_err": abs(res["f16s"]["J"] - res["f32"]["J"]) / abs(res["f32"]["J"]),
+                                     "dJdgamma_rel_l2": _rel(res["f16s"]["g"], res["f32"]["g"])}
+    print(json.dumps(line), flush=True)
+
+
 # ------------------------------------------------------ conditioning suite
 
 def _conditioning_cases():
@@ -1155,7 +1295,8 @@ def main():
         counters_run(args, torch)
         return
     suites = {"bfs": bfs_bench, "hbm": hbm_suite, "design": design_suite, "fulltime": fulltime_suite,
-              "paper": paper_suite, "optimize": optimize_suite, "conditioning": conditioning_suite}
+              "paper": paper_suite, "optimize": optimize_suite, "conditioning": conditioning_suite,
+              "c3": c3_suite, "c4": c4_suite}
     if args.suite:
         suites[args.suite](args, torch)
         return
