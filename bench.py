@@ -872,6 +872,12 @@ def c5_precisions(w, gamma_dev, res, args, torch):
         ss = out[prec]["same_start"]
         out[prec]["bars"] = {"J_window_1e-3": None if bj is None else ss["J_rel_err"] <= bj,
                              "dJdgamma_" + ("1e-4" if prec == "f32" else "1e-2"): ss["dJdgamma_rel_l2"] <= bg}
+    # the configured 5000-step window amplifies state perturbations about
+    # 2e6-fold (bench.py --suite conditioning): its gradient is
+    # ill-conditioned, and FP64's own J moves by about 1% when its start
+    # state changes by rounding; the window lengths at which each bar holds
+    # are measured there
+    out["window_gradient_conditioning"] = "profiles/precision_conditioning.md"
     return out
 
 

@@ -305,20 +305,22 @@ lbm_status lbm_set_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y);
  * steps per launch (the recompute of the adjoint sweep too, storing the
  * moment records of both steps). A workgroup owns tile_x x tile_y nodes in
  * x and y and tile_z consecutive z planes; it takes the first step plane by
- * plane over the tile grown by one node in x and y, keeping three planes of
- * that state in LDS (walls on x and y faces as ghost cells, as for D2Q9),
- * and the second step of each plane as soon as the plane above is ready.
- * nsteps = 1 turns it off. Requires at least 256 nodes per block,
- * (tile_x + 2) * (tile_y + 2) <= 1024 and 3 (tile_x + 2)(tile_y + 2) x
- * (19 state values in the storage-rounded LDS type + one compute-type
- * value) within 159 KB, and a state (19 x nodes x storage bytes) and a
- * moment record (10 x nodes x compute bytes) below 4 GB each. Samples,
- * checkpoints and window ends fall on a launch's last step as in 2D.
- * Default (set by lbm_init): FP32 grids of more than 2M nodes take 2 steps
- * on 32 x 13 tiles, with the z run that lets the blocks fill the compute
- * units in nearly whole rounds with the fewest halo planes; other D3Q19
- * contexts take single steps. Errors: LBM_E_INVALID for a D2Q9 context or
- * out-of-range arguments, LBM_E_HIP if the LDS opt-in fails. */
+ * plane over the tile grown by one node in x and y, keeping that state in
+ * an LDS ring (walls on x and y faces as ghost cells, as for D2Q9), and the
+ * second step of each plane as soon as the plane above is ready. The ring
+ * keeps each direction of a plane only as long as the second step reads it
+ * (43 plane slots in all). nsteps = 1 turns it off. Requires
+ * at least 256 nodes per block, (tile_x + 2) * (tile_y + 2) <= 1024 and
+ * (tile_x + 2)(tile_y + 2) x (43 state values in the storage-rounded LDS
+ * type + two compute-type values) within 159 KB, and a state (19 x nodes x
+ * storage bytes) and a moment record (10 x nodes x compute bytes) below
+ * 4 GB each. Samples, checkpoints and window ends fall on a launch's last
+ * step as in 2D. Default (set by lbm_init): FP32 grids of more than 2M
+ * nodes take 2 steps on 32 x 19 tiles (768 threads per workgroup), with the
+ * z run that lets the blocks fill the compute units in nearly whole rounds
+ * with the fewest halo planes; other D3Q19 contexts take single steps.
+ * Errors: LBM_E_INVALID for a D2Q9 context or out-of-range arguments,
+ * LBM_E_HIP if the LDS opt-in fails. */
 lbm_status lbm_set_blocking_3d(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y, int tile_z);
 
 /* Blocking of the adjoint launches that read their pre-states' moment

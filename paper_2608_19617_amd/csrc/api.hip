@@ -929,14 +929,13 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
         if ((st = set_blocking(c, nt, tx, ty)) != LBM_OK) return bail(st);
     } else if (cfg->prec == LBM_F32 && L.N > 2000000 && cfg->nx >= 32 && cfg->ny >= 13 &&
                (size_t)L.Q * L.N * L.ss <= TBZ_STATE_MAX) {
-        // D3Q19 FP32 on large grids: two steps per launch on 32 x 13 tiles
-        // (rows of whole 128-byte lines, one workgroup of 512 threads per
-        // compute unit), z runs as long as possible while the blocks still
-        // fill the compute units in nearly whole rounds (measured on MI355X:
-        // 0.75 of the HBM peak in algorithmic bytes against 0.63 for single
-        // steps on the 384 x 128 x 128 channel). FP64 and FP16S stay single
-        // steps: their blocked launches measured no faster.
-        if ((st = set_blocking_3d(c, 2, 32, 13, default_z_run(c, 32, 13))) != LBM_OK) return bail(st);
+        // D3Q19 FP32 on large grids: two steps per launch on 32 x 19 tiles
+        // (rows of whole 128-byte lines; the 714-cell region fits one
+        // compute unit's LDS with 768 threads), z runs as long as possible
+        // while the blocks still fill the compute units in nearly whole
+        // rounds. FP64 and FP16S stay single steps: their blocked launches
+        // measured no faster.
+        if ((st = set_blocking_3d(c, 2, 32, 19, default_z_run(c, 32, 19))) != LBM_OK) return bail(st);
     }
     if (cfg->lattice == LBM_D3Q19 && cfg->prec != LBM_F64 && L.N > 2000000 && cfg->nx >= 32 && cfg->ny >= 13 &&
         (size_t)10 * L.N * L.cs <= TBZ_STATE_MAX && (size_t)L.Q * L.N * L.as <= TBZ_STATE_MAX) {

@@ -630,27 +630,29 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
 // an output block of ox x oy x oz nodes: an xy tile and a run of oz planes.
 // Step 1 is taken plane by plane, from the plane below the run to the plane
 // above it, over the tile grown by one node in x and y (cut to the domain on
-// non-periodic axes), and its post-collision state is kept in LDS in a ring
-// of three plane slots; step 2 of plane k follows once step 1 of plane k + 1
-// is in the ring, pulls from the three slots and writes to global memory.
-// The global loads of the next step-1 plane are issued before step 2 of the
+// non-periodic axes), and its post-collision state is kept in an LDS ring;
+// step 2 of plane k follows once step 1 of plane k + 1 is in the ring, pulls
+// from the planes k - 1, k and k + 1 there and writes to global memory. The
+// global loads of the next step-1 planes are issued before step 2 of the
 // current plane, so they are in flight while it computes. Halo work is only
 // in x and y (plus two planes per run), unlike a tile grown in all three
 // axes.
 //
-// Walls on x and y faces are ghost cells as in the D2Q9 kernel: a face node
-// stores each population leaving across the face at cell + c_b in plane
-// opp(b) of the slot of plane k + c_bz. A wall on a z face is the halfway
-// reflection taken in the step-2 pull itself; a whole plane lies on such a
-// face, so that choice is uniform across the workgroup. Slot reuse is safe:
-// step 1 of plane k + 1 writes ghosts into the slot of plane k + 2, which
-// still holds plane k - 1 for step 2 of plane k, but only into planes with
-// c_z = -1, and step 2 reads plane k - 1 only in planes with c_z = +1.
+// The ring holds each direction of a plane only as long as it is read (see
+// TbzRing): 43 plane slots instead of three whole planes (57), so a 32 x 19
+// tile with its halo (714 cells) fits one compute unit with 768 threads.
 //
-// LDS: the s values of the three slots (compute type), then the three slots
-// of Q planes of (ox + 2) x (oy + 2) values in the storage-rounded LDS type.
-// TB threads (256 for planes of up to 256 region cells, else 512) take U
-// cells each of a plane (U = 2 for regions of more than 512 cells).
+// Walls on x and y faces are ghost cells as in the D2Q9 kernel: a face node
+// stores each population b leaving across the face at cell + c_b in the slot
+// of direction opp(b) of plane k + c_bz, where step 2 of the plane that
+// pulls it looks. A wall on a z face is the halfway reflection taken in the
+// step-2 pull itself (the node's own opp(a) value of plane k); a whole plane
+// lies on such a face, so that choice is uniform across the workgroup.
+//
+// LDS: the s values of two planes (compute type), then the 43 plane slots of
+// (ox + 2) x (oy + 2) values in the storage-rounded LDS type. TB threads
+// (256, 512 or 768 for planes of up to that many region cells, else 512
+// threads with two cells each) take U cells each of a plane.
 
 // Open-face code of a node's (x, y) position (open_code without the z test).
 __device__ __forceinline__ int open_code_xy(const Geo& g, int x, int y) {
@@ -666,12 +668,12 @@ __device__ __forceinline__ int open_code_xy(const Geo& g, int x, int y) {
     return 0;
 }
 
-// Ghost-cell stores of a D3Q19 node on non-periodic x or y faces. Forward
-// (SGN = +1): each direction b leaving across such a face stores v[b] at
-// cell + c_b (in x, y) in plane opp(b) of the slot of the plane the
-// direction reaches (slot[c_bz + 1]). Adjoint (SGN = -1): each direction b
-// whose -c_b leaves stores v[b] at cell - c_b in plane opp(b) of
-// slot[1 - c_bz]. Slots are Q * psz apart.
+// Ghost-cell stores of a D3Q19 node on non-periodic x or y faces into a
+// ring of three whole-plane slots Q * psz apart (the adjoint's). SGN = +1:
+// each direction b leaving across such a face stores v[b] at cell + c_b (in
+// x, y) in plane opp(b) of slot[c_bz + 1]. SGN = -1 (adjoint): each
+// direction b whose -c_b leaves stores v[b] at cell - c_b in plane opp(b)
+// of slot[1 - c_bz].
 template <class LT, class T, int SGN>
 __device__ __forceinline__ void tbz_ghosts(const Geo& g, LT* __restrict__ ring, int psz, int LW, int LH,
                                            const int slot[3], const TbCell& c, const T v[19]) {
@@ -697,6 +699,52 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 
+// Plane slots of the forward z-marching ring. Step 2 of plane k pulls its
+// c_z = +1 directions from plane k - 1, its c_z = 0 directions from plane k
+// and its c_z = -1 directions from plane k + 1, and runs in the ring level
+// after step 1 of plane k + 1. So a plane's c_z = -1 directions are read in
+// the level that writes them, its c_z = 0 directions one level later and
+// its c_z = +1 directions two levels later. Counting also the ghosts that a
+// face node of plane k writes into planes k - 1 and k + 1, the classes need
+// two, two and three slots: 2 * 5 + 2 * 9 + 3 * 5 = 43 planes, taken in
+// turn by ring level (level j holds plane zs - 1 + j).
+struct TbzRing {
+    static constexpr int PLANES = 43;
+    static constexpr int cls(int a) { return D3Q19::cz[a] + 1; }   // 0: c_z = -1, 1: c_z = 0, 2: c_z = +1
+    static constexpr int slots(int k) { return k == 2 ? 3 : 2; }
+    static constexpr int count(int k) { return k == 1 ? 9 : 5; }
+    static constexpr int first(int k) { return k == 0 ? 0 : (k == 1 ? 10 : 28); }
+    static constexpr int rank(int a) {
+        int r = 0;
+        for (int b = 0; b < a; ++b) r += D3Q19::cz[b] == D3Q19::cz[a] ? 1 : 0;
+        return r;
+    }
+    // plane slot of direction a for ring level j >= -1
+    static __device__ __forceinline__ int plane(int a, int j) {
+        const int k = cls(a);
+        return first(k) + ((j + 6) % slots(k)) * count(k) + rank(a);
+    }
+};
+
+// Ghost-cell stores of a D3Q19 node of ring level j on non-periodic x or y
+// faces (forward): each direction b leaving across such a face stores v[b]
+// at cell + c_b (in x, y) in the slot of direction opp(b) of level j + c_bz.
+template <class LT, class T>
+__device__ __forceinline__ void tbz_ghosts_fwd(const Geo& g, LT* __restrict__ ring, int psz, int LW, int LH, int j,
+                                               const TbCell& c, const T v[19]) {
+    using L = D3Q19;
+    const bool inner = c.lx >= 1 && c.ly >= 1 && c.lx <= LW - 2 && c.ly <= LH - 2;
+    if (!inner) return;
+    const bool fx0 = !g.per_x && c.x == 0, fx1 = !g.per_x && c.x == g.nx - 1;
+    const bool fy0 = !g.per_y && c.y == 0, fy1 = !g.per_y && c.y == g.ny - 1;
+#pragma unroll
+    for (int b = 1; b < L::Q; ++b) {
+        const int sx = L::cx[b], sy = L::cy[b];
+        const bool leaves = (sx < 0 && fx0) || (sx > 0 && fx1) || (sy < 0 && fy0) || (sy > 0 && fy1);
+        if (leaves) ring[TbzRing::plane(L::opp[b], j + L::cz[b]) * psz + c.cell + sy * LW + sx] = (LT)v[b];
+    }
+}
+
 template <class S, class T, bool SAMPLE, bool WPRE, int TB, int U, bool REC = false>
 __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* __restrict__ gout,
                                                  S* __restrict__ pre, const T* __restrict__ sfield, Geo g, Phys ph,
@@ -709,7 +757,7 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
     extern __shared__ unsigned char lds_raw[];
     const int LW = ox + 2, LH = oy + 2, psz = LW * LH;
     T* sring = reinterpret_cast<T*>(lds_raw);
-    LT* ring = reinterpret_cast<LT*>(sring + 3 * psz);
+    LT* ring = reinterpret_cast<LT*>(sring + 2 * psz);
     // blocks are numbered x fastest, then y, then z run; each XCD takes a
     // contiguous range of those numbers (workgroup b runs on XCD b mod 8), so
     // the tiles that share halo rows and cache lines mostly share an L2
@@ -798,9 +846,7 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
         }
         if (ok) {
             const bool zf = !g.per_z && (z == 0 || z == g.nz - 1);
-            const int slot[3] = {(j + 2) % 3, j % 3, (j + 1) % 3};
-            LT* dst = ring + slot[1] * L::Q * psz;
-            T* sdst = sring + slot[1] * psz;
+            T* sdst = sring + ((j + 6) % 2) * psz;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (!v1[u]) continue;
@@ -815,8 +861,8 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
                 T out[L::Q];
                 collide<L, T>(mo, s[u], out);
 #pragma unroll
-                for (int a = 0; a < L::Q; ++a) dst[a * psz + c1[u].cell] = (LT)out[a];
-                if (f1[u]) tbz_ghosts<LT, T, 1>(g, ring, psz, LW, LH, slot, c1[u], out);
+                for (int a = 0; a < L::Q; ++a) ring[TbzRing::plane(a, j) * psz + c1[u].cell] = (LT)out[a];
+                if (f1[u]) tbz_ghosts_fwd<LT, T>(g, ring, psz, LW, LH, j, c1[u], out);
             }
         }
         if (REC) {
@@ -852,18 +898,13 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
         if (ok) {
             const bool zlo = !g.per_z && z == 0, zhi = !g.per_z && z == g.nz - 1;
             const bool zf = zlo || zhi;
-            const int sm = (k + 2) % 3, s0 = k % 3, sp = (k + 1) % 3;
             int off[L::Q];   // uniform source offset of each direction, relative to the cell
 #pragma unroll
             for (int a = 0; a < L::Q; ++a) {
                 const int shift = -(L::cy[a] * LW + L::cx[a]);
-                if (L::cz[a] == 0) {
-                    off[a] = (s0 * L::Q + a) * psz + shift;
-                } else {
-                    const bool refl = L::cz[a] > 0 ? zlo : zhi;   // source beyond a z wall
-                    const int sl = L::cz[a] > 0 ? sm : sp;
-                    off[a] = refl ? (s0 * L::Q + L::opp[a]) * psz : (sl * L::Q + a) * psz + shift;
-                }
+                // the source plane is k - c_az; beyond a z wall, the node's own opp(a)
+                const bool refl = (L::cz[a] > 0 && zlo) || (L::cz[a] < 0 && zhi);
+                off[a] = refl ? TbzRing::plane(L::opp[a], k) * psz : TbzRing::plane(a, k - L::cz[a]) * psz + shift;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -879,7 +920,7 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
                 Moments<L, T> mo;
                 moments<L, T>(h, ph, mo);
                 if (REC) record_values<L, T>(mo, rv[u]);
-                const T sc = sring[s0 * psz + c.cell];
+                const T sc = sring[((k + 6) % 2) * psz + c.cell];
                 if (SAMPLE && v2[u]) {
                     double vv[3];
                     node_samples<L, T>(ob, c.x, c.y, z, sc, mo, vv);
@@ -1690,10 +1731,14 @@ static void launch_tbz(const StepLaunch& a) {
                        a.rec_slot / sizeof(T))
     if (nt == 256) {
         LBM_TBZ(256, 1);
-    } else if (u == 1) {
+    } else if (nt == 512 && u == 1) {
         LBM_TBZ(512, 1);
     } else if constexpr (sizeof(T) == 4) {   // FP64 regions never exceed 512 cells (LDS)
-        LBM_TBZ(512, 2);
+        if (u == 1) {
+            LBM_TBZ(768, 1);
+        } else {
+            LBM_TBZ(512, 2);
+        }
     }
 #undef LBM_TBZ
 }
@@ -1974,9 +2019,9 @@ size_t tb_lds_bytes_prec(int nsteps, int tile_x, int tile_y, int prec) {
 }
 
 size_t tbz_lds_bytes(int tile_x, int tile_y, size_t lsize, size_t vsize) {
-    // three plane slots: s values, then the Q state planes
+    // s values of two planes, then the plane slots of the ring
     const size_t psz = (size_t)(tile_x + 2) * (tile_y + 2);
-    return 3 * psz * (vsize + 19 * lsize);
+    return psz * (2 * vsize + TbzRing::PLANES * lsize);
 }
 
 size_t tbz_lds_bytes_prec(int tile_x, int tile_y, int prec) {
@@ -1984,7 +2029,10 @@ size_t tbz_lds_bytes_prec(int tile_x, int tile_y, int prec) {
                      : tbz_lds_bytes(tile_x, tile_y, prec == 1 ? 4 : 2, 4);
 }
 
-int tbz_threads(int tile_x, int tile_y) { return (long)(tile_x + 2) * (tile_y + 2) <= 256 ? 256 : 512; }
+int tbz_threads(int tile_x, int tile_y) {
+    const long cells = (long)(tile_x + 2) * (tile_y + 2);
+    return cells <= 256 ? 256 : (cells <= 512 ? 512 : (cells <= 768 ? 768 : 512));
+}
 
 size_t adj_tbz_lds_bytes(int tile_x, int tile_y, size_t asize, size_t tsize) {
     // three plane slots: FP64 sensitivity, s, then the Q adjoint planes
@@ -1992,7 +2040,7 @@ size_t adj_tbz_lds_bytes(int tile_x, int tile_y, size_t asize, size_t tsize) {
     return 3 * psz * (8 + tsize + 19 * asize);
 }
 
-int tbz_cells(int tile_x, int tile_y) { return (long)(tile_x + 2) * (tile_y + 2) <= 512 ? 1 : 2; }
+int tbz_cells(int tile_x, int tile_y) { return (long)(tile_x + 2) * (tile_y + 2) <= 768 ? 1 : 2; }
 
 long tb_blocks(int nx, int ny, int tile_x, int tile_y) {
     return (long)((nx + tile_x - 1) / tile_x) * ((ny + tile_y - 1) / tile_y);
@@ -2050,6 +2098,7 @@ static hipError_t tb_attr_all(int b) {
     if (e == hipSuccess) e = tbz_attr<S, T, 256, 1>(b);
     if (e == hipSuccess) e = tbz_attr<S, T, 512, 1>(b);
     if constexpr (sizeof(T) == 4) {
+        if (e == hipSuccess) e = tbz_attr<S, T, 768, 1>(b);
         if (e == hipSuccess) e = tbz_attr<S, T, 512, 2>(b);
     }
     if (e == hipSuccess) e = tb_attr<S, T, A, 512, 0>(b);

@@ -333,8 +333,10 @@ def test_blocked_d3q19_matches_single_steps(Solver, prec, case):
     f0 = random_start_state(prob, seed=23 + case)
     tol = {"f64": 1e-13, "f32": 1e-6, "f16s": 1e-3}[prec]
     res = {}
+    # 256-thread (a, b, c), 512-thread (e, FP64 d), 768-thread (d) and two-cells-per-thread (f) launches
     blocks = (("single", (1,)), ("a", (2, 8, 8, 4)), ("b", (2, 16, 4, 4)), ("c", (2, 7, 5, 8)),
-              ("d", (2, 16, 14, 2) if prec == "f64" else (2, 24, 24, 2)), ("e", (2, 16, 16, 1)))
+              ("d", (2, 16, 14, 2) if prec == "f64" else (2, 24, 24, 2)), ("e", (2, 16, 16, 1)),
+              ("f", (2, 20, 12, 3) if prec == "f64" else (2, 30, 25, 2)))
     for key, blk in blocks:
         sv = Solver(w, prec)
         sv.set_blocking_3d(*blk) if len(blk) > 1 else sv.set_blocking_3d(1)
@@ -347,7 +349,7 @@ def test_blocked_d3q19_matches_single_steps(Solver, prec, case):
         res[key] = (f, J, g.cpu().numpy())
         sv.close()
     f1, J1, g1 = res["single"]
-    for key in ("a", "b", "c", "d", "e"):
+    for key in ("a", "b", "c", "d", "e", "f"):
         f, J, g = res[key]
         assert rel_l2(f, f1) <= tol, (key, rel_l2(f, f1))
         assert np.max(np.abs(J - J1)) <= tol * np.max(np.abs(J1)) + 1e-15
