@@ -338,20 +338,21 @@ lbm_status lbm_set_adjoint_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int ti
  * moment records from a recomputed segment: nsteps = 2 takes two reverse
  * steps per launch. A workgroup owns tile_x x tile_y nodes in x and y and
  * tile_z consecutive z planes; the first step runs plane by plane over the
- * tile grown by one node in x and y, keeping three planes of adjoint
- * populations in LDS (walls on x and y faces as ghost cells, 0 behind open
- * faces), and the second gathers from them; each step reads its own
- * pre-state's record from the segment, and the tile's sensitivity takes
- * one FP64 read-modify-write per launch. nsteps = 1 turns it off. Requires
- * at least 256 nodes per block, (tile_x + 2) * (tile_y + 2) <= 512 (256
- * for LBM_F64), 3 (tile_x + 2) x (tile_y + 2) x (8 + one compute-type
- * value + 19 adjoint values) bytes within 159 KB, and a moment record and
+ * tile grown by one node in x and y, keeping its adjoint populations in an
+ * LDS ring that holds each direction only as long as the second step
+ * gathers it (43 plane slots; walls on x and y faces as ghost cells, 0
+ * behind open faces), and the second gathers from it; each step reads its
+ * own pre-state's record from the segment, and the tile's sensitivity
+ * takes one FP64 read-modify-write per launch. nsteps = 1 turns it off.
+ * Requires at least 256 nodes per block, (tile_x + 2) * (tile_y + 2) <= 768
+ * (256 for LBM_F64), (tile_x + 2) x (tile_y + 2) x (16 + two compute-type
+ * values + 43 adjoint values) bytes within 159 KB, and a moment record and
  * the adjoint populations below 4 GB each. Default (set by lbm_init): FP32
- * and FP16S grids of more than 2M nodes take 2 steps on 32 x 13 or 48 x 8
- * tiles, whichever has the shorter path per compute unit (rounds of
- * workgroups times the step-1 region of a block) with its z run chosen as
- * for the forward; FP64 and smaller grids take single steps. Errors: LBM_E_INVALID for a D2Q9 context or out-of-range
- * arguments, LBM_E_HIP if the LDS opt-in fails. */
+ * and FP16S grids of more than 2M nodes take 2 steps (tiles in
+ * lbm_init's measured default) with the z run chosen as for the forward;
+ * FP64 and smaller grids take single steps. Errors: LBM_E_INVALID for a
+ * D2Q9 context or out-of-range arguments, LBM_E_HIP if the LDS opt-in
+ * fails. */
 lbm_status lbm_set_adjoint_blocking_3d(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y, int tile_z);
 
 /* Thread-local message of the last failing call on this thread. */

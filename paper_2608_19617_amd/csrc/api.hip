@@ -514,9 +514,9 @@ lbm_status set_adj_blocking_3d(lbm_ctx* c, int nsteps, int tile_x, int tile_y, i
     if (nsteps == 2) {
         if (tile_x < 1 || tile_y < 1 || tile_z < 1 || (long)tile_x * tile_y * tile_z < 256)
             return fail(LBM_E_INVALID, "tile must hold at least 256 nodes");
-        const long cells_max = c->L.as == 8 ? 256 : 512;   // one cell per thread; FP64 uses 256 threads
+        const long cells_max = c->L.as == 8 ? 256 : 768;   // one cell per thread; FP64 uses 256 threads
         if ((long)(tile_x + 2) * (tile_y + 2) > cells_max)
-            return fail(LBM_E_INVALID, "(tile_x + 2) * (tile_y + 2) too large (512, FP64 256)");
+            return fail(LBM_E_INVALID, "(tile_x + 2) * (tile_y + 2) too large (768, FP64 256)");
         if (adj_tbz_lds_bytes(tile_x, tile_y, c->L.as, c->L.cs) > TB_LDS_MAX)
             return fail(LBM_E_INVALID, "tile needs more than 159 KB of LDS");
         if ((size_t)10 * c->L.N * c->L.cs > TBZ_STATE_MAX || (size_t)c->L.Q * c->L.N * c->L.as > TBZ_STATE_MAX)
@@ -562,18 +562,6 @@ static int default_z_run(lbm_ctx* c, int tile_x, int tile_y) {
         }
     }
     return best;
-}
-
-// Critical path of a two-step z-marching launch per compute unit, in cell
-// updates of one step: rounds of workgroups times the step-1 region of a
-// block (the tile grown by one node in x and y, its run grown by one plane
-// on each side).
-static double tbz_cost(lbm_ctx* c, int tile_x, int tile_y, int oz) {
-    const int cus = compute_units();
-    const long tiles = (long)((c->cfg.nx + tile_x - 1) / tile_x) * ((c->cfg.ny + tile_y - 1) / tile_y);
-    const long blocks = tiles * ((c->cfg.nz + oz - 1) / oz);
-    const long rounds = (blocks + cus - 1) / cus;
-    return (double)rounds * (tile_x + 2.0) * (tile_y + 2.0) * (oz + 2.0);
 }
 
 lbm_status set_adj_blocking(lbm_ctx* c, int nsteps, int tile_x, int tile_y) {
@@ -940,21 +928,18 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
     if (cfg->lattice == LBM_D3Q19 && cfg->prec != LBM_F64 && L.N > 2000000 && cfg->nx >= 32 && cfg->ny >= 13 &&
         (size_t)10 * L.N * L.cs <= TBZ_STATE_MAX && (size_t)L.Q * L.N * L.as <= TBZ_STATE_MAX) {
         // D3Q19 adjoint with FP32 adjoint populations on large grids: two
-        // reverse steps per launch, on 32 x 13 tiles or, where its blocks fill
-        // the compute units better for less halo work, 48 x 8 (measured on
-        // MI355X on the 384 x 128 x 128 channel, FP32: 236 us per reverse
-        // step on 48 x 8 tiles in z runs of 64, 256 workgroups, against 245
-        // on 32 x 13, 240 workgroups, and 265 for single steps). FP64 stays
-        // single-step (its blocked launches measured slower).
-        int atx = 32, aty = 13, aoz = default_z_run(c, 32, 13);
+        // reverse steps per launch with 768 threads on 48 x 13 tiles (32 x 19
+        // on grids narrower than 48), z runs chosen as for the forward
+        // (measured on MI355X on the 384 x 128 x 128 channel, FP32: 212 us per
+        // reverse step on 48 x 13, 219 on 32 x 19, 230 on the 512-thread 48 x 8
+        // tiles and 238 on 32 x 13). FP64 stays single-step (its blocked
+        // launches measured slower).
+        int atx = 32, aty = 19;
         if (cfg->nx >= 48) {
-            const int oz = default_z_run(c, 48, 8);
-            if (tbz_cost(c, 48, 8, oz) < tbz_cost(c, atx, aty, aoz)) {
-                atx = 48;
-                aty = 8;
-                aoz = oz;
-            }
+            atx = 48;
+            aty = 13;
         }
+        const int aoz = default_z_run(c, atx, aty);
         if ((st = set_adj_blocking_3d(c, 2, atx, aty, aoz)) != LBM_OK) return bail(st);
     }
     hipError_t e = hipStreamSynchronize(c->stream);

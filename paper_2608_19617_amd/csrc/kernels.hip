@@ -668,28 +668,6 @@ __device__ __forceinline__ int open_code_xy(const Geo& g, int x, int y) {
     return 0;
 }
 
-// Ghost-cell stores of a D3Q19 node on non-periodic x or y faces into a
-// ring of three whole-plane slots Q * psz apart (the adjoint's). SGN = +1:
-// each direction b leaving across such a face stores v[b] at cell + c_b (in
-// x, y) in plane opp(b) of slot[c_bz + 1]. SGN = -1 (adjoint): each
-// direction b whose -c_b leaves stores v[b] at cell - c_b in plane opp(b)
-// of slot[1 - c_bz].
-template <class LT, class T, int SGN>
-__device__ __forceinline__ void tbz_ghosts(const Geo& g, LT* __restrict__ ring, int psz, int LW, int LH,
-                                           const int slot[3], const TbCell& c, const T v[19]) {
-    using L = D3Q19;
-    const bool inner = c.lx >= 1 && c.ly >= 1 && c.lx <= LW - 2 && c.ly <= LH - 2;
-    if (!inner) return;
-    const bool fx0 = !g.per_x && c.x == 0, fx1 = !g.per_x && c.x == g.nx - 1;
-    const bool fy0 = !g.per_y && c.y == 0, fy1 = !g.per_y && c.y == g.ny - 1;
-#pragma unroll
-    for (int b = 1; b < L::Q; ++b) {
-        const int sx = SGN * L::cx[b], sy = SGN * L::cy[b];
-        const bool leaves = (sx < 0 && fx0) || (sx > 0 && fx1) || (sy < 0 && fy0) || (sy > 0 && fy1);
-        if (leaves) ring[(slot[SGN * L::cz[b] + 1] * L::Q + L::opp[b]) * psz + c.cell + sy * LW + sx] = (LT)v[b];
-    }
-}
-
 // Workgroup barrier that orders LDS accesses only, so global loads issued
 // before it stay in flight across it.
 __device__ __forceinline__ void lds_barrier() {
@@ -699,18 +677,22 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 
-// Plane slots of the forward z-marching ring. Step 2 of plane k pulls its
-// c_z = +1 directions from plane k - 1, its c_z = 0 directions from plane k
-// and its c_z = -1 directions from plane k + 1, and runs in the ring level
-// after step 1 of plane k + 1. So a plane's c_z = -1 directions are read in
-// the level that writes them, its c_z = 0 directions one level later and
-// its c_z = +1 directions two levels later. Counting also the ghosts that a
-// face node of plane k writes into planes k - 1 and k + 1, the classes need
-// two, two and three slots: 2 * 5 + 2 * 9 + 3 * 5 = 43 planes, taken in
-// turn by ring level (level j holds plane zs - 1 + j).
+// Plane slots of the z-marching rings. Forward (SGN = +1): step 2 of plane
+// k pulls its c_z = +1 directions from plane k - 1, its c_z = 0 directions
+// from plane k and its c_z = -1 directions from plane k + 1, and runs in the
+// ring level after step 1 of plane k + 1. So a plane's c_z = -1 directions
+// are read in the level that writes them, its c_z = 0 directions one level
+// later and its c_z = +1 directions two levels later. The adjoint (SGN = -1)
+// gathers from plane k + c_z instead, so the roles of c_z = +1 and -1 swap.
+// Counting also the ghosts that a face node of plane k writes into planes
+// k - 1 and k + 1, the three classes need two, two and three slots:
+// 2 * 5 + 2 * 9 + 3 * 5 = 43 planes instead of three whole planes (57),
+// taken in turn by ring level (level j holds plane zs - 1 + j).
+template <int SGN>
 struct TbzRing {
     static constexpr int PLANES = 43;
-    static constexpr int cls(int a) { return D3Q19::cz[a] + 1; }   // 0: c_z = -1, 1: c_z = 0, 2: c_z = +1
+    // 0: read in the writing level, 1: one level later, 2: two levels later
+    static constexpr int cls(int a) { return SGN * D3Q19::cz[a] + 1; }
     static constexpr int slots(int k) { return k == 2 ? 3 : 2; }
     static constexpr int count(int k) { return k == 1 ? 9 : 5; }
     static constexpr int first(int k) { return k == 0 ? 0 : (k == 1 ? 10 : 28); }
@@ -727,11 +709,14 @@ struct TbzRing {
 };
 
 // Ghost-cell stores of a D3Q19 node of ring level j on non-periodic x or y
-// faces (forward): each direction b leaving across such a face stores v[b]
-// at cell + c_b (in x, y) in the slot of direction opp(b) of level j + c_bz.
-template <class LT, class T>
-__device__ __forceinline__ void tbz_ghosts_fwd(const Geo& g, LT* __restrict__ ring, int psz, int LW, int LH, int j,
-                                               const TbCell& c, const T v[19]) {
+// faces. Forward (SGN = +1): each direction b leaving across such a face
+// stores v[b] at cell + c_b (in x, y) in the slot of direction opp(b) of
+// level j + c_bz. Adjoint (SGN = -1): each direction b whose -c_b leaves
+// stores v[b] at cell - c_b in the slot of direction opp(b) of level
+// j - c_bz.
+template <class LT, class T, int SGN>
+__device__ __forceinline__ void tbz_ghosts(const Geo& g, LT* __restrict__ ring, int psz, int LW, int LH, int j,
+                                           const TbCell& c, const T v[19]) {
     using L = D3Q19;
     const bool inner = c.lx >= 1 && c.ly >= 1 && c.lx <= LW - 2 && c.ly <= LH - 2;
     if (!inner) return;
@@ -739,9 +724,10 @@ __device__ __forceinline__ void tbz_ghosts_fwd(const Geo& g, LT* __restrict__ ri
     const bool fy0 = !g.per_y && c.y == 0, fy1 = !g.per_y && c.y == g.ny - 1;
 #pragma unroll
     for (int b = 1; b < L::Q; ++b) {
-        const int sx = L::cx[b], sy = L::cy[b];
+        const int sx = SGN * L::cx[b], sy = SGN * L::cy[b];
         const bool leaves = (sx < 0 && fx0) || (sx > 0 && fx1) || (sy < 0 && fy0) || (sy > 0 && fy1);
-        if (leaves) ring[TbzRing::plane(L::opp[b], j + L::cz[b]) * psz + c.cell + sy * LW + sx] = (LT)v[b];
+        if (leaves)
+            ring[TbzRing<SGN>::plane(L::opp[b], j + SGN * L::cz[b]) * psz + c.cell + sy * LW + sx] = (LT)v[b];
     }
 }
 
@@ -861,8 +847,8 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
                 T out[L::Q];
                 collide<L, T>(mo, s[u], out);
 #pragma unroll
-                for (int a = 0; a < L::Q; ++a) ring[TbzRing::plane(a, j) * psz + c1[u].cell] = (LT)out[a];
-                if (f1[u]) tbz_ghosts_fwd<LT, T>(g, ring, psz, LW, LH, j, c1[u], out);
+                for (int a = 0; a < L::Q; ++a) ring[TbzRing<1>::plane(a, j) * psz + c1[u].cell] = (LT)out[a];
+                if (f1[u]) tbz_ghosts<LT, T, 1>(g, ring, psz, LW, LH, j, c1[u], out);
             }
         }
         if (REC) {
@@ -904,7 +890,7 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
                 const int shift = -(L::cy[a] * LW + L::cx[a]);
                 // the source plane is k - c_az; beyond a z wall, the node's own opp(a)
                 const bool refl = (L::cz[a] > 0 && zlo) || (L::cz[a] < 0 && zhi);
-                off[a] = refl ? TbzRing::plane(L::opp[a], k) * psz : TbzRing::plane(a, k - L::cz[a]) * psz + shift;
+                off[a] = refl ? TbzRing<1>::plane(L::opp[a], k) * psz : TbzRing<1>::plane(a, k - L::cz[a]) * psz + shift;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -1349,7 +1335,8 @@ __device__ __forceinline__ void gather_index(const Geo& g, int n, int x, int y, 
 // k_hi - 1. Step 1 takes nu_hat^{k_hi} from global memory to
 // nu_hat^{k_hi - 1} plane by plane over the xy tile grown by one node,
 // into a three-slot LDS ring; step 2 of plane z gathers its kappa from the
-// ring (planes z - 1, z, z + 1) and writes nu_hat^{k_hi - 2} for the tile.
+// ring (planes z - 1, z, z + 1) and writes nu_hat^{k_hi - 2} for the tile;
+// the ring keeps each direction of a plane only as long as step 2 reads it.
 // Each step reads the moments of its own pre-state f^{k-1} from the
 // segment's record of that step (record k - 2 - kseg).
 // Walls on x and y faces are ghost cells written by step 1 (nu_hat_b, or 0
@@ -1362,10 +1349,10 @@ __device__ __forceinline__ void gather_index(const Geo& g, int n, int x, int y, 
 // plane (out-of-range offsets for no-ops), and the loads of the next plane
 // are in flight while the current one computes.
 //
-// LDS: three slots each of the sensitivity (FP64), s (compute type) and the
-// Q adjoint planes of (ox + 2) x (oy + 2) values. TB threads (256 for planes
-// of up to 256 region cells and for FP64, else 512) take one cell each of a
-// plane.
+// LDS: two plane slots each of the sensitivity (FP64) and s (compute
+// type), then the 43 plane slots of the adjoint ring (TbzRing<-1>) of
+// (ox + 2) x (oy + 2) values. TB threads (256 for planes of up to 256 region
+// cells and for FP64, else 512 or 768) take one cell each of a plane.
 template <class S, class T, class A, int TB>
 __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in, A* __restrict__ nu_out,
                                                     const T* __restrict__ rseg, size_t slot, long kseg,
@@ -1377,8 +1364,9 @@ __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in,
     extern __shared__ unsigned char lds_raw[];
     const int LW = ox + 2, LH = oy + 2, psz = LW * LH;
     double* dsring = reinterpret_cast<double*>(lds_raw);
-    T* sring = reinterpret_cast<T*>(dsring + 3 * psz);
-    A* ring = reinterpret_cast<A*>(sring + 3 * psz);
+    T* sring = reinterpret_cast<T*>(dsring + 2 * psz);
+    A* ring = reinterpret_cast<A*>(sring + 2 * psz);
+    using RG = TbzRing<-1>;
     const int b = xcd_block();
     const int tx = b % tiles_x, ty = (b / tiles_x) % tiles_y, tz = b / (tiles_x * tiles_y);
     const int x0 = tx * ox - 1, y0 = ty * oy - 1;
@@ -1479,24 +1467,23 @@ __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in,
         if (!level_z(j, z)) return;
         const bool zf = !g.per_z && (z == 0 || z == g.nz - 1);
         const int oc = zf ? 0 : o1;
-        const int slots[3] = {(j + 2) % 3, j % 3, (j + 1) % 3};   // planes z - 1, z, z + 1
+        const int s1 = (j + 6) % 2;
         if (!v1) return;
         T kap[L::Q], mu[L::Q];
 #pragma unroll
         for (int a = 0; a < L::Q; ++a) kap[a] = (T)in.nk[a];
         const T ds = update(in.r, kap, in.s, oc, u1, c1.x, c1.y, z, w1, mu);
-        A* dst = ring + slots[1] * L::Q * psz;
 #pragma unroll
-        for (int a = 0; a < L::Q; ++a) dst[a * psz + c1.cell] = (A)mu[a];
-        sring[slots[1] * psz + c1.cell] = in.s;
-        if (own1) dsring[slots[1] * psz + c1.cell] = (double)ds;
+        for (int a = 0; a < L::Q; ++a) ring[RG::plane(a, j) * psz + c1.cell] = (A)mu[a];
+        sring[s1 * psz + c1.cell] = in.s;
+        if (own1) dsring[s1 * psz + c1.cell] = (double)ds;
         if (f1) {
             // ghost cells of the adjoint wall rule (0 on an open node)
             if (oc) {
 #pragma unroll
                 for (int a = 0; a < L::Q; ++a) mu[a] = (T)0;
             }
-            tbz_ghosts<A, T, -1>(g, ring, psz, LW, LH, slots, c1, mu);
+            tbz_ghosts<A, T, -1>(g, ring, psz, LW, LH, j, c1, mu);
         }
     };
     auto step2 = [&](int k, const In2& in) {
@@ -1510,18 +1497,14 @@ __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in,
         if (ok) {
             const bool zlo = !g.per_z && z == 0, zhi = !g.per_z && z == g.nz - 1;
             const int oc = (zlo || zhi) ? 0 : o2;
-            const int sm = (k + 2) % 3, s0 = k % 3, sp = (k + 1) % 3;
+            const int s0 = (k + 6) % 2;
             int off[L::Q];   // uniform gather offset of each direction, relative to the cell
 #pragma unroll
             for (int a = 0; a < L::Q; ++a) {
                 const int shift = L::cy[a] * LW + L::cx[a];
-                if (L::cz[a] == 0) {
-                    off[a] = (s0 * L::Q + a) * psz + shift;
-                } else {
-                    const bool refl = L::cz[a] > 0 ? zhi : zlo;   // target beyond a z wall
-                    const int sl = L::cz[a] > 0 ? sp : sm;
-                    off[a] = refl ? (s0 * L::Q + L::opp[a]) * psz : (sl * L::Q + a) * psz + shift;
-                }
+                // the target plane is k + c_az; beyond a z wall, the node's own opp(a)
+                const bool refl = (L::cz[a] > 0 && zhi) || (L::cz[a] < 0 && zlo);
+                off[a] = refl ? RG::plane(L::opp[a], k) * psz : RG::plane(a, k + L::cz[a]) * psz + shift;
             }
             T kap[L::Q];
 #pragma unroll
@@ -1543,7 +1526,7 @@ __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in,
     for (int a = 0; a < L::Q; ++a) a1.nk[a] = b1.nk[a] = (A)0;
     a1.s = b1.s = (T)0;
     a2.sold = b2.sold = 0.0;
-    if constexpr (sizeof(A) == 4) {
+    if constexpr (sizeof(A) == 4 && TB <= 512) {
         // ring level j: step 1 of level j from its input set, the step-1
         // loads of level j + 2 into that set, then step 2 of level j - 1
         // and the step-2 loads of level j + 1 into its set. Two sets of each
@@ -1563,7 +1546,8 @@ __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in,
             pass(j + 1, b1, a2);
         }
     } else {
-        // FP64 (no registers for a second set): one level ahead, from -1
+        // FP64, and 768 threads (no registers for a second set): one level
+        // ahead, from -1
         for (int j = -1; j <= nzc + 1; ++j) {
             step1(j, a1);
             load1(j + 1, a1);
@@ -1816,10 +1800,15 @@ static hipError_t adj_t(const AdjLaunch& a) {
     hipLaunchKernelGGL((k_adjoint_tbz<S, T, A, TBV>), grid, dim3(TBV), lds, a.stream, nin, nout, gs, slot,      \
                        a.kseg, sf, a.sens, g, a.ph, a.ob, a.k_hi, a.ns, a.dW, a.wgt, a.tile_x, a.tile_y,        \
                        a.tile_z, tiles_x, tiles_y)
-        if (sizeof(A) == 8 || tbz_threads(a.tile_x, a.tile_y) == 256) {
+        const int nt = tbz_threads(a.tile_x, a.tile_y);
+        if (sizeof(A) == 8 || nt == 256) {
             LBM_ADJ_TBZ(256);   // FP64: one cell per thread of 256 (register budget)
         } else if constexpr (sizeof(A) == 4) {
-            LBM_ADJ_TBZ(512);
+            if (nt == 768) {
+                LBM_ADJ_TBZ(768);
+            } else {
+                LBM_ADJ_TBZ(512);
+            }
         }
 #undef LBM_ADJ_TBZ
         return hipGetLastError();
@@ -2021,7 +2010,7 @@ size_t tb_lds_bytes_prec(int nsteps, int tile_x, int tile_y, int prec) {
 size_t tbz_lds_bytes(int tile_x, int tile_y, size_t lsize, size_t vsize) {
     // s values of two planes, then the plane slots of the ring
     const size_t psz = (size_t)(tile_x + 2) * (tile_y + 2);
-    return psz * (2 * vsize + TbzRing::PLANES * lsize);
+    return psz * (2 * vsize + TbzRing<1>::PLANES * lsize);
 }
 
 size_t tbz_lds_bytes_prec(int tile_x, int tile_y, int prec) {
@@ -2035,9 +2024,9 @@ int tbz_threads(int tile_x, int tile_y) {
 }
 
 size_t adj_tbz_lds_bytes(int tile_x, int tile_y, size_t asize, size_t tsize) {
-    // three plane slots: FP64 sensitivity, s, then the Q adjoint planes
+    // FP64 sensitivity and s of two planes, then the plane slots of the ring
     const size_t psz = (size_t)(tile_x + 2) * (tile_y + 2);
-    return 3 * psz * (8 + tsize + 19 * asize);
+    return psz * (2 * 8 + 2 * tsize + TbzRing<-1>::PLANES * asize);
 }
 
 int tbz_cells(int tile_x, int tile_y) { return (long)(tile_x + 2) * (tile_y + 2) <= 768 ? 1 : 2; }
@@ -2093,6 +2082,9 @@ static hipError_t tb_attr_all(int b) {
     if constexpr (sizeof(A) == 4) {
         if (e == hipSuccess)
             e = hipFuncSetAttribute((const void*)k_adjoint_tbz<S, T, A, 512>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, b);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_adjoint_tbz<S, T, A, 768>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, b);
     }
     if (e == hipSuccess) e = tbz_attr<S, T, 256, 1>(b);

@@ -367,9 +367,9 @@ def test_blocked_d3q19_matches_single_steps(Solver, prec, case):
 def test_blocked_d3q19_adjoint_matches_single_steps(Solver, prec, case):
     """Two-step D3Q19 adjoint launches (z-marching blocks, adjoint wall rule
     as ghost cells or z reflections, 0 behind open faces, one
-    read-modify-write of the sensitivity per launch; 256- and 512-thread
-    blocks) give the dJ/dgamma of single-step adjoint launches after the
-    same forward launches (single and blocked)."""
+    read-modify-write of the sensitivity per launch; 256-, 512- and
+    768-thread blocks) give the dJ/dgamma of single-step adjoint launches
+    after the same forward launches (single and blocked)."""
     name, w = _small_3d_cases()[case]
     w.window_len, w.sample_every, w.ckpt_every, w.max_windows = 8, 2, 8, 2
     prob = oracle_problem(w)
@@ -377,7 +377,8 @@ def test_blocked_d3q19_adjoint_matches_single_steps(Solver, prec, case):
     tol = {"f64": 1e-13, "f32": 1e-6, "f16s": 1e-5}[prec]
     blocks = [(8, 8, 4), (7, 5, 8), (14, 14, 2) if prec == "f64" else (16, 14, 2)]
     if prec != "f64":
-        blocks.append((48, 8, 4))       # the 48 x 8 default shape, wider than the grid, ragged in y
+        blocks.append((48, 8, 4))       # 48 x 8, wider than the grid, ragged in y
+        blocks.append((24, 24, 2))      # a 676-cell region: 768 threads, one input set in flight
     # each blocked adjoint against the single-step adjoint of the same forward
     # launches (forward blocking changes the rounding below FP64)
     runs = [((1,), (1,)), ((1,), (2,) + blocks[0]), ((2, 8, 8, 4), (1,))] + \
@@ -427,11 +428,11 @@ def test_d3q19_record_sweep_blocked_matches_oracle(Solver, prec, K):
 
 
 def test_adjoint_blocking_3d_rejects_bad_blocks(Solver):
-    """Adjoint blocks below 256 nodes, xy regions above 512 cells (256 in
+    """Adjoint blocks below 256 nodes, xy regions above 768 cells (256 in
     FP64), three steps, and a D2Q9 context are refused."""
     from paper_2608_19617_amd.binding import LbmError
     name, w = _small_3d_cases()[0]
-    for prec, bad in (("f32", ((2, 4, 4, 4), (2, 30, 16, 1), (3, 8, 8, 4))), ("f64", ((2, 16, 14, 2),))):
+    for prec, bad in (("f32", ((2, 4, 4, 4), (2, 40, 20, 1), (3, 8, 8, 4))), ("f64", ((2, 16, 14, 2),))):
         sv = Solver(w, prec)
         for blk in bad:
             with pytest.raises(LbmError):
