@@ -651,8 +651,8 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
 //
 // LDS: the s values of two planes (compute type), then the 43 plane slots of
 // (ox + 2) x (oy + 2) values in the storage-rounded LDS type. TB threads
-// (256, 512 or 768 for planes of up to that many region cells, else 512
-// threads with two cells each) take U cells each of a plane.
+// (256, 512, 768 or 1024 for planes of up to that many region cells) take
+// one cell each of a plane (U = 1; the kernel is written for U cells).
 
 // Open-face code of a node's (x, y) position (open_code without the z test).
 __device__ __forceinline__ int open_code_xy(const Geo& g, int x, int y) {
@@ -955,9 +955,21 @@ __global__ __launch_bounds__(TB) void k_step_tbz(const S* __restrict__ gin, S* _
         for (int a = 0; a < L::Q; ++a) hA[u][a] = hB[u][a] = (R)0;
         sA[u] = sB[u] = (T)0;
     }
-    for (int j = -2; j <= nzc + 1; j += 2) {
-        level(j, hA, sA);
-        level(j + 1, hB, sB);
+    if constexpr (TB <= 768) {
+        for (int j = -2; j <= nzc + 1; j += 2) {
+            level(j, hA, sA);
+            level(j + 1, hB, sB);
+        }
+    } else {
+        // 1024 threads: four waves per SIMD hide the loads, and one input set
+        // (loads one level ahead) keeps the kernel within 128 VGPRs
+        for (int j = -1; j <= nzc + 1; ++j) {
+            step1(j, hA, sA);
+            load1(j + 1, hA, sA);
+            lds_barrier();
+            step2(j);
+            lds_barrier();
+        }
     }
     if (SAMPLE) {
         block_sum_n<3, TB>(v, partials + 3 * (size_t)blockIdx.x);
@@ -1707,7 +1719,7 @@ static void launch_tbz(const StepLaunch& a) {
     const int tiles_z = (g.nz + a.tile_z - 1) / a.tile_z;
     const size_t lds = tbz_lds_bytes(a.tile_x, a.tile_y, sizeof(LT), sizeof(T));
     const dim3 grid(tiles_x * tiles_y * tiles_z);
-    const int nt = tbz_threads(a.tile_x, a.tile_y), u = tbz_cells(a.tile_x, a.tile_y);
+    const int nt = tbz_threads(a.tile_x, a.tile_y);   // one cell per thread
 #define LBM_TBZ(TB, U)                                                                                          \
     hipLaunchKernelGGL((k_step_tbz<S, T, SAMPLE, WPRE, TB, U, REC>), grid, dim3(TB), lds, a.stream,             \
                        (const S*)a.gin, (S*)a.gout, (S*)a.pre, (const T*)a.s, g, a.ph, a.ob, a.partials,        \
@@ -1715,13 +1727,13 @@ static void launch_tbz(const StepLaunch& a) {
                        a.rec_slot / sizeof(T))
     if (nt == 256) {
         LBM_TBZ(256, 1);
-    } else if (nt == 512 && u == 1) {
+    } else if (nt == 512) {
         LBM_TBZ(512, 1);
     } else if constexpr (sizeof(T) == 4) {   // FP64 regions never exceed 512 cells (LDS)
-        if (u == 1) {
+        if (nt == 768) {
             LBM_TBZ(768, 1);
         } else {
-            LBM_TBZ(512, 2);
+            LBM_TBZ(1024, 1);
         }
     }
 #undef LBM_TBZ
@@ -2020,7 +2032,7 @@ size_t tbz_lds_bytes_prec(int tile_x, int tile_y, int prec) {
 
 int tbz_threads(int tile_x, int tile_y) {
     const long cells = (long)(tile_x + 2) * (tile_y + 2);
-    return cells <= 256 ? 256 : (cells <= 512 ? 512 : (cells <= 768 ? 768 : 512));
+    return cells <= 256 ? 256 : (cells <= 512 ? 512 : (cells <= 768 ? 768 : 1024));
 }
 
 size_t adj_tbz_lds_bytes(int tile_x, int tile_y, size_t asize, size_t tsize) {
@@ -2029,7 +2041,6 @@ size_t adj_tbz_lds_bytes(int tile_x, int tile_y, size_t asize, size_t tsize) {
     return psz * (2 * 8 + 2 * tsize + TbzRing<-1>::PLANES * asize);
 }
 
-int tbz_cells(int tile_x, int tile_y) { return (long)(tile_x + 2) * (tile_y + 2) <= 768 ? 1 : 2; }
 
 long tb_blocks(int nx, int ny, int tile_x, int tile_y) {
     return (long)((nx + tile_x - 1) / tile_x) * ((ny + tile_y - 1) / tile_y);
@@ -2091,7 +2102,7 @@ static hipError_t tb_attr_all(int b) {
     if (e == hipSuccess) e = tbz_attr<S, T, 512, 1>(b);
     if constexpr (sizeof(T) == 4) {
         if (e == hipSuccess) e = tbz_attr<S, T, 768, 1>(b);
-        if (e == hipSuccess) e = tbz_attr<S, T, 512, 2>(b);
+        if (e == hipSuccess) e = tbz_attr<S, T, 1024, 1>(b);
     }
     if (e == hipSuccess) e = tb_attr<S, T, A, 512, 0>(b);
     if (e == hipSuccess) e = tb_attr<S, T, A, 1024, 0>(b);

@@ -112,7 +112,6 @@ long tb_blocks(int nx, int ny, int tile_x, int tile_y);
 size_t tbz_lds_bytes(int tile_x, int tile_y, size_t lsize, size_t vsize);
 size_t tbz_lds_bytes_prec(int tile_x, int tile_y, int prec);
 int tbz_threads(int tile_x, int tile_y);
-int tbz_cells(int tile_x, int tile_y);
 size_t adj_tbz_lds_bytes(int tile_x, int tile_y, size_t asize, size_t tsize);
 hipError_t tb_prepare(int prec);
 int tb_threads(int nsteps, int tile_x, int tile_y);
