@@ -316,7 +316,8 @@ lbm_status lbm_set_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y);
  * storage bytes) and a moment record (10 x nodes x compute bytes) below
  * 4 GB each. Samples, checkpoints and window ends fall on a launch's last
  * step as in 2D. Default (set by lbm_init): FP32 grids of more than 2M
- * nodes take 2 steps on 32 x 19 tiles (768 threads per workgroup), with the
+ * nodes take 2 steps on 48 x 16 tiles (1024 threads per workgroup; 32 x 19
+ * with 768 threads where nx < 48 or ny < 16), with the
  * z run that lets the blocks fill the compute units in nearly whole rounds
  * with the fewest halo planes; other D3Q19 contexts take single steps.
  * Errors: LBM_E_INVALID for a D2Q9 context or out-of-range arguments,

@@ -917,13 +917,16 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
         if ((st = set_blocking(c, nt, tx, ty)) != LBM_OK) return bail(st);
     } else if (cfg->prec == LBM_F32 && L.N > 2000000 && cfg->nx >= 32 && cfg->ny >= 13 &&
                (size_t)L.Q * L.N * L.ss <= TBZ_STATE_MAX) {
-        // D3Q19 FP32 on large grids: two steps per launch on 32 x 19 tiles
-        // (rows of whole 128-byte lines; the 714-cell region fits one
-        // compute unit's LDS with 768 threads), z runs as long as possible
-        // while the blocks still fill the compute units in nearly whole
-        // rounds. FP64 and FP16S stay single steps: their blocked launches
-        // measured no faster.
-        if ((st = set_blocking_3d(c, 2, 32, 19, default_z_run(c, 32, 19))) != LBM_OK) return bail(st);
+        // D3Q19 FP32 on large grids: two steps per launch on 48 x 16 tiles
+        // (a 900-cell region in one compute unit's LDS, 1024 threads; 32 x 19
+        // with 768 threads on grids narrower than 48 or lower than 16), z runs
+        // as long as possible while the blocks still fill the compute units in
+        // nearly whole rounds (measured on MI355X on the 384 x 128 x 128
+        // channel: 124.9 us per step on 48 x 16 in runs of 32 planes, 131.8 on
+        // 48 x 13 and 140.1 on 32 x 19 with 768 threads). FP64 and FP16S stay
+        // single steps: their blocked launches measured no faster.
+        const int ftx = (cfg->nx >= 48 && cfg->ny >= 16) ? 48 : 32, fty = ftx == 48 ? 16 : 19;
+        if ((st = set_blocking_3d(c, 2, ftx, fty, default_z_run(c, ftx, fty))) != LBM_OK) return bail(st);
     }
     if (cfg->lattice == LBM_D3Q19 && cfg->prec != LBM_F64 && L.N > 2000000 && cfg->nx >= 32 && cfg->ny >= 13 &&
         (size_t)10 * L.N * L.cs <= TBZ_STATE_MAX && (size_t)L.Q * L.N * L.as <= TBZ_STATE_MAX) {

@@ -639,8 +639,9 @@ __global__ __launch_bounds__(TB) void k_step_tb(const S* __restrict__ gin, S* __
 // axes.
 //
 // The ring holds each direction of a plane only as long as it is read (see
-// TbzRing): 43 plane slots instead of three whole planes (57), so a 32 x 19
-// tile with its halo (714 cells) fits one compute unit with 768 threads.
+// TbzRing): 43 plane slots instead of three whole planes (57), so a 48 x 16
+// tile with its halo (900 cells, 158 KB in FP32) fits one compute unit with
+// 1024 threads.
 //
 // Walls on x and y faces are ghost cells as in the D2Q9 kernel: a face node
 // stores each population b leaving across the face at cell + c_b in the slot
