@@ -983,7 +983,7 @@ def c5_roofline(tm, N, prec):
     if traffic is not None:
         line["traffic_GBs"] = round(traffic / launch_s / 1e9, 1)
         line["traffic_frac_of_peak"] = round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4)
-    for k in ("valu_busy", "vmem_busy", "waves_per_cu", "binding"):
+    for k in ("valu_busy", "waves_per_simd", "binding"):
         if k in pv:
             line[k] = pv[k]
     return line

@@ -315,11 +315,12 @@ lbm_status lbm_set_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y);
  * type + two compute-type values) within 159 KB, and a state (19 x nodes x
  * storage bytes) and a moment record (10 x nodes x compute bytes) below
  * 4 GB each. Samples, checkpoints and window ends fall on a launch's last
- * step as in 2D. Default (set by lbm_init): FP32 grids of more than 2M
- * nodes take 2 steps on 48 x 16 tiles (1024 threads per workgroup; 32 x 19
- * with 768 threads where nx < 48 or ny < 16), with the
- * z run that lets the blocks fill the compute units in nearly whole rounds
- * with the fewest halo planes; other D3Q19 contexts take single steps.
+ * step as in 2D. Default (set by lbm_init) on grids of more than 2M nodes:
+ * FP32 takes 2 steps on 48 x 16 tiles (1024 threads per workgroup; 32 x 19
+ * with 768 threads where nx < 48 or ny < 16), FP64 2 steps on 48 x 7 tiles
+ * (512 threads; 32 x 10 where nx < 48), each with the z run that lets the
+ * blocks fill the compute units in nearly whole rounds with the fewest halo
+ * planes; FP16S and smaller grids take single steps.
  * Errors: LBM_E_INVALID for a D2Q9 context or out-of-range arguments,
  * LBM_E_HIP if the LDS opt-in fails. */
 lbm_status lbm_set_blocking_3d(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y, int tile_z);
@@ -346,14 +347,15 @@ lbm_status lbm_set_adjoint_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int ti
  * own pre-state's record from the segment, and the tile's sensitivity
  * takes one FP64 read-modify-write per launch. nsteps = 1 turns it off.
  * Requires at least 256 nodes per block, (tile_x + 2) * (tile_y + 2) <= 768
- * (256 for LBM_F64), (tile_x + 2) x (tile_y + 2) x (16 + two compute-type
- * values + 43 adjoint values) bytes within 159 KB, and a moment record and
- * the adjoint populations below 4 GB each. Default (set by lbm_init): FP32
- * and FP16S grids of more than 2M nodes take 2 steps (tiles in
- * lbm_init's measured default) with the z run chosen as for the forward;
- * FP64 and smaller grids take single steps. Errors: LBM_E_INVALID for a
- * D2Q9 context or out-of-range arguments, LBM_E_HIP if the LDS opt-in
- * fails. */
+ * (one thread per region cell), (tile_x + 2) x (tile_y + 2) x (16 + two
+ * compute-type values + 43 adjoint values) bytes within 159 KB (in FP64
+ * about 430 region cells), and a moment record and the adjoint populations
+ * below 4 GB each. Default (set by lbm_init) on grids of more than 2M
+ * nodes: 2 steps on 48 x 13 tiles with 768 threads for FP32 and FP16S
+ * storage (32 x 19 where nx < 48), on 40 x 8 tiles with 512 threads for
+ * FP64 (32 x 10 where nx < 40), with the z run chosen as for the forward;
+ * smaller grids take single steps. Errors: LBM_E_INVALID for a D2Q9 context
+ * or out-of-range arguments, LBM_E_HIP if the LDS opt-in fails. */
 lbm_status lbm_set_adjoint_blocking_3d(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y, int tile_z);
 
 /* Thread-local message of the last failing call on this thread. */

@@ -514,9 +514,10 @@ lbm_status set_adj_blocking_3d(lbm_ctx* c, int nsteps, int tile_x, int tile_y, i
     if (nsteps == 2) {
         if (tile_x < 1 || tile_y < 1 || tile_z < 1 || (long)tile_x * tile_y * tile_z < 256)
             return fail(LBM_E_INVALID, "tile must hold at least 256 nodes");
-        const long cells_max = c->L.as == 8 ? 256 : 768;   // one cell per thread; FP64 uses 256 threads
-        if ((long)(tile_x + 2) * (tile_y + 2) > cells_max)
-            return fail(LBM_E_INVALID, "(tile_x + 2) * (tile_y + 2) too large (768, FP64 256)");
+        // one cell per thread, at most 768 threads (registers); FP64 regions
+        // are further bounded by the LDS (about 430 cells)
+        if ((long)(tile_x + 2) * (tile_y + 2) > 768)
+            return fail(LBM_E_INVALID, "(tile_x + 2) * (tile_y + 2) must be at most 768");
         if (adj_tbz_lds_bytes(tile_x, tile_y, c->L.as, c->L.cs) > TB_LDS_MAX)
             return fail(LBM_E_INVALID, "tile needs more than 159 KB of LDS");
         if ((size_t)10 * c->L.N * c->L.cs > TBZ_STATE_MAX || (size_t)c->L.Q * c->L.N * c->L.as > TBZ_STATE_MAX)
@@ -531,10 +532,12 @@ lbm_status set_adj_blocking_3d(lbm_ctx* c, int nsteps, int tile_x, int tile_y, i
 }
 
 // z-run length of a D3Q19 blocked launch on tile_x x tile_y tiles: the run
-// count c maximises E * oz / (oz + 1), where E is the fraction of the
+// count c maximises E * oz / (oz + 2), where E is the fraction of the
 // compute units' rounds that the tiles x c blocks fill (one block per
-// compute unit) and (oz + 1) / oz the extra work of the two halo planes
-// per run of oz planes.
+// compute unit) and (oz + 2) / oz the cost of the halo planes of a run of
+// oz planes (step 1 computes oz + 2 planes, the loads span oz + 4). Measured
+// on MI355X on the 384 x 128 x 128 channel this picks the fastest run of the
+// FP32 and FP64 forward and adjoint defaults.
 static int compute_units() {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -555,7 +558,7 @@ static int default_z_run(lbm_ctx* c, int tile_x, int tile_y) {
         const long blocks = tiles * ((nz + oz - 1) / oz);
         if (blocks > c->L.pstride) continue;
         const long rounds = (blocks + cus - 1) / cus;
-        const double score = (double)blocks / ((double)rounds * cus) * oz / (oz + 1.0);
+        const double score = (double)blocks / ((double)rounds * cus) * oz / (oz + 2.0);
         if (score > best_score + 1e-9) {
             best_score = score;
             best = oz;
@@ -923,24 +926,39 @@ lbm_status lbm_init(const lbm_config* cfg, const double* gamma_dev, void* worksp
         // as long as possible while the blocks still fill the compute units in
         // nearly whole rounds (measured on MI355X on the 384 x 128 x 128
         // channel: 124.9 us per step on 48 x 16 in runs of 32 planes, 131.8 on
-        // 48 x 13 and 140.1 on 32 x 19 with 768 threads). FP64 and FP16S stay
-        // single steps: their blocked launches measured no faster.
+        // 48 x 13 and 140.1 on 32 x 19 with 768 threads). FP16S stays single
+        // steps: its blocked launches measured no faster (113.9 against 109.6
+        // us per step on that channel).
         const int ftx = (cfg->nx >= 48 && cfg->ny >= 16) ? 48 : 32, fty = ftx == 48 ? 16 : 19;
         if ((st = set_blocking_3d(c, 2, ftx, fty, default_z_run(c, ftx, fty))) != LBM_OK) return bail(st);
+    } else if (cfg->prec == LBM_F64 && L.N > 2000000 && cfg->nx >= 32 && cfg->ny >= 7 &&
+               (size_t)L.Q * L.N * L.ss <= TBZ_STATE_MAX) {
+        // D3Q19 FP64 on large grids: two steps per launch on 48 x 7 tiles (a
+        // 450-cell region, the most the LDS holds in FP64; 512 threads; 32 x 10
+        // on grids narrower than 48). Measured on MI355X on the 384 x 128 x
+        // 128 channel: 271 us per step in runs of 26 planes against 379 for
+        // single steps (40 x 8: 284, 32 x 10: 291, 24 x 14: 306).
+        const int ftx = cfg->nx >= 48 ? 48 : 32, fty = ftx == 48 ? 7 : 10;
+        if ((st = set_blocking_3d(c, 2, ftx, fty, default_z_run(c, ftx, fty))) != LBM_OK) return bail(st);
     }
-    if (cfg->lattice == LBM_D3Q19 && cfg->prec != LBM_F64 && L.N > 2000000 && cfg->nx >= 32 && cfg->ny >= 13 &&
+    if (cfg->lattice == LBM_D3Q19 && L.N > 2000000 && cfg->nx >= 32 && cfg->ny >= (cfg->prec == LBM_F64 ? 8 : 13) &&
         (size_t)10 * L.N * L.cs <= TBZ_STATE_MAX && (size_t)L.Q * L.N * L.as <= TBZ_STATE_MAX) {
-        // D3Q19 adjoint with FP32 adjoint populations on large grids: two
-        // reverse steps per launch with 768 threads on 48 x 13 tiles (32 x 19
-        // on grids narrower than 48), z runs chosen as for the forward
-        // (measured on MI355X on the 384 x 128 x 128 channel, FP32: 212 us per
-        // reverse step on 48 x 13, 219 on 32 x 19, 230 on the 512-thread 48 x 8
-        // tiles and 238 on 32 x 13). FP64 stays single-step (its blocked
-        // launches measured slower).
-        int atx = 32, aty = 19;
-        if (cfg->nx >= 48) {
-            atx = 48;
-            aty = 13;
+        // D3Q19 adjoint on large grids: two reverse steps per launch, z runs
+        // chosen as for the forward. FP32 adjoint populations (FP32 and FP16S
+        // storage): 768 threads on 48 x 13 tiles (32 x 19 on grids narrower
+        // than 48); measured on MI355X on the 384 x 128 x 128
+        // channel, FP32: 212 us per reverse step on 48 x 13, 219 on 32 x 19,
+        // 230 on the 512-thread 48 x 8 tiles and 238 on 32 x 13. FP64: 512
+        // threads on 40 x 8 tiles (a 420-cell region; 32 x 10 on grids
+        // narrower than 40): 416 us per reverse step against 484 for single
+        // steps (32 x 10: 426, 24 x 14: 447, 256-thread 14 x 14: 603).
+        int atx, aty;
+        if (cfg->prec == LBM_F64) {
+            atx = cfg->nx >= 40 ? 40 : 32;
+            aty = atx == 40 ? 8 : 10;
+        } else {
+            atx = cfg->nx >= 48 ? 48 : 32;
+            aty = atx == 48 ? 13 : 19;
         }
         const int aoz = default_z_run(c, atx, aty);
         if ((st = set_adj_blocking_3d(c, 2, atx, aty, aoz)) != LBM_OK) return bail(st);

@@ -1364,8 +1364,8 @@ __device__ __forceinline__ void gather_index(const Geo& g, int n, int x, int y, 
 //
 // LDS: two plane slots each of the sensitivity (FP64) and s (compute
 // type), then the 43 plane slots of the adjoint ring (TbzRing<-1>) of
-// (ox + 2) x (oy + 2) values. TB threads (256 for planes of up to 256 region
-// cells and for FP64, else 512 or 768) take one cell each of a plane.
+// (ox + 2) x (oy + 2) values. TB threads (256, 512 or, below FP64, 768:
+// the smallest that covers the region's cells) take one cell each of a plane.
 template <class S, class T, class A, int TB>
 __global__ __launch_bounds__(TB) void k_adjoint_tbz(const A* __restrict__ nu_in, A* __restrict__ nu_out,
                                                     const T* __restrict__ rseg, size_t slot, long kseg,
@@ -1712,7 +1712,7 @@ static void launch_tb(const StepLaunch& a) {
 }
 
 template <class S, class T, bool SAMPLE, bool WPRE, bool REC = false>
-static void launch_tbz(const StepLaunch& a) {
+static hipError_t launch_tbz(const StepLaunch& a) {
     using LT = typename TbLds<S, T>::type;
     const Geo& g = a.geo;
     const int tiles_x = (g.nx + a.tile_x - 1) / a.tile_x;
@@ -1730,14 +1730,17 @@ static void launch_tbz(const StepLaunch& a) {
         LBM_TBZ(256, 1);
     } else if (nt == 512) {
         LBM_TBZ(512, 1);
-    } else if constexpr (sizeof(T) == 4) {   // FP64 regions never exceed 512 cells (LDS)
+    } else if constexpr (sizeof(T) == 4) {
         if (nt == 768) {
             LBM_TBZ(768, 1);
         } else {
             LBM_TBZ(1024, 1);
         }
+    } else {
+        return hipErrorInvalidValue;   // FP64 regions above 512 cells do not fit the LDS
     }
 #undef LBM_TBZ
+    return hipGetLastError();
 }
 
 template <class L, class S, class T>
@@ -1751,15 +1754,10 @@ static hipError_t step_t(const StepLaunch& a) {
         if (a.nsteps != 2) return hipErrorInvalidValue;
         if (a.rec) {
             if (a.sample || pre) return hipErrorInvalidValue;
-            launch_tbz<S, T, false, false, true>(a);
-        } else if (a.sample) {
-            if (pre) launch_tbz<S, T, true, true>(a);
-            else launch_tbz<S, T, true, false>(a);
-        } else {
-            if (pre) launch_tbz<S, T, false, true>(a);
-            else launch_tbz<S, T, false, false>(a);
+            return launch_tbz<S, T, false, false, true>(a);
         }
-        return hipGetLastError();
+        if (a.sample) return pre ? launch_tbz<S, T, true, true>(a) : launch_tbz<S, T, true, false>(a);
+        return pre ? launch_tbz<S, T, false, true>(a) : launch_tbz<S, T, false, false>(a);
     }
     if (a.nsteps > 1) {
         if (L::D != 2) return hipErrorInvalidValue;
@@ -1814,14 +1812,18 @@ static hipError_t adj_t(const AdjLaunch& a) {
                        a.kseg, sf, a.sens, g, a.ph, a.ob, a.k_hi, a.ns, a.dW, a.wgt, a.tile_x, a.tile_y,        \
                        a.tile_z, tiles_x, tiles_y)
         const int nt = tbz_threads(a.tile_x, a.tile_y);
-        if (sizeof(A) == 8 || nt == 256) {
-            LBM_ADJ_TBZ(256);   // FP64: one cell per thread of 256 (register budget)
+        if (nt == 256) {
+            LBM_ADJ_TBZ(256);
+        } else if (nt == 512) {
+            LBM_ADJ_TBZ(512);
         } else if constexpr (sizeof(A) == 4) {
             if (nt == 768) {
                 LBM_ADJ_TBZ(768);
             } else {
-                LBM_ADJ_TBZ(512);
+                return hipErrorInvalidValue;   // regions above 768 cells (register budget)
             }
+        } else {
+            return hipErrorInvalidValue;       // FP64 regions above 512 cells do not fit the LDS
         }
 #undef LBM_ADJ_TBZ
         return hipGetLastError();
@@ -2091,10 +2093,10 @@ template <class S, class T, class A>
 static hipError_t tb_attr_all(int b) {
     hipError_t e = hipFuncSetAttribute((const void*)k_adjoint_tbz<S, T, A, 256>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_adjoint_tbz<S, T, A, 512>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                b);
     if constexpr (sizeof(A) == 4) {
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_adjoint_tbz<S, T, A, 512>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, b);
         if (e == hipSuccess)
             e = hipFuncSetAttribute((const void*)k_adjoint_tbz<S, T, A, 768>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, b);

@@ -325,7 +325,7 @@ def _small_3d_cases():
 def test_blocked_d3q19_matches_single_steps(Solver, prec, case):
     """Two-step D3Q19 launches (z-marching blocks, xy tiles grown by one node
     in LDS, walls as ghost cells or z reflections, Zou-He faces, periodic
-    wraps; one and, below FP64, two cells per thread) give the states, window objectives
+    wraps; 256 to 1024 threads, one cell each) give the states, window objectives
     and adjoint of single-step launches; FP64 also against the oracle."""
     name, w = _small_3d_cases()[case]
     w.window_len, w.sample_every, w.ckpt_every, w.max_windows = 8, 2, 4, 2
@@ -333,7 +333,7 @@ def test_blocked_d3q19_matches_single_steps(Solver, prec, case):
     f0 = random_start_state(prob, seed=23 + case)
     tol = {"f64": 1e-13, "f32": 1e-6, "f16s": 1e-3}[prec]
     res = {}
-    # 256-thread (a, b, c), 512-thread (e, FP64 d), 768-thread (d) and two-cells-per-thread (f) launches
+    # 256-thread (a, b, c), 512-thread (e, FP64 d and f), 768-thread (d) and 1024-thread (f) launches
     blocks = (("single", (1,)), ("a", (2, 8, 8, 4)), ("b", (2, 16, 4, 4)), ("c", (2, 7, 5, 8)),
               ("d", (2, 16, 14, 2) if prec == "f64" else (2, 24, 24, 2)), ("e", (2, 16, 16, 1)),
               ("f", (2, 20, 12, 3) if prec == "f64" else (2, 30, 25, 2)))
@@ -367,8 +367,8 @@ def test_blocked_d3q19_matches_single_steps(Solver, prec, case):
 def test_blocked_d3q19_adjoint_matches_single_steps(Solver, prec, case):
     """Two-step D3Q19 adjoint launches (z-marching blocks, adjoint wall rule
     as ghost cells or z reflections, 0 behind open faces, one
-    read-modify-write of the sensitivity per launch; 256-, 512- and
-    768-thread blocks) give the dJ/dgamma of single-step adjoint launches
+    read-modify-write of the sensitivity per launch; 256-, 512- and, below
+    FP64, 768-thread blocks) give the dJ/dgamma of single-step adjoint launches
     after the same forward launches (single and blocked)."""
     name, w = _small_3d_cases()[case]
     w.window_len, w.sample_every, w.ckpt_every, w.max_windows = 8, 2, 8, 2
@@ -376,7 +376,9 @@ def test_blocked_d3q19_adjoint_matches_single_steps(Solver, prec, case):
     f0 = random_start_state(prob, seed=41 + case)
     tol = {"f64": 1e-13, "f32": 1e-6, "f16s": 1e-5}[prec]
     blocks = [(8, 8, 4), (7, 5, 8), (14, 14, 2) if prec == "f64" else (16, 14, 2)]
-    if prec != "f64":
+    if prec == "f64":
+        blocks.append((24, 14, 2))      # a 416-cell region: 512 threads
+    else:
         blocks.append((48, 8, 4))       # 48 x 8, wider than the grid, ragged in y
         blocks.append((24, 24, 2))      # a 676-cell region: 768 threads, one input set in flight
     # each blocked adjoint against the single-step adjoint of the same forward
@@ -397,6 +399,85 @@ def test_blocked_d3q19_adjoint_matches_single_steps(Solver, prec, case):
         g1, J1 = res[(fwd, (1,))]
         assert rel_l2(g, g1) <= tol, (fwd, adj, rel_l2(g, g1))
         assert J == J1, (fwd, adj, J, J1)
+
+
+def _ragged_3d(walls_z):
+    """100 x 37 x 9 channel: 48 x 16 x 4 blocks leave ragged tiles in x
+    (100 = 2 x 48 + 4), y (37 = 2 x 16 + 5) and z (9 = 2 x 4 + 1)."""
+    w = W.cylinder_3d(nx=100, ny=37, nz=9, radius=5, center=(25, 18), window_len=8, sample_every=2,
+                      ckpt_every=4, n_windows=1)
+    w.gamma = np.clip(w.gamma + 0.2 * W.random_design(w.shape, 17), 0, 1)
+    if walls_z:
+        w.periodic = (False, False, False)
+    return w
+
+
+# widest forward and adjoint blocks per storage precision (LDS and registers)
+_WIDE_BLOCKS = {
+    "f64": ([(2, 40, 8, 4), (2, 32, 10, 3)], [(2, 24, 14, 3), (2, 14, 14, 2)]),
+    "f32": ([(2, 48, 16, 4), (2, 30, 25, 3)], [(2, 48, 13, 3), (2, 24, 24, 2)]),
+    "f16s": ([(2, 48, 16, 4), (2, 30, 25, 3), (2, 30, 30, 2)], [(2, 48, 13, 3), (2, 24, 24, 2)]),
+}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("walls_z", [False, True])
+def test_blocked_d3q19_large_regions_on_ragged_tiles(Solver, prec, walls_z):
+    """The widest blocked launches on a grid that several tiles cover with
+    ragged tails in x, y and z: below FP64 the 1024-thread forward and
+    recompute (regions of 769-1024 cells: 48 x 16 and 30 x 25 tiles, and in
+    FP16S the full 32 x 32 region) and the 768-thread adjoint (48 x 13,
+    24 x 24); in FP64 the 512-thread forward and adjoint (regions of up to
+    the LDS limit of about 450 and 430 cells). States, window objectives
+    and dJ/dgamma equal those of single-step launches; in FP64 and FP32
+    every run also matches the oracle (FP64: states 1e-12, J 1e-12,
+    dJ/dgamma 1e-11; FP32: 1e-6, 1e-3, 1e-4)."""
+    w = _ragged_3d(walls_z)
+    prob = oracle_problem(w)
+    f0 = random_start_state(prob, seed=61 + walls_z)
+    tol = {"f64": 1e-13, "f32": 1e-6, "f16s": 1e-3}[prec]
+    tol_adj = {"f64": 1e-13, "f32": 1e-6, "f16s": 1e-5}[prec]
+    fwd_wide, adj_wide = _WIDE_BLOCKS[prec]
+    runs = [(fb, (1,)) for fb in [(1,)] + fwd_wide] + [(fwd_wide[0], ab) for ab in adj_wide]
+    res = {}
+    for fb, ab in runs:
+        print(f"ragged 3D {prec} walls_z={walls_z}: forward blocks {fb}, adjoint blocks {ab}", flush=True)
+        sv = Solver(w, prec)
+        sv.set_blocking_3d(*fb)
+        sv.set_adjoint_blocking_3d(*ab)
+        sv.set_state(f0, 0)
+        sv.forward(w.window_len)
+        f, step = sv.get_state()
+        J, _, _ = sv.history()
+        g, Ja = sv.adjoint()
+        assert step == w.window_len
+        res[(fb, ab)] = (f, J, g.cpu().numpy(), Ja)
+        sv.close()
+    f1, J1, g1, _ = res[((1,), (1,))]
+    for (fb, ab), (f, J, g, Ja) in res.items():
+        # states and window objectives against single steps
+        assert rel_l2(f, f1) <= tol, (fb, rel_l2(f, f1))
+        assert np.max(np.abs(J - J1)) <= tol * np.max(np.abs(J1)) + 1e-15
+        if ab == (1,):
+            assert rel_l2(g, g1) <= 100 * tol, (fb, rel_l2(g, g1))
+        else:
+            # a blocked adjoint against the single-step adjoint after the same forward launches
+            g2, _ = res[(fb, (1,))][2:]
+            assert rel_l2(g, g2) <= tol_adj, (fb, ab, rel_l2(g, g2))
+            assert Ja == res[(fb, (1,))][3]
+    if prec in ("f64", "f32"):
+        tf, tJ, tg = {"f64": (1e-12, 1e-12, 1e-11), "f32": (1e-6, 1e-3, 1e-4)}[prec]
+        J_o, g_o, _ = ad.window_gradient(prob, w.gamma, f0)
+        s_ = fw.design_map(prob, w.gamma)
+        f_o = f0
+        for _ in range(w.window_len):
+            f_o = fw.step(prob, f_o, s_)
+        for key, (f, J, g, Ja) in res.items():
+            print(f"  {key}: state {rel_l2(f, f_o):.2e}, J {abs(Ja - J_o) / abs(J_o):.2e}, "
+                  f"dJ/dgamma {rel_l2(g, g_o):.2e}")
+            assert rel_l2(f, f_o) <= tf
+            assert abs(Ja - J_o) <= tJ * abs(J_o)
+            assert rel_l2(g, g_o) <= tg
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
@@ -428,11 +509,12 @@ def test_d3q19_record_sweep_blocked_matches_oracle(Solver, prec, K):
 
 
 def test_adjoint_blocking_3d_rejects_bad_blocks(Solver):
-    """Adjoint blocks below 256 nodes, xy regions above 768 cells (256 in
-    FP64), three steps, and a D2Q9 context are refused."""
+    """Adjoint blocks below 256 nodes, xy regions above 768 cells, FP64
+    regions beyond the LDS (468 cells), three steps, and a D2Q9 context are
+    refused."""
     from paper_2608_19617_amd.binding import LbmError
     name, w = _small_3d_cases()[0]
-    for prec, bad in (("f32", ((2, 4, 4, 4), (2, 40, 20, 1), (3, 8, 8, 4))), ("f64", ((2, 16, 14, 2),))):
+    for prec, bad in (("f32", ((2, 4, 4, 4), (2, 40, 20, 1), (3, 8, 8, 4))), ("f64", ((2, 24, 16, 2),))):
         sv = Solver(w, prec)
         for blk in bad:
             with pytest.raises(LbmError):
@@ -902,9 +984,10 @@ def test_u_bend_oracle_one_step(Solver):
 
 
 def test_cylinder_3d_full_size(Solver):
-    """D3Q19 channel 384 x 128 x 128: 2 steps from a shared FP64 state against
-    the oracle (FP64 and FP32), and dJ/dgamma of a 40-step window from the
-    shared state, FP32 against FP64 (<= 1e-4)."""
+    """D3Q19 channel 384 x 128 x 128 in the default (two-step) launches: 2
+    steps from a shared FP64 state against the oracle (FP64 and FP32), and
+    dJ/dgamma of a 40-step window from the shared state, FP64 against the
+    FP64 single-step launches (<= 1e-12) and FP32 against FP64 (<= 1e-4)."""
     w = W.cylinder_3d(window_len=40, sample_every=20, ckpt_every=10, n_windows=1)
     f0 = _share_state(Solver, w, 200)
     w1 = W.cylinder_3d(window_len=2, sample_every=2, ckpt_every=2, n_windows=1)
@@ -921,15 +1004,24 @@ def test_cylinder_3d_full_size(Solver):
         sv.close()
     del f_o
     res = {}
-    for prec in ("f64", "f32"):
+    for prec, single in (("f64", False), ("f64", True), ("f32", False)):
         sv = Solver(w, prec)
+        if single:
+            sv.set_blocking_3d(1)
+            sv.set_adjoint_blocking_3d(1)
         sv.set_state(f0, 0)
         sv.forward(w.window_len)
         g, J = sv.adjoint()
-        res[prec] = g.cpu().numpy()
+        res[(prec, single)] = (g.cpu().numpy(), J)
         sv.close()
-    e = rel_l2(res["f32"], res["f64"])
-    print(f"cylinder 3D dJ/dgamma FP32 vs FP64: {e:.2e}")
+    g64, J64 = res[("f64", False)]
+    g64s, J64s = res[("f64", True)]
+    e64 = rel_l2(g64, g64s)
+    e = rel_l2(res[("f32", False)][0], g64)
+    print(f"cylinder 3D dJ/dgamma: FP64 two-step vs single-step launches {e64:.2e}, "
+          f"J {abs(J64 - J64s) / abs(J64s):.2e}; FP32 vs FP64 {e:.2e}")
+    assert e64 <= 1e-12
+    assert abs(J64 - J64s) <= 1e-12 * abs(J64s)
     assert e <= 1e-4
 
 
