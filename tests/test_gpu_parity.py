@@ -905,6 +905,68 @@ def test_cylinder_wake_full_size_adjoint_vs_oracle(Solver, wake_window_oracle, p
     sv.close()
 
 
+# the oracle's crop of the D3Q19 channel: x 69-91, y 51-76, every z
+_C3_X0, _C3_X1, _C3_Y0, _C3_Y1 = 69, 92, 51, 77
+
+
+@pytest.fixture(scope="module")
+def cylinder_3d_window_oracle(Solver):
+    """D3Q19 channel 384 x 128 x 128: the GPU FP64 state after 200 steps and
+    the oracle's J and window gradient of a 4-step window from it (samples
+    at steps 2 and 4) with pressure sections at x = 78 and x = 82 over rows
+    60-67 and every z, across the front of the cylinder (its surface at
+    x = 80). Over 4 steps the gradient reaches at most 4 nodes from a
+    section, and the forward state there depends on the start state at most
+    4 nodes further, so the oracle computes J and the gradient exactly on a
+    crop whose faces are 9 nodes from the sections (walls on the crop's
+    faces change nothing within 4 steps of them); the full grid's gradient
+    is exactly 0 outside the crop."""
+    w = W.cylinder_3d(window_len=200, sample_every=20, ckpt_every=50, n_windows=1)
+    f0 = _share_state(Solver, w, 200)
+    w1 = W.cylinder_3d(window_len=4, sample_every=2, ckpt_every=4, n_windows=1)
+    w1.sec_in, w1.sec_out = (78, 60, 68), (82, 60, 68)
+    x0, x1, y0, y1 = _C3_X0, _C3_X1, _C3_Y0, _C3_Y1
+    c = W.cylinder_3d(nx=x1 - x0, ny=y1 - y0, nz=w1.shape[2], window_len=4, sample_every=2, ckpt_every=4,
+                      n_windows=1)
+    c.tau, c.c_smag = w1.tau, w1.c_smag
+    c.gamma = w1.gamma[x0:x1, y0:y1, :].copy()
+    c.west, c.east = np.zeros_like(c.west), np.zeros_like(c.east)
+    c.sec_in, c.sec_out = (78 - x0, 60 - y0, 68 - y0), (82 - x0, 60 - y0, 68 - y0)
+    J_o, g_o, _ = ad.window_gradient(oracle_problem(c), c.gamma, np.ascontiguousarray(f0[:, x0:x1, y0:y1, :]))
+    return w1, f0, J_o, g_o
+
+
+@pytest.mark.parametrize("prec,tol_J,tol_g", [("f64", 1e-15, 1e-10), ("f32", 1e-9, 1e-4), ("f16s", 1e-5, 1e-2)])
+def test_cylinder_3d_full_size_adjoint_vs_oracle(Solver, cylinder_3d_window_oracle, prec, tol_J, tol_g):
+    """The library's default launches on the D3Q19 channel 384 x 128 x 128
+    (two-step z-marching forward, recompute and adjoint in FP64 and FP32;
+    single-step forward and recompute with the two-step adjoint in FP16S)
+    over a 4-step window from a shared state: J against the oracle (bounded
+    relative to the pressure level c_s^2 rho_0, as the pressure drop between
+    sections 4 nodes apart is small; measured FP64 4.5e-17, FP32 1.6e-11,
+    FP16S 1.6e-7), dJ/dgamma on the oracle's crop (relative L2, measured
+    5.3e-15, 9.2e-8, 7.0e-5 against the bars 1e-10, 1e-4, 1e-2) and exactly 0
+    on the rest of the grid (Sec. 3.2, Eqs. adjoint_collision,
+    adjoint_streaming, sensitivity)."""
+    w1, f0, J_o, g_o = cylinder_3d_window_oracle
+    sv = Solver(w1, prec)
+    sv.set_state(f0, 0)
+    sv.forward(w1.window_len)
+    g, J = sv.adjoint()
+    g = g.cpu().numpy()
+    sv.close()
+    inside = g[_C3_X0:_C3_X1, _C3_Y0:_C3_Y1, :]
+    outside = np.count_nonzero(g) - np.count_nonzero(inside)
+    eg = rel_l2(inside, g_o)
+    print(f"cylinder 3D 384x128x128 {prec}: 4-step window J {abs(J - J_o):.2e} absolute (J = {J_o:.3e}), "
+          f"dJ/dgamma {eg:.2e} on the crop, nonzero entries {np.count_nonzero(g_o)} (oracle), "
+          f"{outside} outside the crop")
+    assert np.count_nonzero(g_o) > 20000
+    assert outside == 0
+    assert abs(J - J_o) <= tol_J / 3.0
+    assert eg <= tol_g
+
+
 @pytest.fixture(scope="module")
 def u_bend_window_oracle(Solver):
     """U-bend 1024 x 1024: the GPU FP64 state after 1000 steps and the
