@@ -224,3 +224,37 @@ def test_windowed_j_central_differences(Solver, prec, h, tol):
     print(f"WindowedJ central differences {prec} h={h:g}: max |fd - adjoint| / max|dJ/dgamma| {errs.max():.2e}")
     assert errs.max() <= tol
     sv.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("eps,w_eff,conv", [(0.1, 2, True), (-1.0, 4, False)])
+def test_window_criterion_zero_monitor(Solver, prec, eps, w_eff, conv):
+    """The criterion's zero-mean edge (Eq. statistical_criterion is
+    undefined for M_i = 0; read as: converged only when M_(i-1) = 0 too, and
+    never with the test disabled, eps < 0): a fluid at rest in a periodic box
+    with a random design stays exactly at rest in every storage (shifted
+    populations are exactly 0 and partial bounce-back of a rest state
+    changes nothing), so every window's pressure-drop mean is exactly 0. The
+    GPU's decisions, relative changes and W_eff equal the oracle's window
+    loop."""
+    w = W.cylinder_channel(nx=40, ny=20, radius=4, center=(20, 10), window_len=20, sample_every=5,
+                           ckpt_every=10, n_windows=4)
+    w.periodic = (True, True, False)
+    w.west, w.east = np.zeros(20, np.int64), np.zeros(20, np.int64)
+    w.u_in = np.zeros(20)
+    w.u_init_mode = 0
+    w.gamma = W.random_design(w.shape, 7)
+    w.eps = eps
+    prob = oracle_problem(w)
+    out = fw.run(prob, w.gamma, w.max_windows * w.window_len, stop_on_converge=True)
+    assert out["w_eff"] == w_eff and out["converged"][-1] == conv
+    assert np.all(np.array(out["M"]) == 0.0)
+    sv = Solver(w, prec)
+    rep = sv.forward(w.max_windows * w.window_len, stop_on_converge=True)
+    J, M, R = sv.history()
+    assert rep["w_eff"] == w_eff and rep["steps_done"] == w_eff * w.window_len
+    assert bool(rep["converged"]) == conv
+    assert np.all(M == 0.0) and np.all(J == 0.0)
+    assert np.isnan(R[0]) and np.all(R[1:] == 0.0)
+    assert np.array_equal(R[1:], np.array(out["rel"][1:]))
+    sv.close()
