@@ -1204,7 +1204,6 @@ __global__ __launch_bounds__(TB) void k_adjoint_tb(const A* __restrict__ nu_in, 
     const int bufsz = L::Q * plane_sz;
     T* sbuf = lds + 2 * bufsz;
     const TbRows<T> rows = tb_rows<T>(sbuf + plane_sz, LH);
-    const T d0 = (T)g.drho_out;
     int tx, ty;
     tb_tile(tiles_x, tx, ty);
     const int x0 = tx * ox - H, y0 = ty * oy - H;
