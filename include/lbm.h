@@ -315,9 +315,11 @@ lbm_status lbm_set_blocking(lbm_ctx* ctx, int nsteps, int tile_x, int tile_y);
  * type + two compute-type values) within 159 KB, and a state (19 x nodes x
  * storage bytes) and a moment record (10 x nodes x compute bytes) below
  * 4 GB each. Samples, checkpoints and window ends fall on a launch's last
- * step as in 2D. Default (set by lbm_init) on grids of more than 2M nodes:
+ * step as in 2D. This call sets the tiles of the recompute's launches to
+ * the same. Default (set by lbm_init) on grids of more than 2M nodes:
  * FP32 takes 2 steps on 48 x 16 tiles (1024 threads per workgroup; 32 x 19
- * with 768 threads where nx < 48 or ny < 16), FP64 2 steps on 48 x 7 tiles
+ * with 768 threads where nx < 48 or ny < 16) and its recompute 2 steps on
+ * 32 x 19 tiles (768 threads), FP64 2 steps on 48 x 7 tiles
  * (512 threads; 32 x 10 where nx < 48), each with the z run that lets the
  * blocks fill the compute units in nearly whole rounds with the fewest halo
  * planes; FP16S and smaller grids take single steps.
