@@ -64,7 +64,7 @@ def parse():
                          "channel 384x128x128 (cyl3d) or the cylinder wake 8192x2048 (wake8192) in their "
                          "default launches: 40 forward steps and the adjoint of their last 20-step window")
     ap.add_argument("--suite", choices=["bfs", "hbm", "design", "fulltime", "paper", "optimize", "conditioning",
-                                        "c3", "c4"],
+                                        "wake2048", "ubend1024"],
                     default=None,
                     help="bfs: the backward-facing step 800x200 (FP32 vs FP64 window criterion "
                          "workload) benchmarked to its converged window and adjoint; hbm: rooflines of the forward, recompute and adjoint kernels on grids far "
@@ -75,7 +75,10 @@ def parse():
                          "paper: the paper's cylinder-drag and wake-recovery examples at their sizes "
                          "with their objectives and the finite-difference check of the adjoint; "
                          "optimize: the paper's cylinder drag minimisation (Re 51.2) for up to 60 "
-                         "iterations of forward windows, adjoint and design update")
+                         "iterations of forward windows, adjoint and design update; conditioning: "
+                         "precision errors and finite differences against window length; wake2048: the "
+                         "cylinder wake 2048x512 with 20000-step windows through the autograd entry "
+                         "point; ubend1024: the U-bend 1024x1024, FP16S against FP32 over 10000 steps")
     return ap.parse_args()
 
 
@@ -307,7 +310,7 @@ def hbm_suite(args, torch):
     for prec in ("f64", "f32", "f16s"):
         w = W.cylinder_wake(nx=8192, ny=2048, radius=128, window_len=500, sample_every=20, ckpt_every=50,
                             max_windows=2)
-        cases.append(("cylinder wake 8192x2048 (C3 x4 per axis)", w, prec, FWD_BYTES[prec], ADJ_BYTES[prec],
+        cases.append(("cylinder wake 8192x2048 (the 2048x512 wake x4 per axis)", w, prec, FWD_BYTES[prec], ADJ_BYTES[prec],
                       REC_BYTES[prec]))
     for prec in ("f32", "f16s", "f64"):
         w3 = W.cylinder_3d(window_len=100, sample_every=20, ckpt_every=20, n_windows=2)
@@ -751,12 +754,12 @@ def bfs_bench(args, torch):
 
 
 
-# ----------------------------------------------------- default: C5 channel
+# ------------------------------- default: the D3Q19 channel 384x128x128
 
 C5_SLAB_NZ, C5_SLAB_FWD, C5_SLAB_WIN = 2, 4, 2
 
 
-def c5_workload():
+def channel3d_workload():
     """The D3Q19 cylinder channel 384 x 128 x 128: 4 windows of 5000 steps
     (dW = 20, K = 250), pressure-drop objective and monitor; the window test
     (eps = 1e-3) is evaluated at every window end, and the run is the fixed
@@ -780,23 +783,23 @@ def _free(torch, *solvers):
     torch.cuda.empty_cache()
 
 
-def c5_step(sv, w, gamma_dev):
+def channel3d_step(sv, w, gamma_dev):
     sv.set_gamma(gamma_dev)
     rep = sv.forward(w.max_windows * w.window_len)
     g, J = sv.adjoint()
     return rep, g, J
 
 
-def c5_timed(w, gamma_dev, args, torch):
+def channel3d_timed(w, gamma_dev, args, torch):
     from paper_2608_19617_amd.solver import Solver
     sv = Solver(w, args.prec)
     for _ in range(args.warmup):
-        c5_step(sv, w, gamma_dev)
+        channel3d_step(sv, w, gamma_dev)
     torch.cuda.synchronize()
     sv.timing(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        rep, g, J = c5_step(sv, w, gamma_dev)
+        rep, g, J = channel3d_step(sv, w, gamma_dev)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     tm = sv.timing(False)
@@ -812,7 +815,7 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - b) / np.linalg.norm(b))
 
 
-def c5_precisions(w, gamma_dev, res, args, torch):
+def channel3d_precisions(w, gamma_dev, res, args, torch):
     """FP64 and FP16S beside the timed FP32 run: one step of each from rest
     (timed; the FP64 state entering the last window is exported on the way,
     outside the timed parts), then the last window of FP32 and FP16S rerun
@@ -848,7 +851,7 @@ def c5_precisions(w, gamma_dev, res, args, torch):
         sv = Solver(w, prec)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rep, g, J = c5_step(sv, w, gamma_dev)
+        rep, g, J = channel3d_step(sv, w, gamma_dev)
         torch.cuda.synchronize()
         mlups[prec] = upd / (time.perf_counter() - t0) / 1e6
         from_rest[prec] = (J, g.cpu().numpy())
@@ -926,7 +929,7 @@ def _oracle_slab_worker(nz, n_fwd, n_win):
     return t_f, t_a, w.nodes
 
 
-def c5_cpu_baseline(fwd_per_step, adj_per_step):
+def channel3d_cpu_baseline(fwd_per_step, adj_per_step):
     """The oracle on the host's cores, on slabs of the same workload: one
     process alone (single thread), then one process per core of the host's
     share (at most 16) running the same slab at once. Rates are node updates
@@ -956,7 +959,7 @@ def c5_cpu_baseline(fwd_per_step, adj_per_step):
                                    "adj_mlups": round(sum(r[2] / r[1] for r in every) / cores / 1e6, 4)}}
 
 
-def c5_roofline(tm, N, prec):
+def channel3d_roofline(tm, N, prec):
     """Roofline of the dominant kernel of the step (the forward: 20 000 of the
     step's 25 000 updates), from the HIP-event launch averages of the timed
     steps; the counter bytes and SQ figures come from the committed profile
@@ -989,12 +992,12 @@ def c5_roofline(tm, N, prec):
     return line
 
 
-def c5_bench(args, torch):
+def channel3d_bench(args, torch):
     import numpy as np
-    w = c5_workload()
+    w = channel3d_workload()
     N = w.nodes
     gamma_dev = _device_gamma(w, torch)
-    res = c5_timed(w, gamma_dev, args, torch)
+    res = channel3d_timed(w, gamma_dev, args, torch)
     tm = res["tm"]
     fwd_per_step = w.max_windows * w.window_len
     adj_per_step = w.window_len
@@ -1029,7 +1032,7 @@ def c5_bench(args, torch):
                    "sample_every": w.sample_every, "ckpt_every": w.ckpt_every,
                    "fwd_steps_per_step": fwd_per_step, "adj_steps_per_step": adj_per_step,
                    "workspace_GB": round(res["workspace"] / 1e9, 1)},
-        "roofline": c5_roofline(tm, N, p),
+        "roofline": channel3d_roofline(tm, N, p),
         "kernels": kern,
         "J": res["J"],
         "windows": {"J": [float(j) for j in res["J_hist"]],
@@ -1037,15 +1040,15 @@ def c5_bench(args, torch):
                     "criterion_passed_at_last_window": bool(res["rep"]["converged"])},
     }
     if not args.no_compare:
-        line["precision"] = c5_precisions(w, gamma_dev, res, args, torch)
+        line["precision"] = channel3d_precisions(w, gamma_dev, res, args, torch)
     if not args.no_cpu:
-        line["cpu_baseline"] = c5_cpu_baseline(fwd_per_step, adj_per_step)
+        line["cpu_baseline"] = channel3d_cpu_baseline(fwd_per_step, adj_per_step)
     print(json.dumps(line), flush=True)
 
 
-# ------------------------------------------------------------ C3 and C4
+# ------------------- the cylinder wake 2048x512 and the U-bend 1024x1024
 
-def c3_suite(args, torch):
+def wake2048_suite(args, torch):
     """The cylinder wake 2048 x 512 (disk R = 32, Re 1000, u_max = 0.04,
     C_s = 0.1) in FP32 through WindowedJ: windows of 20 000 steps (dW = 20,
     K = 500) from rest until the criterion (eps = 1e-3) passes or 5 windows
@@ -1058,7 +1061,7 @@ def c3_suite(args, torch):
     from paper_2608_19617_amd.autograd import windowed_objective
     from paper_2608_19617_amd.solver import Solver
     w = W.cylinder_wake(window_len=20000, sample_every=20, ckpt_every=500, max_windows=5, eps=1e-3)
-    line = {"suite": "c3", "workload": "cylinder wake 2048x512 Re 1000, windows of 20000, K 500", "dtype": "f32"}
+    line = {"suite": "wake2048", "workload": "cylinder wake 2048x512 Re 1000, windows of 20000, K 500", "dtype": "f32"}
     sv = Solver(w, "f32")
     gamma = torch.tensor(w.gamma, dtype=torch.float64, device="cuda", requires_grad=True)
     torch.cuda.synchronize()
@@ -1113,7 +1116,7 @@ def c3_suite(args, torch):
     print(json.dumps(line), flush=True)
 
 
-def c4_suite(args, torch):
+def ubend1024_suite(args, torch):
     """The U-bend 1024 x 1024 (legs of width 128 on the west face, Re 2000,
     uniform inlet 0.03, C_s = 0.1; J = window mean of dissipation plus the
     pressure drop, dW = 20, K = 500): a spin-up window of 10 000 steps, then
@@ -1158,7 +1161,7 @@ def c4_suite(args, torch):
         same[prec] = (J, g.cpu().numpy())
         _free(torch, sv)
     N = w.nodes
-    line = {"suite": "c4", "workload": "U-bend 1024x1024 Re 2000, spin-up window + 10000-step window", "precisions": {}}
+    line = {"suite": "ubend1024", "workload": "U-bend 1024x1024 Re 2000, spin-up window + 10000-step window", "precisions": {}}
     for prec, r in res.items():
         e = {"J": r["J"], "forward_mlups": round(2 * w.window_len * N / r["forward_s"] / 1e6, 1),
              "reverse_sweep_mlups": round(w.window_len * N / r["adjoint_s"] / 1e6, 1),
@@ -1186,10 +1189,10 @@ def _conditioning_cases():
     entries, finite-difference steps h)."""
     from paper_2608_19617_amd import workloads as W
 
-    def c5(L):
+    def channel3d(L):
         return W.cylinder_3d(window_len=L, sample_every=20, ckpt_every=min(250, L // 2), n_windows=1)
 
-    def c3(L):
+    def wake(L):
         return W.cylinder_wake(window_len=L, sample_every=20, ckpt_every=min(500, L // 2), max_windows=1, eps=-1.0)
 
     def bfs(L):
@@ -1201,8 +1204,8 @@ def _conditioning_cases():
                               eps=-1.0)
 
     hs = (1e-3, 1e-4, 1e-5, 1e-6)
-    return [("cylinder_3d_384x128x128", c5, 15000, (40, 200, 1000, 5000), 5000, 4, hs),
-            ("cylinder_wake_2048x512", c3, 20000, (100, 1000, 5000, 20000), 20000, 8, hs),
+    return [("cylinder_3d_384x128x128", channel3d, 15000, (40, 200, 1000, 5000), 5000, 4, hs),
+            ("cylinder_wake_2048x512", wake, 20000, (100, 1000, 5000, 20000), 20000, 8, hs),
             ("backward_facing_step_800x200", bfs, 38000, (100, 500, 2000), 2000, 8, hs),
             ("u_bend_paper_240x192_re400", ubend, 40000, (2000, 5000, 10000, 20000), 20000, 12,
              (1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8))]
@@ -1319,11 +1322,11 @@ def main():
         return
     suites = {"bfs": bfs_bench, "hbm": hbm_suite, "design": design_suite, "fulltime": fulltime_suite,
               "paper": paper_suite, "optimize": optimize_suite, "conditioning": conditioning_suite,
-              "c3": c3_suite, "c4": c4_suite}
+              "wake2048": wake2048_suite, "ubend1024": ubend1024_suite}
     if args.suite:
         suites[args.suite](args, torch)
         return
-    c5_bench(args, torch)
+    channel3d_bench(args, torch)
 
 
 if __name__ == "__main__":

@@ -166,7 +166,7 @@ def test_c1_fp64_fields(c1, c1_gpu64):
     e300 = rel_l2(c1_gpu64["f300"], c1["f300"])
     e1000 = rel_l2(c1_gpu64["f1000"], c1["f1000"])
     e1000_ld = rel_l2(c1_gpu64["f1000"], c1["f1000_ld"])
-    print(f"C1 FP64 fields: step 300 {e300:.2e}; step 1000 vs oracle {e1000:.2e}, vs extended "
+    print(f"cylinder channel 160x64 FP64 fields: step 300 {e300:.2e}; step 1000 vs oracle {e1000:.2e}, vs extended "
           f"precision {e1000_ld:.2e} (FP64 oracle vs extended {c1['drift1000']:.2e})")
     assert e300 <= 1e-12
     # the outlet amplifies round-off, so two FP64 programs differ by about
@@ -204,7 +204,7 @@ def test_c1_fp64_windows_and_adjoint(c1_gpu64, c1_window4):
     eJ = np.abs(c1_gpu64["J"][1:] - c1_window4["J"]) / np.abs(c1_window4["J"])
     eJ4 = abs(c1_gpu64["J4"] - c1_window4["J4"]) / abs(c1_window4["J4"])
     eg = rel_l2(c1_gpu64["g4"], c1_window4["g4"])
-    print(f"C1 FP64 from shared window starts: window means {eJ.max():.2e}; J4 {eJ4:.2e}; dJ/dgamma {eg:.2e}")
+    print(f"cylinder channel 160x64 FP64 from shared window starts: window means {eJ.max():.2e}; J4 {eJ4:.2e}; dJ/dgamma {eg:.2e}")
     assert eJ.max() <= 1e-11
     assert eJ4 <= 1e-11
     assert eg <= 1e-10
@@ -224,7 +224,7 @@ def test_c1_reduced_precision(Solver, c1, c1_gpu64, c1_window4, prec, tol_J, tol
     e300 = rel_l2(f300, c1["f300"])
     eJ = abs(J - c1_window4["J4"]) / abs(c1_window4["J4"])
     eg = rel_l2(g.cpu().numpy(), c1_window4["g4"])
-    print(f"C1 {prec}: fields@300 {e300:.2e}; J4 {eJ:.2e}; dJ/dgamma {eg:.2e}")
+    print(f"cylinder channel 160x64 {prec}: fields@300 {e300:.2e}; J4 {eJ:.2e}; dJ/dgamma {eg:.2e}")
     assert e300 <= (1e-5 if prec == "f32" else 1e-2)
     assert eJ <= tol_J
     assert eg <= tol_g
